@@ -1,0 +1,187 @@
+"""Radar-scan throughput on one MI355X.
+
+One step = one full polar image of the procedural urban block (199,866
+triangles, 400 azimuths x 1024 rays per beam, 4 bounces, 3776 bins of
+0.044 m, 2 degree beam, P = 0.9): ray generation, BVH closest hits,
+Fresnel/Snell/BRDF interaction, fixed-point range binning and the float
+image, all in the HIP library.  The scene and its BVH are resident before
+the timed region.
+
+Prints one JSON line: Mray-segments/s (closest-hit queries per second) and
+scans/s, the roofline of the dominant kernel (the bounce kernel) from live
+HIP-event timings and a counting pass, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic bytes per unit of work
+NODE_BYTES = 64      # one two-child node: both child boxes + child refs
+TRI_BYTES = 48       # v0 | e1 | e2 of a leaf triangle
+HIT_BYTES = 16       # normal + material of the hit triangle
+RAY_BYTES = 52       # one queued ray (read once, written once)
+BIN_BYTES = 8        # one 64-bit fixed-point atomic
+# algorithmic float operations (fused multiply-add = 2)
+NODE_FLOPS = 42      # two slab tests: 12 FMA, 18 min/max, 2 scaled compares
+TRI_FLOPS = 46       # Moller-Trumbore (all stages)
+SHADE_FLOPS = 160    # normal orientation, mirror/refraction directions, Fresnel, lobe
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import workloads as W
+    if name == "urban":
+        return W.urban_block(), "urban_block_200k"
+    if name == "tiny":
+        return W.tiny_room(), "tiny_room_60"
+    if name == "large":
+        return W.large_scene(), "large_scene_2m"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(scene, threads: int, n_cols: int):
+    import numpy as np
+    import oracle
+    naz = scene.params["n_azimuth"]
+    cols = np.linspace(0, naz - 1, n_cols).round().astype(np.uint32)
+    t0 = time.perf_counter()
+    out = oracle.scan_scene(scene, columns=cols, threads=threads, energy=False)
+    dt = time.perf_counter() - t0
+    segs = int(out["segments"].sum())
+    return dict(value=segs / dt / 1e6, unit="Mray-segments/s", cores=threads, kind="oracle",
+                sample=f"{n_cols} of {naz} azimuth columns of the same scan ({segs} segments, "
+                       f"{dt:.1f} s wall, brute force over all triangles)",
+                scans_per_s=(segs / dt) / (segs / n_cols * naz))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-columns", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2310_03505_amd as R
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    scene, wname = workload(args.workload)
+    p = scene.params
+    log(f"bench: {wname}, {scene.n_tris} tris, {p['n_azimuth']}x{p['rays_per_beam']}, "
+        f"B={p['max_bounces']}, bins={p['n_bins']}")
+    ctx = R.Context(0)
+    sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+    info = sc.info()
+    c, s = ctx.handle, sc.handle
+    img = torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+
+    # warmup + one scan with stats (segments per scan)
+    for _ in range(max(args.warmup, 1)):
+        R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img)
+    _, st = R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img, stats=True)
+    segs = st["segments"]
+
+    # counting pass: node visits and triangle tests per scan (not timed)
+    R.rr_profile_enable(c, R.RR_PROFILE_COUNT)
+    R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img)
+    torch.cuda.synchronize()
+    cnt = R.rr_profile_read(c)
+    R.rr_profile_enable(c, 0)
+
+    # timed region: K scans; HIP events around every bounce launch on the
+    # scan's stream (torch's current stream)
+    R.rr_profile_enable(c, R.RR_PROFILE_TIME)
+    R.rr_profile_read(c)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    prof = R.rr_profile_read(c)
+    R.rr_profile_enable(c, 0)
+
+    ms_per_step = ms / args.steps
+    seg_rate = segs * args.steps / (ms / 1e3) / 1e6
+    scans_per_s = args.steps / (ms / 1e3)
+
+    # roofline of the bounce kernel: algorithmic bytes and flops per launch
+    launches_per_scan = p["max_bounces"]
+    rays = sum(st["rays_per_depth"])
+    queued = rays - st["rays_per_depth"][0]           # rays read from a queue (= children written)
+    hits = cnt["rays"]                                 # upper bound on shaded hits
+    bytes_scan = (cnt["node_visits"] * NODE_BYTES + cnt["tri_tests"] * TRI_BYTES
+                  + hits * (HIT_BYTES + BIN_BYTES) + 2 * queued * RAY_BYTES)
+    flops_scan = cnt["node_visits"] * NODE_FLOPS + cnt["tri_tests"] * TRI_FLOPS + hits * SHADE_FLOPS
+    launch_ms = prof["bounce_ms"] / max(prof["launches"], 1)
+    bytes_launch = bytes_scan / launches_per_scan
+    flops_launch = flops_scan / launches_per_scan
+    gbs = bytes_launch / (launch_ms / 1e3) / 1e9
+    tfl = flops_launch / (launch_ms / 1e3) / 1e12
+    mem_frac, alu_frac = gbs / HBM_PEAK_GBS, tfl / FP32_PEAK_TFLOPS
+    if mem_frac >= alu_frac:
+        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(mem_frac, 4), traffic=None)
+    else:
+        roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(alu_frac, 4), traffic=None)
+    roof.update(kernel="k_bounce", launch_ms=round(launch_ms, 4),
+                bytes_per_launch=int(bytes_launch), flops_per_launch=int(flops_launch),
+                other_fraction=round(alu_frac if roof["bound"] == "hbm" else mem_frac, 4),
+                node_visits_per_segment=round(cnt["node_visits"] / max(cnt["rays"], 1), 2),
+                tri_tests_per_segment=round(cnt["tri_tests"] / max(cnt["rays"], 1), 2),
+                level_ms=[round(x / args.steps, 4) for x in prof["level_ms"][:p["max_bounces"]]])
+
+    out = {
+        "metric": "Mray-segments/s", "value": round(seg_rate, 2), "unit": "Mray-segments/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wname, "n_tris": scene.n_tris, "n_azimuth": p["n_azimuth"],
+                   "rays_per_beam": p["rays_per_beam"], "max_bounces": p["max_bounces"],
+                   "n_bins": p["n_bins"], "segments_per_scan": segs,
+                   "rays_per_depth": st["rays_per_depth"][:p["max_bounces"]],
+                   "scans_per_s": round(scans_per_s, 2), "bvh_nodes": info["n_nodes"],
+                   "bvh_depth": info["max_depth"], "wall_s": round(wall, 3)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            threads = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            threads = min(16, os.cpu_count() or 1)
+        ncol = args.cpu_columns or threads
+        log(f"cpu baseline: oracle on {ncol} columns, {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(scene, threads, ncol)
+    sc.release()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

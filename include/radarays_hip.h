@@ -1,0 +1,260 @@
+/*
+ * radarays_hip.h -- C ABI of the MI355X radar-scan library.
+ *
+ * The library simulates a rotating FMCW radar the way RadaRays does (Mock,
+ * Magnusson, Hertzberg, Sec. III): for every azimuth of the spinning sensor
+ * it draws rays from a Gaussian beam cone, traces them through a triangle
+ * mesh with reflection and refraction (Snell + Fresnel), returns part of
+ * the energy of every hit to the sensor through the paper's standard BRDF,
+ * and sums the returns into an azimuth x range polar image.
+ *
+ * Conventions
+ *  - All functions return an rr_status (0 = success).  On failure nothing has
+ *    been enqueued on the stream and outputs are untouched, except where a
+ *    function says otherwise.  rr_last_error() gives a message.
+ *  - Pointers named *_dev are device pointers on the context's GPU; all
+ *    other pointers are host pointers.  The library copies every host input
+ *    before returning; the caller keeps ownership of its buffers.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Scan calls are
+ *    asynchronous on that stream unless a stats pointer is passed.
+ *  - A context is not thread-safe; use one per host thread or lock.  A
+ *    context's internal workspace is shared by its scans: scans of one
+ *    context on different streams must not overlap in time (use
+ *    rr_radar_scan_ws with separate workspaces, or separate contexts).
+ *  - Triangle ids in records and statistics are the caller's original
+ *    indices into `indices`.
+ */
+#ifndef RADARAYS_HIP_H
+#define RADARAYS_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rr_status;
+#define RR_OK 0
+#define RR_EINVAL (-1)    /* invalid argument; nothing launched */
+#define RR_ENOMEM (-2)    /* device/host allocation failed or over budget */
+#define RR_EDEVICE (-3)   /* HIP runtime error */
+#define RR_ESTATE (-4)    /* call order violated (e.g. scan before bvh_build) */
+#define RR_EOVERFLOW (-5) /* a ray-queue capacity invariant was violated */
+
+/* sensor flags */
+#define RR_BEAM_GAIN 1u      /* weight returns by the receive gain exp(-z^2/2) */
+#define RR_FIXED_PATTERN 2u  /* every azimuth uses the same cone offsets */
+#define RR_MIRROR_PAIRS 4u   /* odd rays mirror the azimuth offset of ray i-1 */
+#define RR_RETURN_ALL 8u     /* return all reflected energy (w = 1; lidar-like) */
+
+/* material kinds */
+#define RR_DIELECTRIC 0u /* Fresnel reflection + Snell refraction, lossless */
+#define RR_METAL 1u      /* reflects `reflectance`, absorbs the rest */
+#define RR_LAMBERTIAN 2u /* reflects `reflectance` (albedo), absorbs the rest */
+
+/* limits */
+#define RR_MAX_BOUNCES 8u
+#define RR_MAX_MATERIALS 255u
+#define RR_MAX_AZIMUTH 65535u
+#define RR_MAX_RAYS_PER_BEAM (1u << 20)
+#define RR_MAX_BINS 65535u
+#define RR_MAX_PRIMARIES (1u << 26) /* n_azimuth * rays_per_beam */
+
+typedef struct rr_context rr_context;
+typedef struct rr_scene rr_scene;
+
+/* Sensor pose in the world frame.  Sensor frame: +x = azimuth 0, +z = the
+ * rotation axis; azimuth k points at angle 2*pi*k/n_azimuth counter-clockwise
+ * about +z (Sec. III-B).  The quaternion (w, x, y, z) is normalised by the
+ * library and rejected if its norm is off by more than 1e-3. */
+typedef struct {
+  float position[3];
+  float quat_wxyz[4];
+} rr_pose;
+
+/* Per-scan sensor parameters (Sec. III-A, III-B, IV).
+ *  n_azimuth      columns of the polar image, 1..65535
+ *  rays_per_beam  N_s primary rays per azimuth, 1..2^20 (each carries 1/N_s
+ *                 of the azimuth's unit emitted energy, Sec. III-A)
+ *  max_bounces    B: interactions per path, 1..8; returns are computed at
+ *                 every interaction, children spawn while depth + 1 < B
+ *  n_bins         rows of the image, 1..65535
+ *  bin_size_m     range bin width; a return lands in floor(range/bin_size)
+ *                 where range is the one-way optical path length; returns
+ *                 at or beyond n_bins * bin_size are dropped
+ *  beam_width_rad b in [0, pi): beam width of Eq. 2 and the window of Eq. 4
+ *  beam_prob      P in (0, 1): probability of a ray inside b/2 (Eq. 2)
+ *  energy_cutoff  children whose energy is <= this are not traced (>= 0)
+ *  seed, scan_id  key of the counter-based generator of the ray samples
+ *  flags          RR_* sensor flags */
+typedef struct {
+  uint32_t n_azimuth, rays_per_beam, max_bounces, n_bins;
+  float bin_size_m, beam_width_rad, beam_prob, energy_cutoff;
+  uint64_t seed;
+  uint32_t scan_id, flags;
+} rr_sensor_params;
+
+/* Material (Sec. III-A; Eq. 5 parameters, S = 1 - A - B).
+ *  kind        RR_DIELECTRIC / RR_METAL / RR_LAMBERTIAN
+ *  n           refractive index of a dielectric (> 0), ignored otherwise
+ *  reflectance reflected share for metal and Lambertian, in [0, 1]
+ *  A, B, C     lobe parameters: A, B in [0, 1], A + B <= 1, C >= 0 */
+typedef struct {
+  uint32_t kind;
+  float n, reflectance, A, B, C;
+} rr_material;
+
+/* BVH build options (all zero = defaults). */
+typedef struct {
+  uint32_t max_leaf_size; /* triangles per leaf, 1..16, default 4 */
+  uint32_t sah_bins;      /* SAH bins per axis, 4..64, default 16 */
+  uint32_t n_threads;     /* host build threads, 0 = all cores */
+  uint32_t reserved;
+} rr_bvh_options;
+
+typedef struct {
+  uint32_t n_tris;        /* triangles in the scene */
+  uint32_t n_hittable;    /* non-degenerate triangles placed in the BVH */
+  uint32_t n_nodes;       /* inner nodes */
+  uint32_t n_leaves;
+  uint32_t max_depth;
+  uint32_t reserved;
+  uint64_t device_bytes;  /* nodes + triangles resident on the GPU */
+  double sah_cost;
+  double build_ms;
+} rr_bvh_info;
+
+/* Filled when a scan is given a stats pointer (the call then waits for the
+ * stream).  segments = closest-hit queries traced (misses included). */
+typedef struct {
+  uint64_t segments;
+  uint64_t rays_per_depth[RR_MAX_BOUNCES];
+  uint32_t overflow; /* nonzero: a ray queue overflowed (a library bug) */
+  uint32_t reserved;
+} rr_scan_stats;
+
+/* One scan of a batch. */
+typedef struct {
+  rr_pose pose;
+  rr_sensor_params params;
+  float* image_dev; /* n_azimuth * n_bins floats, row-major [azimuth][bin] */
+} rr_scan_desc;
+
+/* ---------------------------------------------------------------- context */
+const char* rr_status_str(rr_status s);
+
+/* Create a context on HIP device `device` (>= 0).  ENOMEM/EDEVICE on failure. */
+rr_status rr_create(int device, rr_context** out);
+/* Waits for the device, frees everything the context owns.  NULL is a no-op. */
+rr_status rr_destroy(rr_context* ctx);
+/* Message of the last failure on this context (or of the last context-less
+ * failure when ctx is NULL).  Never NULL. */
+const char* rr_last_error(const rr_context* ctx);
+
+/* ---------------------------------------------------------------- scene */
+/* Copy a triangle mesh into the library (host side).  vertices: nv x 3 float
+ * (finite, |x| <= 1e7); indices: nt x 3 (each < nv); tri_material: nt ids
+ * (checked against the material table at scan time).  nt may be 0.
+ * Zero-area triangles are kept but can never be hit (no normal).  ctx may
+ * be NULL: the scene then lives on the host only (BVH build and the host
+ * self-check work; scans need a scene created with a context). */
+rr_status rr_scene_upload(rr_context* ctx, const float* vertices, uint32_t nv,
+                          const uint32_t* indices, uint32_t nt, const uint16_t* tri_material,
+                          rr_scene** out);
+
+/* Build the bounding-volume hierarchy on the host (binned SAH, depth <= 32)
+ * and copy nodes and triangles to the context's GPU.  Synchronous.  After it
+ * the scene is immutable and may be shared by concurrent scans.  opt may be
+ * NULL.  Calling it again rebuilds. */
+rr_status rr_bvh_build(rr_context* ctx, rr_scene* scene, const rr_bvh_options* opt);
+
+rr_status rr_bvh_get_info(const rr_scene* scene, rr_bvh_info* out);
+
+/* Host check of the built hierarchy: traces n_rays random rays (origins in
+ * the scene bounds, seeded) through it on the CPU and through a brute-force
+ * loop over all triangles, and counts closest hits that differ. */
+rr_status rr_bvh_selfcheck(const rr_scene* scene, uint32_t n_rays, uint64_t seed,
+                           uint64_t* mismatches);
+
+/* Frees the scene (host and device copies).  The caller must have waited for
+ * scans that use it. */
+rr_status rr_scene_release(rr_context* ctx, rr_scene* scene);
+
+/* ---------------------------------------------------------------- scans */
+/* Exact device bytes one scan with these parameters needs as workspace:
+ * two ray queues of N_p * 2^(B-1) rays, the fixed-point accumulator and the
+ * counters.  EINVAL if the parameters are out of range. */
+rr_status rr_workspace_query(const rr_sensor_params* params, size_t* bytes);
+
+/* One polar image (Sec. III-A, III-B).  image_dev receives n_azimuth x n_bins
+ * floats, row-major [azimuth][bin]: the energy returned into each range bin
+ * as a fraction of the azimuth's unit emitted energy (linear, no dB).  The
+ * image is fully overwritten.  Accumulation uses 64-bit fixed-point integer
+ * atomics, so results are bit-identical from run to run.  The workspace is
+ * owned by the context and grown on demand. */
+rr_status rr_radar_scan(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
+                        const rr_sensor_params* params, const rr_material* materials,
+                        uint32_t n_materials, float* image_dev, rr_scan_stats* stats,
+                        void* stream);
+
+/* As rr_radar_scan with a caller-provided workspace of at least
+ * rr_workspace_query() bytes (device memory, 256-byte aligned).  Scans on
+ * different workspaces may overlap on different streams. */
+rr_status rr_radar_scan_ws(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
+                           const rr_sensor_params* params, const rr_material* materials,
+                           uint32_t n_materials, float* image_dev, void* workspace_dev,
+                           size_t workspace_bytes, rr_scan_stats* stats, void* stream);
+
+/* Debug/parity variant of rr_radar_scan.  Optional outputs (NULL = skip):
+ *  records_dev  int32 [n_azimuth * rays_per_beam][2^B - 1], heap order per
+ *               primary (slot h-1 for heap id h; 1 = primary, 2h = reflected
+ *               child, 2h+1 = refracted child): original triangle id of the
+ *               segment's hit, -1 for a miss, -2 for a segment never spawned
+ *  accum_dev    uint64 [n_azimuth * n_bins]: the fixed-point accumulator
+ *               (energy * 2^56) the image is converted from
+ * primary_mask_dev (optional) uint8 [n_azimuth * rays_per_beam]: primaries
+ * with a zero byte are not traced at all. */
+rr_status rr_radar_scan_records(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
+                                const rr_sensor_params* params, const rr_material* materials,
+                                uint32_t n_materials, const uint8_t* primary_mask_dev,
+                                float* image_dev, int32_t* records_dev, uint64_t* accum_dev,
+                                rr_scan_stats* stats, void* stream);
+
+/* Many scans (poses, azimuth counts, rays per beam and bounce limits may all
+ * differ; the beam width must be shared) traced together: one ray-generation launch, one persistent
+ * bounce launch per depth over the rays of every scan, one finalize.  Each
+ * image equals what rr_radar_scan gives for that scan, bit for bit.
+ * stats (optional) sums over the batch. */
+rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* scene, const rr_scan_desc* scans,
+                              uint32_t n_scans, const rr_material* materials,
+                              uint32_t n_materials, rr_scan_stats* stats, void* stream);
+
+/* Workspace bytes rr_radar_scan_batch needs for these scans. */
+rr_status rr_batch_workspace_query(const rr_scan_desc* scans, uint32_t n_scans, size_t* bytes);
+
+/* ---------------------------------------------------------------- profiling */
+#define RR_PROFILE_TIME 1u  /* bracket every bounce launch with HIP events */
+#define RR_PROFILE_COUNT 2u /* use the counting kernel: node visits, triangle tests */
+
+typedef struct {
+  uint64_t launches;           /* bounce launches recorded */
+  double bounce_ms;            /* summed event time of those launches */
+  double level_ms[RR_MAX_BOUNCES];
+  uint64_t node_visits;        /* inner nodes fetched (RR_PROFILE_COUNT) */
+  uint64_t tri_tests;          /* ray-triangle tests (RR_PROFILE_COUNT) */
+  uint64_t rays;               /* rays traced by the counted launches */
+} rr_profile;
+
+/* Measurement hooks for benchmarks (not needed for scans).  Enabling with
+ * flags = 0 disables.  The counting kernel is slower; its results are the
+ * same images. */
+rr_status rr_profile_enable(rr_context* ctx, uint32_t flags);
+/* Waits for the recorded events, returns the totals since the last read and
+ * resets them. */
+rr_status rr_profile_read(rr_context* ctx, rr_profile* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RADARAYS_HIP_H */

@@ -1,0 +1,355 @@
+"""Python binding of libradarays_hip.so, the MI355X radar-scan library.
+
+Argument marshalling only: every step of a scan runs in the HIP library.
+The functions keep the names of the C ABI (``include/radarays_hip.h``);
+PyTorch provides device memory and the current stream.  The library must
+have been built (``python -m paper_2310_03505_amd.build``); importing the
+binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libradarays_hip.so")
+
+RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ESTATE, RR_EOVERFLOW = 0, -1, -2, -3, -4, -5
+RR_BEAM_GAIN, RR_FIXED_PATTERN, RR_MIRROR_PAIRS, RR_RETURN_ALL = 1, 2, 4, 8
+RR_DIELECTRIC, RR_METAL, RR_LAMBERTIAN = 0, 1, 2
+RR_MAX_BOUNCES = 8
+
+
+class RadarError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class rr_pose(C.Structure):
+    _fields_ = [("position", C.c_float * 3), ("quat_wxyz", C.c_float * 4)]
+
+
+class rr_sensor_params(C.Structure):
+    _fields_ = [("n_azimuth", C.c_uint32), ("rays_per_beam", C.c_uint32),
+                ("max_bounces", C.c_uint32), ("n_bins", C.c_uint32),
+                ("bin_size_m", C.c_float), ("beam_width_rad", C.c_float),
+                ("beam_prob", C.c_float), ("energy_cutoff", C.c_float),
+                ("seed", C.c_uint64), ("scan_id", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class rr_material(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("n", C.c_float), ("reflectance", C.c_float),
+                ("A", C.c_float), ("B", C.c_float), ("C", C.c_float)]
+
+
+class rr_bvh_options(C.Structure):
+    _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32),
+                ("n_threads", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class rr_bvh_info(C.Structure):
+    _fields_ = [("n_tris", C.c_uint32), ("n_hittable", C.c_uint32), ("n_nodes", C.c_uint32),
+                ("n_leaves", C.c_uint32), ("max_depth", C.c_uint32), ("reserved", C.c_uint32),
+                ("device_bytes", C.c_uint64), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
+
+
+class rr_scan_stats(C.Structure):
+    _fields_ = [("segments", C.c_uint64), ("rays_per_depth", C.c_uint64 * RR_MAX_BOUNCES),
+                ("overflow", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class rr_profile(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("bounce_ms", C.c_double),
+                ("level_ms", C.c_double * RR_MAX_BOUNCES), ("node_visits", C.c_uint64),
+                ("tri_tests", C.c_uint64), ("rays", C.c_uint64)]
+
+
+RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
+
+
+class rr_scan_desc(C.Structure):
+    _fields_ = [("pose", rr_pose), ("params", rr_sensor_params), ("image_dev", C.c_void_p)]
+
+
+EXPORTS = (
+    "rr_status_str", "rr_create", "rr_destroy", "rr_last_error", "rr_scene_upload",
+    "rr_bvh_build", "rr_bvh_get_info", "rr_bvh_selfcheck", "rr_scene_release",
+    "rr_workspace_query", "rr_radar_scan", "rr_radar_scan_ws", "rr_radar_scan_records",
+    "rr_radar_scan_batch", "rr_batch_workspace_query", "rr_profile_enable", "rr_profile_read",
+)
+
+_lib = None
+
+
+def load_library():
+    """Load libradarays_hip.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2310_03505_amd.build` (there is no fallback)")
+    lib = C.CDLL(LIB_PATH)
+    P, vp = C.POINTER, C.c_void_p
+    st = C.c_int32
+    sig = {
+        "rr_status_str": (C.c_char_p, [st]),
+        "rr_create": (st, [C.c_int, P(vp)]),
+        "rr_destroy": (st, [vp]),
+        "rr_last_error": (C.c_char_p, [vp]),
+        "rr_scene_upload": (st, [vp, P(C.c_float), C.c_uint32, P(C.c_uint32), C.c_uint32,
+                                 P(C.c_uint16), P(vp)]),
+        "rr_bvh_build": (st, [vp, vp, P(rr_bvh_options)]),
+        "rr_bvh_get_info": (st, [vp, P(rr_bvh_info)]),
+        "rr_bvh_selfcheck": (st, [vp, C.c_uint32, C.c_uint64, P(C.c_uint64)]),
+        "rr_scene_release": (st, [vp, vp]),
+        "rr_workspace_query": (st, [P(rr_sensor_params), P(C.c_size_t)]),
+        "rr_radar_scan": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material), C.c_uint32,
+                               vp, P(rr_scan_stats), vp]),
+        "rr_radar_scan_ws": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material),
+                                  C.c_uint32, vp, vp, C.c_size_t, P(rr_scan_stats), vp]),
+        "rr_radar_scan_records": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material),
+                                       C.c_uint32, vp, vp, vp, vp, P(rr_scan_stats), vp]),
+        "rr_radar_scan_batch": (st, [vp, vp, P(rr_scan_desc), C.c_uint32, P(rr_material),
+                                     C.c_uint32, P(rr_scan_stats), vp]),
+        "rr_batch_workspace_query": (st, [P(rr_scan_desc), C.c_uint32, P(C.c_size_t)]),
+        "rr_profile_enable": (st, [vp, C.c_uint32]),
+        "rr_profile_read": (st, [vp, P(rr_profile)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, ctx=None):
+    if status != RR_OK:
+        lib = load_library()
+        msg = lib.rr_last_error(ctx).decode(errors="replace")
+        raise RadarError(status, msg or lib.rr_status_str(status).decode())
+
+
+# ------------------------------------------------------------------ marshalling
+def make_pose(pose: dict) -> rr_pose:
+    return rr_pose((C.c_float * 3)(*pose["position"]), (C.c_float * 4)(*pose["quat_wxyz"]))
+
+
+def make_params(p: dict) -> rr_sensor_params:
+    return rr_sensor_params(p["n_azimuth"], p["rays_per_beam"], p["max_bounces"], p["n_bins"],
+                            p["bin_size_m"], p["beam_width_rad"], p["beam_prob"],
+                            p["energy_cutoff"], p["seed"], p["scan_id"], p["flags"])
+
+
+def make_materials(mats):
+    arr = (rr_material * max(1, len(mats)))()
+    for i, m in enumerate(mats):
+        arr[i] = rr_material(m["kind"], m["n"], m["reflectance"], m["A"], m["B"], m["C"])
+    return arr
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ the C ABI, by name
+def rr_create(device: int = 0):
+    lib = load_library()
+    h = C.c_void_p()
+    _check(lib.rr_create(device, C.byref(h)))
+    return h
+
+
+def rr_destroy(ctx):
+    _check(load_library().rr_destroy(ctx))
+
+
+def rr_scene_upload(ctx, vertices, indices, tri_material):
+    import numpy as np
+    lib = load_library()
+    V = np.ascontiguousarray(vertices, dtype=np.float32)
+    F = np.ascontiguousarray(indices, dtype=np.uint32)
+    M = np.ascontiguousarray(tri_material, dtype=np.uint16)
+    h = C.c_void_p()
+    _check(lib.rr_scene_upload(ctx, V.ctypes.data_as(C.POINTER(C.c_float)), V.shape[0],
+                               F.ctypes.data_as(C.POINTER(C.c_uint32)), F.shape[0],
+                               M.ctypes.data_as(C.POINTER(C.c_uint16)), C.byref(h)), ctx)
+    return h
+
+
+def rr_bvh_build(ctx, scene, max_leaf_size: int = 0, sah_bins: int = 0, n_threads: int = 0):
+    opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, 0)
+    _check(load_library().rr_bvh_build(ctx, scene, C.byref(opt)), ctx)
+
+
+def rr_bvh_get_info(scene) -> dict:
+    info = rr_bvh_info()
+    _check(load_library().rr_bvh_get_info(scene, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in rr_bvh_info._fields_ if k != "reserved"}
+
+
+def rr_bvh_selfcheck(scene, n_rays: int = 10000, seed: int = 1) -> int:
+    out = C.c_uint64()
+    _check(load_library().rr_bvh_selfcheck(scene, n_rays, seed, C.byref(out)))
+    return int(out.value)
+
+
+def rr_scene_release(ctx, scene):
+    _check(load_library().rr_scene_release(ctx, scene), ctx)
+
+
+def rr_workspace_query(params: dict) -> int:
+    out = C.c_size_t()
+    prm = make_params(params)
+    _check(load_library().rr_workspace_query(C.byref(prm), C.byref(out)))
+    return int(out.value)
+
+
+def _stats_dict(st: rr_scan_stats) -> dict:
+    return dict(segments=int(st.segments), rays_per_depth=[int(x) for x in st.rays_per_depth],
+                overflow=int(st.overflow))
+
+
+def rr_radar_scan(ctx, scene, pose: dict, params: dict, materials, image=None, stats=False,
+                  stream=None):
+    """One polar image into ``image`` (a float32 CUDA tensor [n_az, n_bins],
+    allocated if None).  Returns (image, stats-or-None)."""
+    import torch
+    if image is None:
+        image = torch.empty((params["n_azimuth"], params["n_bins"]), dtype=torch.float32,
+                            device="cuda")
+    st = rr_scan_stats() if stats else None
+    mats = make_materials(materials)
+    pr, ps = make_pose(pose), make_params(params)
+    _check(load_library().rr_radar_scan(ctx, scene, C.byref(pr), C.byref(ps), mats, len(materials),
+                                        _ptr(image), C.byref(st) if st is not None else None,
+                                        _stream_handle(stream)), ctx)
+    return image, (_stats_dict(st) if st is not None else None)
+
+
+def rr_radar_scan_ws(ctx, scene, pose: dict, params: dict, materials, image, workspace,
+                     stats=False, stream=None):
+    st = rr_scan_stats() if stats else None
+    mats = make_materials(materials)
+    pr, ps = make_pose(pose), make_params(params)
+    _check(load_library().rr_radar_scan_ws(ctx, scene, C.byref(pr), C.byref(ps), mats,
+                                           len(materials), _ptr(image), _ptr(workspace),
+                                           workspace.numel() * workspace.element_size(),
+                                           C.byref(st) if st is not None else None,
+                                           _stream_handle(stream)), ctx)
+    return image, (_stats_dict(st) if st is not None else None)
+
+
+def rr_radar_scan_records(ctx, scene, pose: dict, params: dict, materials, primary_mask=None,
+                          records=True, accum=True, stats=True, stream=None):
+    """Debug/parity scan.  Returns dict(image, records, accum, stats) with
+    CUDA tensors (records int32 [N_p, 2^B-1], accum int64 view of the uint64
+    fixed-point accumulator)."""
+    import torch
+    n_az, n_s, nb, B = (params["n_azimuth"], params["rays_per_beam"], params["n_bins"],
+                        params["max_bounces"])
+    image = torch.empty((n_az, nb), dtype=torch.float32, device="cuda")
+    rec = torch.empty((n_az * n_s, (1 << B) - 1), dtype=torch.int32, device="cuda") if records else None
+    acc = torch.empty((n_az, nb), dtype=torch.int64, device="cuda") if accum else None
+    st = rr_scan_stats() if stats else None
+    mats = make_materials(materials)
+    pr, ps = make_pose(pose), make_params(params)
+    _check(load_library().rr_radar_scan_records(
+        ctx, scene, C.byref(pr), C.byref(ps), mats, len(materials), _ptr(primary_mask),
+        _ptr(image), _ptr(rec), _ptr(acc), C.byref(st) if st is not None else None,
+        _stream_handle(stream)), ctx)
+    return dict(image=image, records=rec, accum=acc,
+                stats=_stats_dict(st) if st is not None else None)
+
+
+def make_scan_descs(scans, images):
+    arr = (rr_scan_desc * len(scans))()
+    for i, ((pose, params), img) in enumerate(zip(scans, images)):
+        arr[i] = rr_scan_desc(make_pose(pose), make_params(params), C.c_void_p(img.data_ptr()))
+    return arr
+
+
+def rr_batch_workspace_query(scans) -> int:
+    arr = (rr_scan_desc * len(scans))()
+    for i, (pose, params) in enumerate(scans):
+        arr[i] = rr_scan_desc(make_pose(pose), make_params(params), None)
+    out = C.c_size_t()
+    _check(load_library().rr_batch_workspace_query(arr, len(scans), C.byref(out)))
+    return int(out.value)
+
+
+def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, stream=None):
+    """Many (pose, params) scans in one pass.  Returns (images, stats)."""
+    import torch
+    if images is None:
+        images = [torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+                  for _, p in scans]
+    descs = make_scan_descs(scans, images)
+    st = rr_scan_stats() if stats else None
+    mats = make_materials(materials)
+    _check(load_library().rr_radar_scan_batch(ctx, scene, descs, len(scans), mats, len(materials),
+                                              C.byref(st) if st is not None else None,
+                                              _stream_handle(stream)), ctx)
+    return images, (_stats_dict(st) if st is not None else None)
+
+
+def rr_profile_enable(ctx, flags: int):
+    _check(load_library().rr_profile_enable(ctx, flags), ctx)
+
+
+def rr_profile_read(ctx) -> dict:
+    p = rr_profile()
+    _check(load_library().rr_profile_read(ctx, C.byref(p)), ctx)
+    return dict(launches=int(p.launches), bounce_ms=float(p.bounce_ms),
+                level_ms=[float(x) for x in p.level_ms], node_visits=int(p.node_visits),
+                tri_tests=int(p.tri_tests), rays=int(p.rays))
+
+
+# ------------------------------------------------------------------ convenience
+class Context:
+    def __init__(self, device: int = 0):
+        self.handle = rr_create(device)
+
+    def close(self):
+        if self.handle:
+            rr_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Scene:
+    """A mesh resident on the GPU with its BVH built."""
+
+    def __init__(self, ctx: Context | None, vertices, indices, tri_material, build=True, **bvh_opts):
+        self.ctx = ctx
+        self._c = ctx.handle if ctx is not None else None
+        self.handle = rr_scene_upload(self._c, vertices, indices, tri_material)
+        if build:
+            rr_bvh_build(self._c, self.handle, **bvh_opts)
+
+    def info(self) -> dict:
+        return rr_bvh_get_info(self.handle)
+
+    def selfcheck(self, n_rays=10000, seed=1) -> int:
+        return rr_bvh_selfcheck(self.handle, n_rays, seed)
+
+    def release(self):
+        if self.handle:
+            rr_scene_release(self._c, self.handle)
+            self.handle = None

@@ -1,0 +1,708 @@
+// api.cpp -- the C ABI declared in include/radarays_hip.h.
+//
+// Host work per scan: validate, derive the per-scan constants (rotation,
+// Eq. 2 radius scale, beam-window coefficients of the standard BRDF), lay
+// out the workspace, and enqueue: clear -> bounce level 0..B-1 -> finalize,
+// all on the caller's stream with no host synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/radarays_hip.h"
+#include "bvh.h"
+#include "kernels.h"
+#include "rr_internal.h"
+
+using namespace rr;
+
+struct rr_context {
+  int device = 0;
+  int n_cu = 256;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t* h_ctr = nullptr;  // pinned, for stats
+  std::string err;
+  // profiling
+  uint32_t prof_flags = 0;
+  struct EvPair {
+    hipEvent_t a, b;
+    uint32_t depth;
+  };
+  std::vector<hipEvent_t> ev_free;
+  std::vector<EvPair> ev_used;
+  unsigned long long* d_prof = nullptr;
+};
+
+struct rr_scene {
+  rr_context* ctx = nullptr;
+  std::vector<float> V;
+  std::vector<uint32_t> F;
+  std::vector<uint16_t> M;
+  uint32_t nv = 0, nt = 0;
+  uint32_t max_mat = 0;
+  bool built = false;
+  BuiltBvh bvh;
+  Node* d_nodes = nullptr;
+  float4* d_tris = nullptr;
+  float4* d_aux = nullptr;
+  uint64_t dev_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+rr_status fail(rr_context* ctx, rr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                    \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? RR_ENOMEM : RR_EDEVICE, "%s: %s", #expr,   \
+                  hipGetErrorString(e_));                                                     \
+  } while (0)
+
+bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+rr_status check_params(rr_context* ctx, const rr_sensor_params* p) {
+  if (!p) return fail(ctx, RR_EINVAL, "params is NULL");
+  if (p->n_azimuth < 1 || p->n_azimuth > RR_MAX_AZIMUTH)
+    return fail(ctx, RR_EINVAL, "n_azimuth %u out of [1, %u]", p->n_azimuth, RR_MAX_AZIMUTH);
+  if (p->rays_per_beam < 1 || p->rays_per_beam > RR_MAX_RAYS_PER_BEAM)
+    return fail(ctx, RR_EINVAL, "rays_per_beam %u out of range", p->rays_per_beam);
+  if (p->max_bounces < 1 || p->max_bounces > RR_MAX_BOUNCES)
+    return fail(ctx, RR_EINVAL, "max_bounces %u out of [1, 8]", p->max_bounces);
+  if (p->n_bins < 1 || p->n_bins > RR_MAX_BINS)
+    return fail(ctx, RR_EINVAL, "n_bins %u out of [1, %u]", p->n_bins, RR_MAX_BINS);
+  if ((uint64_t)p->n_azimuth * p->rays_per_beam > RR_MAX_PRIMARIES)
+    return fail(ctx, RR_EINVAL, "n_azimuth * rays_per_beam exceeds %u", RR_MAX_PRIMARIES);
+  if (!(std::isfinite(p->bin_size_m) && p->bin_size_m > 0.0f))
+    return fail(ctx, RR_EINVAL, "bin_size_m must be finite and > 0");
+  if (!(p->beam_width_rad >= 0.0f && p->beam_width_rad < (float)M_PI))
+    return fail(ctx, RR_EINVAL, "beam_width_rad must be in [0, pi)");
+  if (!(p->beam_prob > 0.0f && p->beam_prob < 1.0f))
+    return fail(ctx, RR_EINVAL, "beam_prob must be in (0, 1)");
+  if (!(std::isfinite(p->energy_cutoff) && p->energy_cutoff >= 0.0f))
+    return fail(ctx, RR_EINVAL, "energy_cutoff must be finite and >= 0");
+  if (!std::isfinite((float)p->n_bins * p->bin_size_m))
+    return fail(ctx, RR_EINVAL, "n_bins * bin_size_m overflows");
+  if (p->flags & ~15u) return fail(ctx, RR_EINVAL, "unknown flag bits 0x%x", p->flags);
+  return RR_OK;
+}
+
+rr_status check_pose(rr_context* ctx, const rr_pose* q) {
+  if (!q) return fail(ctx, RR_EINVAL, "pose is NULL");
+  if (!finite3(q->position)) return fail(ctx, RR_EINVAL, "pose position not finite");
+  double n = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (!std::isfinite(q->quat_wxyz[i])) return fail(ctx, RR_EINVAL, "pose quaternion not finite");
+    n += (double)q->quat_wxyz[i] * q->quat_wxyz[i];
+  }
+  if (std::fabs(std::sqrt(n) - 1.0) > 1e-3) return fail(ctx, RR_EINVAL, "pose quaternion not unit");
+  return RR_OK;
+}
+
+rr_status check_materials(rr_context* ctx, const rr_material* m, uint32_t n, const rr_scene* sc) {
+  if (n < 1 || n > RR_MAX_MATERIALS || !m) return fail(ctx, RR_EINVAL, "need 1..255 materials");
+  for (uint32_t i = 0; i < n; ++i) {
+    const rr_material& q = m[i];
+    if (q.kind > RR_LAMBERTIAN) return fail(ctx, RR_EINVAL, "material %u: unknown kind", i);
+    if (q.kind == RR_DIELECTRIC && !(std::isfinite(q.n) && q.n > 0.0f))
+      return fail(ctx, RR_EINVAL, "material %u: n must be > 0", i);
+    if (!(q.reflectance >= 0.0f && q.reflectance <= 1.0f))
+      return fail(ctx, RR_EINVAL, "material %u: reflectance out of [0,1]", i);
+    if (!(q.A >= 0.0f && q.A <= 1.0f && q.B >= 0.0f && q.B <= 1.0f && q.A + q.B <= 1.0f + 1e-6f))
+      return fail(ctx, RR_EINVAL, "material %u: need A, B in [0,1], A + B <= 1", i);
+    if (!(std::isfinite(q.C) && q.C >= 0.0f)) return fail(ctx, RR_EINVAL, "material %u: C must be >= 0", i);
+  }
+  if (sc && sc->nt && sc->max_mat >= n)
+    return fail(ctx, RR_EINVAL, "scene uses material %u but only %u given", sc->max_mat, n);
+  return RR_OK;
+}
+
+// erfinv by Newton's method on erf (erfc near 1), started from Winitzki's
+// closed-form approximation (a = 0.147).
+double erfinv_newton(double p) {
+  const double a = 0.147;
+  double ap = std::fabs(p);
+  double w = -std::log((1.0 - ap) * (1.0 + ap));  // -ln(1 - p^2)
+  double t = 2.0 / (M_PI * a) - w / 2.0;
+  double x = std::sqrt(std::max(0.0, std::sqrt(t * t + w / a) - t));
+  for (int it = 0; it < 60; ++it) {
+    double f = ap < 0.5 ? std::erf(x) - ap : (1.0 - ap) - std::erfc(x);
+    double dfdx = 2.0 / std::sqrt(M_PI) * std::exp(-x * x);
+    double step = f / dfdx;
+    x -= step;
+    if (std::fabs(step) <= 2e-16 * std::fabs(x)) break;
+  }
+  return p < 0 ? -x : x;
+}
+
+// Integral of cos^C over [-pi/2, pi/2] via the Beta function.
+double lobe_integral(double C) {
+  return std::sqrt(M_PI) * std::exp(std::lgamma((C + 1.0) / 2.0) - std::lgamma(C / 2.0 + 1.0));
+}
+
+void make_scan(const rr_pose& pose, const rr_sensor_params& p, DevScan& s) {
+  std::memset(&s, 0, sizeof s);
+  double w = pose.quat_wxyz[0], x = pose.quat_wxyz[1], y = pose.quat_wxyz[2], z = pose.quat_wxyz[3];
+  double qn = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= qn;
+  x /= qn;
+  y /= qn;
+  z /= qn;
+  s.R[0] = 1.0 - 2.0 * (y * y + z * z);
+  s.R[1] = 2.0 * (x * y - w * z);
+  s.R[2] = 2.0 * (x * z + w * y);
+  s.R[3] = 2.0 * (x * y + w * z);
+  s.R[4] = 1.0 - 2.0 * (x * x + z * z);
+  s.R[5] = 2.0 * (y * z - w * x);
+  s.R[6] = 2.0 * (x * z - w * y);
+  s.R[7] = 2.0 * (y * z + w * x);
+  s.R[8] = 1.0 - 2.0 * (x * x + y * y);
+  double b = p.beam_width_rad, P = p.beam_prob;
+  s.sigma_r = (b / 2.0) / (std::sqrt(2.0) * erfinv_newton(P));
+  for (int a = 0; a < 3; ++a) s.pos[a] = pose.position[a];
+  s.e0 = 1.0f / (float)p.rays_per_beam;
+  s.bin_size = p.bin_size_m;
+  s.r_max = (float)p.n_bins * p.bin_size_m;
+  s.e_cut = p.energy_cutoff;
+  s.n_az = p.n_azimuth;
+  s.n_s = p.rays_per_beam;
+  s.max_b = p.max_bounces;
+  s.n_bins = p.n_bins;
+  s.flags = p.flags;
+  s.scan_id = p.scan_id;
+  s.seed = p.seed;
+  s.n_prim = p.n_azimuth * p.rays_per_beam;
+}
+
+// Beam-window coefficients of the standard BRDF (Eq. 5) normalised to unit
+// integral over [-pi/2, pi/2] (Eq. 3) and integrated over a window of width
+// b around the return angle (Eq. 4); the S lobe uses the midpoint rule.
+void make_materials(const rr_material* m, uint32_t n, float beam_width, std::vector<DevMaterial>& out) {
+  out.resize(n);
+  double b = beam_width;
+  for (uint32_t i = 0; i < n; ++i) {
+    double A = m[i].A, B = m[i].B, S = 1.0 - A - B;
+    double Z = A * M_PI + 2.0 * B + S * lobe_integral(m[i].C);
+    DevMaterial& d = out[i];
+    std::memset(&d, 0, sizeof d);
+    d.kind = m[i].kind;
+    d.n = m[i].n;
+    d.refl = m[i].reflectance;
+    d.C = m[i].C;
+    d.a = A * b / Z;
+    d.beta = 2.0 * B * std::sin(b / 2.0) / Z;
+    d.s = S * b / Z;
+  }
+}
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0;
+  size_t off_q[2][4] = {};
+  size_t total = 0;
+  uint64_t cap = 0;       // rays per queue
+  uint64_t acc_cells = 0;
+  uint64_t n_first = 0;
+  uint32_t max_b = 0;
+};
+
+// Queue d holds level d; level d of a scan has at most N_p * 2^d rays, and
+// only scans with B > d have a level d.
+void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L) {
+  uint64_t level[RR_MAX_BOUNCES] = {};
+  L = Layout();
+  for (uint32_t i = 0; i < n; ++i) {
+    const rr_sensor_params& p = *ps[i];
+    uint64_t np = (uint64_t)p.n_azimuth * p.rays_per_beam;
+    L.n_first += np;
+    L.acc_cells += (uint64_t)p.n_azimuth * p.n_bins;
+    L.max_b = std::max(L.max_b, p.max_bounces);
+    for (uint32_t d = 1; d < p.max_bounces; ++d) level[d] += np << d;
+  }
+  for (uint32_t d = 1; d < RR_MAX_BOUNCES; ++d) L.cap = std::max(L.cap, level[d]);
+  size_t o = 0;
+  L.off_scans = o;
+  o += align256(sizeof(DevScan) * n);
+  L.off_mats = o;
+  o += align256(sizeof(DevMaterial) * RR_MAX_MATERIALS);
+  L.off_ctr = o;
+  o += align256(sizeof(uint32_t) * kCtrWords);
+  L.off_acc = o;
+  o += align256(8 * L.acc_cells);
+  size_t cap = (size_t)std::max<uint64_t>(L.cap, 1);
+  for (int q = 0; q < 2; ++q) {
+    L.off_q[q][0] = o;
+    o += align256(16 * cap);
+    L.off_q[q][1] = o;
+    o += align256(16 * cap);
+    L.off_q[q][2] = o;
+    o += align256(16 * cap);
+    L.off_q[q][3] = o;
+    o += align256(4 * cap);
+  }
+  L.total = o;
+}
+
+QueueView queue_at(char* ws, const Layout& L, int q) {
+  return QueueView{reinterpret_cast<float4*>(ws + L.off_q[q][0]), reinterpret_cast<float4*>(ws + L.off_q[q][1]),
+                   reinterpret_cast<uint4*>(ws + L.off_q[q][2]), reinterpret_cast<uint32_t*>(ws + L.off_q[q][3])};
+}
+
+rr_status check_scene(rr_context* ctx, const rr_scene* sc) {
+  if (!sc) return fail(ctx, RR_EINVAL, "scene is NULL");
+  if (!sc->built) return fail(ctx, RR_ESTATE, "scene has no BVH (call rr_bvh_build)");
+  if (!sc->d_nodes) return fail(ctx, RR_ESTATE, "scene has no device copy (created without a context)");
+  if (sc->ctx != ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
+  return RR_OK;
+}
+
+// Enqueue the scans described by `scans` (prim_base, acc_base filled here).
+rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
+              const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
+              size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
+              float beam_width_for_mats) {
+  Layout L;
+  make_layout(ps, (uint32_t)scans.size(), L);
+  if (ws_bytes < L.total)
+    return fail(ctx, RR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  if (L.cap >= (1ull << 31) || L.n_first >= (1ull << 31))
+    return fail(ctx, RR_ENOMEM, "ray queues exceed 2^31 entries");
+  uint64_t pb = 0, ab = 0;
+  uint32_t max_cells = 0;
+  for (size_t i = 0; i < scans.size(); ++i) {
+    scans[i].prim_base = (uint32_t)pb;
+    scans[i].acc_base = ab;
+    pb += scans[i].n_prim;
+    ab += (uint64_t)scans[i].n_az * scans[i].n_bins;
+    max_cells = std::max<uint32_t>(max_cells, scans[i].n_az * scans[i].n_bins);
+  }
+  std::vector<DevMaterial> dm;
+  make_materials(mats, n_mats, beam_width_for_mats, dm);
+  DevScan* d_scans = reinterpret_cast<DevScan*>(ws + L.off_scans);
+  DevMaterial* d_mats = reinterpret_cast<DevMaterial*>(ws + L.off_mats);
+  uint32_t* d_ctr = reinterpret_cast<uint32_t*>(ws + L.off_ctr);
+  auto* d_acc = reinterpret_cast<unsigned long long*>(ws + L.off_acc);
+  HIP_TRY(ctx, put_blob(d_scans, scans.data(), sizeof(DevScan) * scans.size(), st));
+  HIP_TRY(ctx, put_blob(d_mats, dm.data(), sizeof(DevMaterial) * dm.size(), st));
+  HIP_TRY(ctx, launch_clear(d_acc, (size_t)L.acc_cells, d_ctr, (uint32_t)L.n_first, st));
+  for (size_t i = 0; i < scans.size(); ++i)
+    if (scans[i].records)
+      HIP_TRY(ctx, launch_fill_i32(scans[i].records,
+                                   (size_t)scans[i].n_prim * ((1u << scans[i].max_b) - 1u), -2, st));
+  BounceArgs a{};
+  a.nodes = sc->d_nodes;
+  a.n_nodes = (uint32_t)sc->bvh.nodes.size();
+  a.tris = sc->d_tris;
+  a.aux = sc->d_aux;
+  a.scans = d_scans;
+  a.n_scans = (uint32_t)scans.size();
+  a.mats = d_mats;
+  a.acc = d_acc;
+  a.out_cap = (uint32_t)L.cap;
+  a.n_first = (uint32_t)L.n_first;
+  a.counters = d_ctr;
+  a.prof = (ctx->prof_flags & RR_PROFILE_COUNT) ? ctx->d_prof : nullptr;
+  const bool timed = (ctx->prof_flags & RR_PROFILE_TIME) != 0;
+  uint32_t persistent = (uint32_t)ctx->n_cu * 8u;
+  uint64_t level_bound = L.n_first;
+  for (uint32_t d = 0; d < L.max_b; ++d) {
+    a.depth = d;
+    a.in = queue_at(ws, L, d & 1);
+    a.out = queue_at(ws, L, (d + 1) & 1);
+    uint64_t blocks = (level_bound + kBlock - 1) / kBlock;
+    uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(blocks, 1), persistent);
+    rr_context::EvPair ev{};
+    if (timed) {
+      for (hipEvent_t* e : {&ev.a, &ev.b}) {
+        if (ctx->ev_free.empty()) {
+          hipEvent_t ne;
+          HIP_TRY(ctx, hipEventCreate(&ne));
+          ctx->ev_free.push_back(ne);
+        }
+        *e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+      }
+      ev.depth = d;
+      HIP_TRY(ctx, hipEventRecord(ev.a, st));
+    }
+    HIP_TRY(ctx, launch_bounce(a, grid, st));
+    if (timed) {
+      HIP_TRY(ctx, hipEventRecord(ev.b, st));
+      ctx->ev_used.push_back(ev);
+    }
+    level_bound = std::min<uint64_t>(level_bound * 2, L.cap);
+  }
+  HIP_TRY(ctx, launch_finalize(d_scans, (uint32_t)scans.size(), d_acc, max_cells, st));
+  if (accum_out)
+    HIP_TRY(ctx, hipMemcpyAsync(accum_out, d_acc, 8 * L.acc_cells, hipMemcpyDeviceToDevice, st));
+  if (stats) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctr, d_ctr, 4 * kCtrWords, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    std::memset(stats, 0, sizeof *stats);
+    for (uint32_t d = 0; d < RR_MAX_BOUNCES; ++d) {
+      uint64_t c = d < L.max_b ? ctx->h_ctr[kCtrCount + d] : 0;
+      stats->rays_per_depth[d] = c;
+      stats->segments += c;
+    }
+    stats->overflow = ctx->h_ctr[kCtrOverflow];
+    if (stats->overflow) return fail(ctx, RR_EOVERFLOW, "ray queue overflow");
+  }
+  return RR_OK;
+}
+
+rr_status ensure_ws(rr_context* ctx, size_t bytes) {
+  if (ctx->ws_bytes >= bytes) return RR_OK;
+  if (ctx->ws) {
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(ctx, RR_ENOMEM, "workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+  ctx->ws = p;
+  ctx->ws_bytes = bytes;
+  return RR_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* rr_status_str(rr_status s) {
+  switch (s) {
+    case RR_OK: return "ok";
+    case RR_EINVAL: return "invalid argument";
+    case RR_ENOMEM: return "out of memory";
+    case RR_EDEVICE: return "device error";
+    case RR_ESTATE: return "invalid state";
+    case RR_EOVERFLOW: return "queue overflow";
+    default: return "unknown status";
+  }
+}
+
+const char* rr_last_error(const rr_context* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+rr_status rr_create(int device, rr_context** out) {
+  if (!out) return fail(nullptr, RR_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) return fail(nullptr, RR_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= n) return fail(nullptr, RR_EINVAL, "device %d out of [0, %d)", device, n);
+  auto* c = new rr_context();
+  c->device = device;
+  DeviceGuard g(device);
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+    c->n_cu = cu;
+  void* p = nullptr;
+  e = hipHostMalloc(&p, 4 * kCtrWords, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, RR_ENOMEM, "pinned host buffer: %s", hipGetErrorString(e));
+  }
+  c->h_ctr = static_cast<uint32_t*>(p);
+  *out = c;
+  return RR_OK;
+}
+
+rr_status rr_destroy(rr_context* ctx) {
+  if (!ctx) return RR_OK;
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->h_ctr) (void)hipHostFree(ctx->h_ctr);
+    if (ctx->d_prof) (void)hipFree(ctx->d_prof);
+    for (auto& p : ctx->ev_used) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+  return RR_OK;
+}
+
+rr_status rr_scene_upload(rr_context* ctx, const float* V, uint32_t nv, const uint32_t* F, uint32_t nt,
+                          const uint16_t* M, rr_scene** out) {
+  if (!out) return fail(ctx, RR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nt && (!V || !F || !M)) return fail(ctx, RR_EINVAL, "NULL mesh array");
+  for (uint32_t i = 0; i < nv; ++i) {
+    const float* p = V + 3 * (size_t)i;
+    if (!finite3(p)) return fail(ctx, RR_EINVAL, "vertex %u not finite", i);
+    for (int a = 0; a < 3; ++a)
+      if (std::fabs(p[a]) > 1e7f) return fail(ctx, RR_EINVAL, "vertex %u beyond 1e7", i);
+  }
+  uint32_t mm = 0;
+  for (uint32_t j = 0; j < nt; ++j) {
+    for (int a = 0; a < 3; ++a)
+      if (F[3 * (size_t)j + a] >= nv) return fail(ctx, RR_EINVAL, "triangle %u: index out of range", j);
+    mm = std::max<uint32_t>(mm, M[j]);
+  }
+  auto* s = new rr_scene();
+  s->ctx = ctx;
+  s->nv = nv;
+  s->nt = nt;
+  s->max_mat = mm;
+  s->V.assign(V, V + 3 * (size_t)nv);
+  s->F.assign(F, F + 3 * (size_t)nt);
+  s->M.assign(M, M + nt);
+  *out = s;
+  return RR_OK;
+}
+
+rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt) {
+  if (!sc) return fail(ctx, RR_EINVAL, "scene is NULL");
+  if (sc->ctx != ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
+  BvhBuildOptions o;
+  if (opt) {
+    if (opt->max_leaf_size) o.max_leaf = opt->max_leaf_size;
+    if (opt->sah_bins) o.bins = opt->sah_bins;
+    o.threads = opt->n_threads;
+  }
+  if (o.max_leaf < 1 || o.max_leaf > 16) return fail(ctx, RR_EINVAL, "max_leaf_size out of [1, 16]");
+  if (o.bins < 4 || o.bins > 64) return fail(ctx, RR_EINVAL, "sah_bins out of [4, 64]");
+  try {
+    build_bvh(sc->V.data(), sc->F.data(), sc->nt, sc->M.data(), o, sc->bvh);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, RR_ENOMEM, "host memory for the BVH");
+  }
+  if (sc->bvh.max_depth >= (uint32_t)kStack)
+    return fail(ctx, RR_EOVERFLOW, "BVH depth %u exceeds the traversal stack", sc->bvh.max_depth);
+  sc->built = true;
+  if (!ctx) return RR_OK;
+  DeviceGuard g(ctx->device);
+  if (sc->d_nodes) (void)hipFree(sc->d_nodes);
+  if (sc->d_tris) (void)hipFree(sc->d_tris);
+  if (sc->d_aux) (void)hipFree(sc->d_aux);
+  sc->d_nodes = nullptr;
+  sc->d_tris = nullptr;
+  sc->d_aux = nullptr;
+  size_t bn = sizeof(Node) * sc->bvh.nodes.size();
+  size_t bt = sizeof(float4) * std::max<size_t>(sc->bvh.tris.size(), 3);
+  size_t ba = sizeof(float4) * std::max<size_t>(sc->bvh.aux.size(), 1);
+  HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&sc->d_nodes), bn));
+  HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&sc->d_tris), bt));
+  HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&sc->d_aux), ba));
+  HIP_TRY(ctx, hipMemcpy(sc->d_nodes, sc->bvh.nodes.data(), bn, hipMemcpyHostToDevice));
+  if (!sc->bvh.tris.empty())
+    HIP_TRY(ctx, hipMemcpy(sc->d_tris, sc->bvh.tris.data(), sizeof(float4) * sc->bvh.tris.size(),
+                           hipMemcpyHostToDevice));
+  if (!sc->bvh.aux.empty())
+    HIP_TRY(ctx, hipMemcpy(sc->d_aux, sc->bvh.aux.data(), sizeof(float4) * sc->bvh.aux.size(),
+                           hipMemcpyHostToDevice));
+  sc->dev_bytes = bn + bt + ba;
+  return RR_OK;
+}
+
+rr_status rr_bvh_get_info(const rr_scene* sc, rr_bvh_info* out) {
+  if (!sc || !out) return fail(nullptr, RR_EINVAL, "NULL argument");
+  if (!sc->built) return fail(nullptr, RR_ESTATE, "scene has no BVH");
+  std::memset(out, 0, sizeof *out);
+  out->n_tris = sc->bvh.n_tris;
+  out->n_hittable = sc->bvh.n_hittable;
+  out->n_nodes = (uint32_t)sc->bvh.nodes.size();
+  out->n_leaves = sc->bvh.n_leaves;
+  out->max_depth = sc->bvh.max_depth;
+  out->device_bytes = sc->dev_bytes;
+  out->sah_cost = sc->bvh.sah_cost;
+  out->build_ms = sc->bvh.build_ms;
+  return RR_OK;
+}
+
+rr_status rr_bvh_selfcheck(const rr_scene* sc, uint32_t n_rays, uint64_t seed, uint64_t* mismatches) {
+  if (!sc || !mismatches) return fail(nullptr, RR_EINVAL, "NULL argument");
+  if (!sc->built) return fail(nullptr, RR_ESTATE, "scene has no BVH");
+  *mismatches = bvh_selfcheck(sc->bvh, n_rays, seed);
+  return RR_OK;
+}
+
+rr_status rr_scene_release(rr_context* ctx, rr_scene* sc) {
+  if (!sc) return RR_OK;
+  if (sc->ctx != ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
+  if (ctx) {
+    DeviceGuard g(ctx->device);
+    if (sc->d_nodes) (void)hipFree(sc->d_nodes);
+    if (sc->d_tris) (void)hipFree(sc->d_tris);
+    if (sc->d_aux) (void)hipFree(sc->d_aux);
+  }
+  delete sc;
+  return RR_OK;
+}
+
+rr_status rr_workspace_query(const rr_sensor_params* params, size_t* bytes) {
+  if (!bytes) return fail(nullptr, RR_EINVAL, "bytes is NULL");
+  rr_status s = check_params(nullptr, params);
+  if (s) return s;
+  Layout L;
+  make_layout(&params, 1, L);
+  *bytes = L.total;
+  return RR_OK;
+}
+
+rr_status rr_batch_workspace_query(const rr_scan_desc* scans, uint32_t n, size_t* bytes) {
+  if (!bytes || !scans || n == 0 || n > 65535) return fail(nullptr, RR_EINVAL, "need 1..65535 scans");
+  std::vector<const rr_sensor_params*> ps(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    rr_status s = check_params(nullptr, &scans[i].params);
+    if (s) return s;
+    ps[i] = &scans[i].params;
+  }
+  Layout L;
+  make_layout(ps.data(), n, L);
+  *bytes = L.total;
+  return RR_OK;
+}
+
+static rr_status scan_common(rr_context* ctx, const rr_scene* sc, const rr_pose* pose,
+                             const rr_sensor_params* params, const rr_material* mats, uint32_t n_mats,
+                             const uint8_t* mask, float* image, int32_t* records, uint64_t* accum,
+                             void* ws, size_t ws_bytes, rr_scan_stats* stats, void* stream) {
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  rr_status s;
+  if ((s = check_scene(ctx, sc)) || (s = check_params(ctx, params)) || (s = check_pose(ctx, pose)) ||
+      (s = check_materials(ctx, mats, n_mats, sc)))
+    return s;
+  if (!image) return fail(ctx, RR_EINVAL, "image_dev is NULL");
+  DeviceGuard g(ctx->device);
+  Layout L;
+  make_layout(&params, 1, L);
+  if (!ws) {
+    if ((s = ensure_ws(ctx, L.total))) return s;
+    ws = ctx->ws;
+    ws_bytes = ctx->ws_bytes;
+  }
+  std::vector<DevScan> scans(1);
+  make_scan(*pose, *params, scans[0]);
+  scans[0].image = image;
+  scans[0].records = records;
+  scans[0].mask = mask;
+  return run(ctx, sc, scans, &params, mats, n_mats, static_cast<char*>(ws), ws_bytes, stats,
+             static_cast<hipStream_t>(stream), accum, params->beam_width_rad);
+}
+
+rr_status rr_radar_scan(rr_context* ctx, const rr_scene* sc, const rr_pose* pose,
+                        const rr_sensor_params* params, const rr_material* mats, uint32_t n_mats,
+                        float* image_dev, rr_scan_stats* stats, void* stream) {
+  return scan_common(ctx, sc, pose, params, mats, n_mats, nullptr, image_dev, nullptr, nullptr, nullptr, 0,
+                     stats, stream);
+}
+
+rr_status rr_radar_scan_ws(rr_context* ctx, const rr_scene* sc, const rr_pose* pose,
+                           const rr_sensor_params* params, const rr_material* mats, uint32_t n_mats,
+                           float* image_dev, void* ws, size_t ws_bytes, rr_scan_stats* stats, void* stream) {
+  if (!ws) return fail(ctx, RR_EINVAL, "workspace_dev is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(ctx, RR_EINVAL, "workspace not 256-byte aligned");
+  return scan_common(ctx, sc, pose, params, mats, n_mats, nullptr, image_dev, nullptr, nullptr, ws, ws_bytes,
+                     stats, stream);
+}
+
+rr_status rr_radar_scan_records(rr_context* ctx, const rr_scene* sc, const rr_pose* pose,
+                                const rr_sensor_params* params, const rr_material* mats, uint32_t n_mats,
+                                const uint8_t* mask, float* image_dev, int32_t* records_dev,
+                                uint64_t* accum_dev, rr_scan_stats* stats, void* stream) {
+  return scan_common(ctx, sc, pose, params, mats, n_mats, mask, image_dev, records_dev, accum_dev, nullptr,
+                     0, stats, stream);
+}
+
+rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan_desc* descs, uint32_t n,
+                              const rr_material* mats, uint32_t n_mats, rr_scan_stats* stats, void* stream) {
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  if (!descs || n == 0 || n > 65535) return fail(ctx, RR_EINVAL, "need 1..65535 scans");
+  rr_status s;
+  if ((s = check_scene(ctx, sc)) || (s = check_materials(ctx, mats, n_mats, sc))) return s;
+  std::vector<const rr_sensor_params*> ps(n);
+  std::vector<DevScan> scans(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    if ((s = check_params(ctx, &descs[i].params)) || (s = check_pose(ctx, &descs[i].pose))) return s;
+    if (!descs[i].image_dev) return fail(ctx, RR_EINVAL, "scan %u: image_dev is NULL", i);
+    if (descs[i].params.beam_width_rad != descs[0].params.beam_width_rad)
+      return fail(ctx, RR_EINVAL, "scans of a batch must share the beam width");
+    ps[i] = &descs[i].params;
+    make_scan(descs[i].pose, descs[i].params, scans[i]);
+    scans[i].image = descs[i].image_dev;
+  }
+  DeviceGuard g(ctx->device);
+  Layout L;
+  make_layout(ps.data(), n, L);
+  if ((s = ensure_ws(ctx, L.total))) return s;
+  return run(ctx, sc, scans, ps.data(), mats, n_mats, static_cast<char*>(ctx->ws), ctx->ws_bytes, stats,
+             static_cast<hipStream_t>(stream), nullptr, descs[0].params.beam_width_rad);
+}
+
+rr_status rr_profile_enable(rr_context* ctx, uint32_t flags) {
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  if (flags & ~(RR_PROFILE_TIME | RR_PROFILE_COUNT)) return fail(ctx, RR_EINVAL, "unknown profile flags");
+  DeviceGuard g(ctx->device);
+  if ((flags & RR_PROFILE_COUNT) && !ctx->d_prof) {
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->d_prof), 4 * sizeof(unsigned long long)));
+    HIP_TRY(ctx, hipMemset(ctx->d_prof, 0, 4 * sizeof(unsigned long long)));
+  }
+  ctx->prof_flags = flags;
+  return RR_OK;
+}
+
+rr_status rr_profile_read(rr_context* ctx, rr_profile* out) {
+  if (!ctx || !out) return fail(ctx, RR_EINVAL, "NULL argument");
+  DeviceGuard g(ctx->device);
+  std::memset(out, 0, sizeof *out);
+  for (auto& p : ctx->ev_used) {
+    HIP_TRY(ctx, hipEventSynchronize(p.b));
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, p.a, p.b));
+    out->bounce_ms += ms;
+    if (p.depth < RR_MAX_BOUNCES) out->level_ms[p.depth] += ms;
+    out->launches++;
+    ctx->ev_free.push_back(p.a);
+    ctx->ev_free.push_back(p.b);
+  }
+  ctx->ev_used.clear();
+  if (ctx->d_prof) {
+    unsigned long long h[4] = {0, 0, 0, 0};
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipMemcpy(h, ctx->d_prof, sizeof h, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemset(ctx->d_prof, 0, sizeof h));
+    out->node_visits = h[0];
+    out->tri_tests = h[1];
+    out->rays = h[2];
+  }
+  return RR_OK;
+}
+
+}  // extern "C"

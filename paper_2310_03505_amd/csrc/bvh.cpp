@@ -1,0 +1,433 @@
+// bvh.cpp -- host construction of the two-wide bounding-volume hierarchy
+// the GPU traverses, and a host self-check of it.
+//
+// Binned surface-area heuristic (Wald 2007) over triangle centroids, all
+// three axes, built top-down; the upper levels run on several host threads
+// and the result is flattened in depth-first order, so the output does not
+// depend on the thread count.  Inner-node depth is bounded by kMaxDepth - 1
+// by switching to object-median splits when the remaining depth budget gets
+// tight, which bounds the traversal stack.
+#include "bvh.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <future>
+#include <memory>
+#include <thread>
+
+namespace rr {
+namespace {
+
+struct Box {
+  float lo[3] = {INFINITY, INFINITY, INFINITY};
+  float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  void grow(const Box& b) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], b.lo[a]);
+      hi[a] = std::max(hi[a], b.hi[a]);
+    }
+  }
+  void grow(const float* p) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], p[a]);
+      hi[a] = std::max(hi[a], p[a]);
+    }
+  }
+  double area() const {
+    double e[3];
+    for (int a = 0; a < 3; ++a) e[a] = hi[a] > lo[a] ? (double)hi[a] - lo[a] : 0.0;
+    return 2.0 * (e[0] * e[1] + e[1] * e[2] + e[2] * e[0]);
+  }
+  bool empty() const { return !(lo[0] <= hi[0]); }
+};
+
+struct Ref {
+  Box box;
+  float c[3];
+  uint32_t id;
+};
+
+struct BNode {
+  Box box;
+  std::unique_ptr<BNode> l, r;
+  uint32_t begin = 0, count = 0;  // leaf range in the ref array
+  bool leaf() const { return !l; }
+};
+
+struct Builder {
+  std::vector<Ref>& refs;
+  uint32_t max_leaf, bins;
+  int par_depth;
+
+  static int ceil_log2(uint64_t x) {
+    int k = 0;
+    while ((1ull << k) < x) ++k;
+    return k;
+  }
+
+  std::unique_ptr<BNode> make_leaf(uint32_t b, uint32_t n, const Box& box) {
+    auto nd = std::make_unique<BNode>();
+    nd->box = box;
+    nd->begin = b;
+    nd->count = n;
+    return nd;
+  }
+
+  // depth = depth of the inner node this call may create
+  std::unique_ptr<BNode> build(uint32_t b, uint32_t e, int depth) {
+    uint32_t n = e - b;
+    Box box, cb;
+    for (uint32_t i = b; i < e; ++i) {
+      box.grow(refs[i].box);
+      cb.grow(refs[i].c);
+    }
+    if (n <= 1) return make_leaf(b, n, box);
+    int budget = ceil_log2((n + max_leaf - 1) / max_leaf);
+    bool median = depth + budget >= kMaxDepth - 1;
+    uint32_t mid = b;
+    if (!median) {
+      // binned SAH over all three axes
+      double best = INFINITY;
+      int best_axis = -1, best_bin = -1;
+      for (int a = 0; a < 3; ++a) {
+        float ext = cb.hi[a] - cb.lo[a];
+        if (!(ext > 0.0f)) continue;
+        std::vector<Box> bb(bins);
+        std::vector<uint32_t> cnt(bins, 0);
+        double k = (double)bins / ext;
+        for (uint32_t i = b; i < e; ++i) {
+          int bi = (int)((refs[i].c[a] - cb.lo[a]) * k);
+          bi = std::min<int>(std::max(bi, 0), bins - 1);
+          bb[bi].grow(refs[i].box);
+          cnt[bi]++;
+        }
+        std::vector<double> rarea(bins, 0.0);
+        std::vector<uint32_t> rcnt(bins, 0);
+        Box acc;
+        uint32_t c = 0;
+        for (int i = bins - 1; i > 0; --i) {
+          acc.grow(bb[i]);
+          c += cnt[i];
+          rarea[i] = acc.empty() ? 0.0 : acc.area();
+          rcnt[i] = c;
+        }
+        Box lacc;
+        uint32_t lc = 0;
+        for (uint32_t i = 0; i + 1 < bins; ++i) {
+          lacc.grow(bb[i]);
+          lc += cnt[i];
+          if (lc == 0 || rcnt[i + 1] == 0) continue;
+          double cost = lacc.area() * lc + rarea[i + 1] * rcnt[i + 1];
+          if (cost < best) {
+            best = cost;
+            best_axis = a;
+            best_bin = (int)i;
+          }
+        }
+      }
+      double parea = box.area();
+      double split_cost = parea > 0.0 ? 1.0 + best / parea : INFINITY;
+      if (n <= max_leaf && (best_axis < 0 || (double)n <= split_cost)) return make_leaf(b, n, box);
+      if (best_axis >= 0) {
+        int a = best_axis;
+        double k = (double)bins / (cb.hi[a] - cb.lo[a]);
+        auto it = std::partition(refs.begin() + b, refs.begin() + e, [&](const Ref& r) {
+          int bi = (int)((r.c[a] - cb.lo[a]) * k);
+          bi = std::min<int>(std::max(bi, 0), bins - 1);
+          return bi <= best_bin;
+        });
+        mid = (uint32_t)(it - refs.begin());
+      } else {
+        median = true;  // all centroids coincide
+      }
+    }
+    if (median || mid == b || mid == e) {
+      if (n <= max_leaf && !median) return make_leaf(b, n, box);
+      int a = 0;
+      for (int q = 1; q < 3; ++q)
+        if (cb.hi[q] - cb.lo[q] > cb.hi[a] - cb.lo[a]) a = q;
+      mid = b + n / 2;
+      std::nth_element(refs.begin() + b, refs.begin() + mid, refs.begin() + e,
+                       [&](const Ref& x, const Ref& y) {
+                         return x.c[a] < y.c[a] || (x.c[a] == y.c[a] && x.id < y.id);
+                       });
+      if (n <= max_leaf && budget == 0) return make_leaf(b, n, box);
+    }
+    auto nd = std::make_unique<BNode>();
+    nd->box = box;
+    if (depth < par_depth && n > 4096) {
+      auto fut = std::async(std::launch::async, [&, b, mid, depth] { return build(b, mid, depth + 1); });
+      nd->r = build(mid, e, depth + 1);
+      nd->l = fut.get();
+    } else {
+      nd->l = build(b, mid, depth + 1);
+      nd->r = build(mid, e, depth + 1);
+    }
+    return nd;
+  }
+};
+
+struct Flattener {
+  const std::vector<Ref>& refs;
+  const std::vector<float4>& tri3;  // per original triangle: v0, e1, e2
+  const std::vector<float4>& aux0;  // per original triangle: normal, material
+  BuiltBvh& out;
+  float pad;
+  double root_area;
+
+  void put_box(Node& nd, int which, const Box& b) {
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = b.empty() ? 0.0f : b.lo[a] - pad;
+      hi[a] = b.empty() ? 0.0f : b.hi[a] + pad;
+    }
+    if (which == 0) {
+      nd.n0 = float4{lo[0], hi[0], lo[1], hi[1]};
+      nd.n2.x = lo[2];
+      nd.n2.y = hi[2];
+    } else {
+      nd.n1 = float4{lo[0], hi[0], lo[1], hi[1]};
+      nd.n2.z = lo[2];
+      nd.n2.w = hi[2];
+    }
+  }
+
+  // returns the child reference for a subtree; emits inner nodes preorder
+  int32_t emit(const BNode* b, uint32_t depth, int32_t* count) {
+    if (b->leaf()) {
+      uint32_t start = (uint32_t)(out.tris.size() / 3);
+      for (uint32_t i = 0; i < b->count; ++i) {
+        uint32_t id = refs[b->begin + i].id;
+        out.tris.push_back(tri3[3 * id + 0]);
+        out.tris.push_back(tri3[3 * id + 1]);
+        out.tris.push_back(tri3[3 * id + 2]);
+        out.aux.push_back(aux0[id]);
+      }
+      out.n_leaves++;
+      if (root_area > 0.0) out.sah_cost += (b->box.empty() ? 0.0 : b->box.area()) / root_area * b->count;
+      *count = (int32_t)b->count;
+      return ~(int32_t)start;
+    }
+    uint32_t idx = (uint32_t)out.nodes.size();
+    out.nodes.emplace_back();
+    out.max_depth = std::max(out.max_depth, depth);
+    if (root_area > 0.0) out.sah_cost += b->box.area() / root_area;
+    Node nd{};
+    put_box(nd, 0, b->l->box);
+    put_box(nd, 1, b->r->box);
+    int32_t c0 = 0, c1 = 0;
+    int32_t r0 = emit(b->l.get(), depth + 1, &c0);
+    int32_t r1 = emit(b->r.get(), depth + 1, &c1);
+    nd.n3 = int4{r0, r1, c0, c1};
+    out.nodes[idx] = nd;
+    return (int32_t)idx;
+  }
+};
+
+inline uint32_t fbits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+inline float bitsf(uint32_t u) {
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+}  // namespace
+
+void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M,
+               const BvhBuildOptions& opt, BuiltBvh& out) {
+  auto t0 = std::chrono::steady_clock::now();
+  out = BuiltBvh();
+  out.n_tris = nt;
+  std::vector<float4> tri3((size_t)nt * 3);
+  std::vector<float4> aux0(nt);
+  std::vector<Ref> refs;
+  refs.reserve(nt);
+  Box scene;
+  float mag = 1.0f;
+  for (uint32_t j = 0; j < nt; ++j) {
+    const float* p0 = V + 3 * (size_t)F[3 * (size_t)j + 0];
+    const float* p1 = V + 3 * (size_t)F[3 * (size_t)j + 1];
+    const float* p2 = V + 3 * (size_t)F[3 * (size_t)j + 2];
+    float e1[3], e2[3], n[3];
+    for (int a = 0; a < 3; ++a) {
+      e1[a] = p1[a] - p0[a];
+      e2[a] = p2[a] - p0[a];
+    }
+    n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    float nn = dot3(n[0], n[1], n[2], n[0], n[1], n[2]);
+    tri3[3 * (size_t)j + 0] = float4{p0[0], p0[1], p0[2], bitsf(j)};
+    tri3[3 * (size_t)j + 1] = float4{e1[0], e1[1], e1[2], 0.0f};
+    tri3[3 * (size_t)j + 2] = float4{e2[0], e2[1], e2[2], 0.0f};
+    if (!(nn > 0.0f)) continue;  // zero-area: no normal, never hit
+    float len = std::sqrt(nn);
+    aux0[j] = float4{n[0] / len, n[1] / len, n[2] / len, bitsf((uint32_t)M[j])};
+    Ref r;
+    r.box.grow(p0);
+    r.box.grow(p1);
+    r.box.grow(p2);
+    for (int a = 0; a < 3; ++a) {
+      r.c[a] = 0.5f * (r.box.lo[a] + r.box.hi[a]);
+      mag = std::max(mag, std::max(std::fabs(r.box.lo[a]), std::fabs(r.box.hi[a])));
+    }
+    r.id = j;
+    scene.grow(r.box);
+    refs.push_back(r);
+  }
+  out.n_hittable = (uint32_t)refs.size();
+  out.pad = mag * (1.0f / 262144.0f);  // 2^-18 of the largest coordinate
+  for (int a = 0; a < 3; ++a) {
+    out.lo[a] = scene.empty() ? 0.0f : scene.lo[a];
+    out.hi[a] = scene.empty() ? 0.0f : scene.hi[a];
+  }
+  unsigned hw = std::thread::hardware_concurrency();
+  unsigned th = opt.threads ? opt.threads : (hw ? hw : 1);
+  int par_depth = 0;
+  while ((1u << par_depth) < th && par_depth < 8) ++par_depth;
+  Builder bld{refs, std::max(1u, opt.max_leaf), std::max(4u, opt.bins), par_depth};
+  std::unique_ptr<BNode> root;
+  uint32_t n = (uint32_t)refs.size();
+  if (n >= 2) {
+    root = bld.build(0, n, 0);
+  }
+  if (!root || root->leaf()) {
+    // the root must be an inner node: hang everything (0 or 1 triangle, or
+    // one leaf) under it next to an empty leaf
+    auto r = std::make_unique<BNode>();
+    Box box;
+    for (uint32_t i = 0; i < n; ++i) box.grow(refs[i].box);
+    r->box = box;
+    r->l = bld.make_leaf(0, n, box);
+    r->r = bld.make_leaf(n, 0, Box());
+    root = std::move(r);
+  }
+  Flattener fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area()};
+  fl.emit(root.get(), 0, nullptr);
+  auto t1 = std::chrono::steady_clock::now();
+  out.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+// ---------------------------------------------------------------- host traversal
+namespace {
+inline void leaf_test(const BuiltBvh& b, uint32_t start, uint32_t count, const float o[3],
+                      const float d[3], int32_t excl, float& best_t, int32_t& best,
+                      uint32_t& best_orig) {
+  for (uint32_t k = 0; k < count; ++k) {
+    uint32_t li = start + k;
+    if ((int32_t)li == excl) continue;
+    const float4& a = b.tris[3 * (size_t)li + 0];
+    const float4& e1 = b.tris[3 * (size_t)li + 1];
+    const float4& e2 = b.tris[3 * (size_t)li + 2];
+    float t;
+    if (!ray_tri(o[0], o[1], o[2], d[0], d[1], d[2], a.x, a.y, a.z, e1.x, e1.y, e1.z, e2.x, e2.y,
+                 e2.z, best_t, t))
+      continue;
+    uint32_t orig = fbits(a.w);
+    if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
+      best_t = t;
+      best = (int32_t)li;
+      best_orig = orig;
+    }
+  }
+}
+}  // namespace
+
+int32_t host_traverse(const BuiltBvh& b, const float o[3], const float d[3], float tmax,
+                      int32_t excl, float* t_out) {
+  RayBox rb;
+  ray_box_setup(o[0], o[1], o[2], d[0], d[1], d[2], rb);
+  float best_t = tmax;
+  int32_t best = -1;
+  uint32_t best_orig = 0xffffffffu;
+  int32_t stack[kStack];
+  int sp = 0;
+  int32_t cur = 0;
+  for (;;) {
+    const Node& nd = b.nodes[(size_t)cur];
+    bool h0, h1;
+    float t0, t1;
+    node_boxes(nd.n0, nd.n1, nd.n2, rb, best_t, h0, h1, t0, t1);
+    int32_t c0 = nd.n3.x, c1 = nd.n3.y;
+    if (h0 && c0 < 0) {
+      leaf_test(b, (uint32_t)~c0, (uint32_t)nd.n3.z, o, d, excl, best_t, best, best_orig);
+      h0 = false;
+    }
+    if (h1 && c1 < 0) {
+      leaf_test(b, (uint32_t)~c1, (uint32_t)nd.n3.w, o, d, excl, best_t, best, best_orig);
+      h1 = false;
+    }
+    if (h0 && h1) {
+      if (t1 < t0) std::swap(c0, c1);
+      if (sp >= kStack) return -2;  // cannot happen with depth <= kMaxDepth - 1
+      stack[sp++] = c1;
+      cur = c0;
+    } else if (h0) {
+      cur = c0;
+    } else if (h1) {
+      cur = c1;
+    } else {
+      if (sp == 0) break;
+      cur = stack[--sp];
+    }
+  }
+  if (t_out) *t_out = best_t;
+  return best;
+}
+
+int32_t host_brute(const BuiltBvh& b, const float o[3], const float d[3], float tmax,
+                   int32_t excl, float* t_out) {
+  float best_t = tmax;
+  int32_t best = -1;
+  uint32_t best_orig = 0xffffffffu;
+  leaf_test(b, 0, (uint32_t)b.aux.size(), o, d, excl, best_t, best, best_orig);
+  if (t_out) *t_out = best_t;
+  return best;
+}
+
+uint64_t bvh_selfcheck(const BuiltBvh& b, uint32_t n_rays, uint64_t seed) {
+  // xorshift64* for ray sampling; rays start inside the scene bounds
+  uint64_t s = seed * 0x9E3779B97F4A7C15ull + 1;
+  auto next = [&]() {
+    s ^= s >> 12;
+    s ^= s << 25;
+    s ^= s >> 27;
+    return (double)((s * 0x2545F4914F6CDD1Dull) >> 11) * (1.0 / 9007199254740992.0);
+  };
+  float diag = 0.0f;
+  for (int a = 0; a < 3; ++a) diag += (b.hi[a] - b.lo[a]) * (b.hi[a] - b.lo[a]);
+  float tmax = 2.0f * std::sqrt(diag) + 1.0f;
+  uint64_t bad = 0;
+  uint32_t nl = (uint32_t)b.aux.size();
+  for (uint32_t r = 0; r < n_rays; ++r) {
+    float o[3], d[3];
+    for (int a = 0; a < 3; ++a) o[a] = (float)(b.lo[a] + (b.hi[a] - b.lo[a]) * next());
+    double x, y, z, q;
+    do {
+      x = 2 * next() - 1;
+      y = 2 * next() - 1;
+      z = 2 * next() - 1;
+      q = x * x + y * y + z * z;
+    } while (q > 1.0 || q < 1e-6);
+    q = std::sqrt(q);
+    d[0] = (float)(x / q);
+    d[1] = (float)(y / q);
+    d[2] = (float)(z / q);
+    int32_t excl = (nl && (r & 3) == 0) ? (int32_t)(next() * nl) : -1;
+    float ta, tb;
+    int32_t ha = host_traverse(b, o, d, tmax, excl, &ta);
+    int32_t hb = host_brute(b, o, d, tmax, excl, &tb);
+    uint32_t oa = ha >= 0 ? fbits(b.tris[3 * (size_t)ha].w) : 0xffffffffu;
+    uint32_t ob = hb >= 0 ? fbits(b.tris[3 * (size_t)hb].w) : 0xffffffffu;
+    if (oa != ob || ha == -2) ++bad;
+  }
+  return bad;
+}
+
+}  // namespace rr

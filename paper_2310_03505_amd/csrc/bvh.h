@@ -1,0 +1,48 @@
+// bvh.h -- host BVH build over a triangle mesh and its host self-check.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "rr_internal.h"
+
+namespace rr {
+
+struct BvhBuildOptions {
+  uint32_t max_leaf = 4;
+  uint32_t bins = 16;
+  uint32_t threads = 0;
+};
+
+struct BuiltBvh {
+  std::vector<Node> nodes;        // inner nodes, node 0 is the root
+  std::vector<float4> tris;       // 3 per leaf triangle: (v0, orig), (e1, 0), (e2, 0)
+  std::vector<float4> aux;        // 1 per leaf triangle: (unit normal, material bits)
+  uint32_t n_tris = 0;            // triangles in the scene
+  uint32_t n_hittable = 0;        // non-degenerate triangles in the leaves
+  uint32_t n_leaves = 0;
+  uint32_t max_depth = 0;         // deepest inner node (root = 0)
+  float pad = 0.0f;               // absolute box padding
+  float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // scene bounds (unpadded)
+  double sah_cost = 0.0;
+  double build_ms = 0.0;
+};
+
+// vertices nv x 3, indices nt x 3 (validated by the caller), materials nt.
+void build_bvh(const float* vertices, const uint32_t* indices, uint32_t nt,
+               const uint16_t* tri_material, const BvhBuildOptions& opt, BuiltBvh& out);
+
+// Closest hit through the hierarchy on the host (the same traversal order
+// and box test the GPU kernel uses).  Returns the leaf index or -1.
+int32_t host_traverse(const BuiltBvh& b, const float o[3], const float d[3], float tmax,
+                      int32_t excl_leaf, float* t_out);
+
+// Closest hit by testing every leaf triangle.
+int32_t host_brute(const BuiltBvh& b, const float o[3], const float d[3], float tmax,
+                   int32_t excl_leaf, float* t_out);
+
+// Random rays through both; number of differing closest hits.
+uint64_t bvh_selfcheck(const BuiltBvh& b, uint32_t n_rays, uint64_t seed);
+
+}  // namespace rr

@@ -1,0 +1,510 @@
+// kernels.hip -- the radar-scan hot path on CDNA4 (gfx950).
+//
+// One bounce level per launch, wavefront style:
+//   level 0: every work item is a primary ray, generated in registers from
+//            the counter-based generator (Sec. III-A, Eq. 2) and traced at
+//            once -- the primaries never touch memory;
+//   level d: work items are the rays the previous level appended to its
+//            output queue.
+// Per ray: closest hit through the BVH (per-lane stack in LDS), then the
+// interaction (Snell, Fresnel, standard BRDF return, Sec. III-A), the return
+// binned into the polar image with a 64-bit fixed-point atomic (Sec. III-B),
+// and up to two children appended to the next queue with one atomic per
+// wave.  Workgroups are persistent: each wave pulls 64 rays at a time from a
+// per-level cursor, so the level's cost is balanced across the chip.
+//
+// Floating-point rules: no contraction except where fmaf is written; the
+// closest-hit, bin and total-internal-reflection decisions and the child
+// geometry are float32 in a fixed order; energies are float64.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+#pragma clang fp contract(off)
+
+namespace rr {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x64-10, Salmon et al., "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11).
+__device__ __forceinline__ void philox4x64_10(uint64_t k0, uint64_t k1, uint64_t x0, uint64_t x1,
+                                              uint64_t x2, uint64_t x3, uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t hi0 = __umul64hi(M0, x0), lo0 = M0 * x0;
+    uint64_t hi1 = __umul64hi(M1, x2), lo1 = M1 * x2;
+    uint64_t y0 = hi1 ^ x1 ^ k0;
+    uint64_t y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+// Primary ray (k, i) of a scan: D3 cone offset (Eq. 2) around azimuth
+// 2*pi*k/N_az, float64 then rounded to float32.
+__device__ __forceinline__ void gen_primary(const DevScan& s, uint32_t k, uint32_t i, float& dx,
+                                            float& dy, float& dz, float& g) {
+  uint64_t ck = (s.flags & 2u) ? 0u : k;
+  uint64_t ci = (s.flags & 4u) ? (uint64_t)(i >> 1) : (uint64_t)i;
+  uint64_t x[4];
+  philox4x64_10(s.seed, (uint64_t)s.scan_id, ck, ci, 0, 0, x);
+  const double two53 = 1.0 / 9007199254740992.0;
+  double u1 = (double)((x[0] >> 11) + 1u) * two53;
+  double u2 = (double)(x[1] >> 11) * two53;
+  double u3 = (double)(x[2] >> 11) * two53;
+  double zz = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  double omega = -M_PI + 2.0 * M_PI * u3;
+  double r = zz * s.sigma_r;
+  double az_off = r * cos(omega), inc_off = r * sin(omega);
+  if ((s.flags & 4u) && (i & 1u)) az_off = -az_off;
+  double phi = 2.0 * M_PI * (double)k / (double)s.n_az + az_off;
+  double theta = inc_off;
+  double ct = cos(theta);
+  double ds0 = ct * cos(phi), ds1 = ct * sin(phi), ds2 = sin(theta);
+  double w0 = s.R[0] * ds0 + s.R[1] * ds1 + s.R[2] * ds2;
+  double w1 = s.R[3] * ds0 + s.R[4] * ds1 + s.R[5] * ds2;
+  double w2 = s.R[6] * ds0 + s.R[7] * ds1 + s.R[8] * ds2;
+  double len = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+  dx = (float)(w0 / len);
+  dy = (float)(w1 / len);
+  dz = (float)(w2 / len);
+  g = (s.flags & 1u) ? (float)exp(-0.5 * zz * zz) : 1.0f;
+}
+
+// Origin offset of Waechter & Binder (Ray Tracing Gems, 2019, ch. 6).
+__device__ __forceinline__ float offset1(float p, float n) {
+  const float origin = 1.0f / 32.0f, float_scale = 1.0f / 65536.0f, int_scale = 256.0f;
+  int of = (int)(int_scale * n);
+  float pi = __int_as_float(__float_as_int(p) + ((p < 0.0f) ? -of : of));
+  return fabsf(p) < origin ? p + float_scale * n : pi;
+}
+
+__device__ __forceinline__ void normalize3(float& x, float& y, float& z) {
+  float len = sqrtf(dot3(x, y, z, x, y, z));
+  x = x / len;
+  y = y / len;
+  z = z / len;
+}
+
+// Closest hit through the BVH.  The per-lane stack lives in LDS with a
+// stride of the block size (entry s of lane t at stk[s * kBlock]), so the 64
+// lanes of a wave touch 64 consecutive words.
+template <bool kCount>
+__device__ __forceinline__ int32_t traverse(const Node* __restrict__ nodes,
+                                            const float4* __restrict__ tris, float ox, float oy,
+                                            float oz, float dx, float dy, float dz, float tmax,
+                                            int32_t excl, int32_t* __restrict__ stk, float& t_hit,
+                                            uint32_t& orig_hit, uint32_t& n_nodes,
+                                            uint32_t& n_tris, uint32_t max_visits) {
+  RayBox rb;
+  ray_box_setup(ox, oy, oz, dx, dy, dz, rb);
+  float best_t = tmax;
+  int32_t best = -1;
+  uint32_t best_orig = 0xffffffffu;
+  int sp = 0;
+  int32_t cur = 0;
+  // every inner node is entered at most once per ray; the bound only guards
+  // against a malformed tree
+  for (uint32_t visit = 0; visit < max_visits; ++visit) {
+    const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+    float4 n0 = np[0], n1 = np[1], n2 = np[2];
+    int4 n3 = reinterpret_cast<const int4*>(np)[3];
+    if (kCount) ++n_nodes;
+    bool h0, h1;
+    float t0, t1;
+    node_boxes(n0, n1, n2, rb, best_t, h0, h1, t0, t1);
+    int32_t c0 = n3.x, c1 = n3.y;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      bool hs = side ? h1 : h0;
+      int32_t cs = side ? c1 : c0;
+      if (hs && cs < 0) {
+        uint32_t start = (uint32_t)~cs, cnt = (uint32_t)(side ? n3.w : n3.z);
+        for (uint32_t q = 0; q < cnt; ++q) {
+          uint32_t li = start + q;
+          if ((int32_t)li == excl) continue;
+          if (kCount) ++n_tris;
+          float4 a = tris[3 * li + 0];
+          float4 e1 = tris[3 * li + 1];
+          float4 e2 = tris[3 * li + 2];
+          float t;
+          if (!ray_tri(ox, oy, oz, dx, dy, dz, a.x, a.y, a.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
+                       best_t, t))
+            continue;
+          uint32_t orig = __float_as_uint(a.w);
+          if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
+            best_t = t;
+            best = (int32_t)li;
+            best_orig = orig;
+          }
+        }
+        if (side)
+          h1 = false;
+        else
+          h0 = false;
+      }
+    }
+    if (h0 && h1) {
+      if (t1 < t0) {
+        int32_t tmp = c0;
+        c0 = c1;
+        c1 = tmp;
+      }
+      // the builder bounds inner-node depth below kStack, so sp < kStack here
+      if (sp < kStack) {
+        stk[sp * kBlock] = c1;
+        ++sp;
+      }
+      cur = c0;
+    } else if (h0) {
+      cur = c0;
+    } else if (h1) {
+      cur = c1;
+    } else {
+      if (sp == 0) break;
+      --sp;
+      cur = stk[sp * kBlock];
+    }
+  }
+  t_hit = best_t;
+  orig_hit = best_orig;
+  return best;
+}
+
+template <bool kFirst, bool kCount>
+__global__ void __launch_bounds__(kBlock) k_bounce(BounceArgs A) {
+  __shared__ int32_t lds_stack[kStack * kBlock];
+  int32_t* stk = lds_stack + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  // a level never holds more rays than its queue (an overflowing append is
+  // dropped and flagged, but its count still grows)
+  const uint32_t n_in = kFirst ? A.n_first : min(A.counters[kCtrCount + A.depth], A.out_cap);
+  uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0;
+  uint32_t* cursor = A.counters + kCtrWork + A.depth;
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+
+  for (;;) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(cursor, 64u);
+    base = __shfl(base, 0);
+    if (base >= n_in) break;
+    const uint32_t idx = base + lane;
+    bool active = idx < n_in;
+
+    // ---- ray state
+    float ox = 0, oy = 0, oz = 0, L = 0, dx = 1, dy = 0, dz = 0, g = 1;
+    double E = 0;
+    uint32_t pid = 0, heap = 1, medium = kAir, scan = 0;
+    int32_t excl = -1;
+    if (active) {
+      if (kFirst) {
+        // primary: find its scan (scans are ordered by prim_base)
+        uint32_t lo = 0, hi = A.n_scans - 1;
+        while (lo < hi) {
+          uint32_t mid = (lo + hi + 1) >> 1;
+          if (A.scans[mid].prim_base <= idx)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        scan = lo;
+        const DevScan& s = A.scans[scan];
+        pid = idx - s.prim_base;
+        if (s.mask && !s.mask[pid]) {
+          active = false;
+        } else {
+          uint32_t k = pid / s.n_s, i = pid - k * s.n_s;
+          gen_primary(s, k, i, dx, dy, dz, g);
+          ox = s.pos[0];
+          oy = s.pos[1];
+          oz = s.pos[2];
+          E = (double)s.e0;
+        }
+      } else {
+        float4 a = A.in.a[idx];
+        float4 b = A.in.b[idx];
+        uint4 c = A.in.c[idx];
+        uint32_t m = A.in.m[idx];
+        ox = a.x;
+        oy = a.y;
+        oz = a.z;
+        L = a.w;
+        dx = b.x;
+        dy = b.y;
+        dz = b.z;
+        g = b.w;
+        E = __hiloint2double((int)c.y, (int)c.x);
+        pid = c.z;
+        excl = (int32_t)c.w;
+        heap = m & 0xffu;
+        medium = (m >> 8) & 0xffu;
+        scan = m >> 16;
+      }
+    }
+
+    // ---- closest hit
+    const DevScan* S = A.scans + scan;
+    float n_cur = 1.0f;
+    int32_t hit = -1;
+    float t = 0.0f;
+    uint32_t orig = 0;
+    uint32_t max_b = 1, n_s = 1;
+    if (active) {
+      max_b = S->max_b;
+      n_s = S->n_s;
+      n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
+      float tmax = (S->r_max - L) / n_cur;
+      hit = traverse<kCount>(A.nodes, A.tris, ox, oy, oz, dx, dy, dz, tmax, excl, stk, t, orig,
+                             cnt_nodes, cnt_tris, A.n_nodes);
+      if (kCount) ++cnt_rays;
+      if (S->records) {
+        size_t nheap = (1u << max_b) - 1u;
+        S->records[(size_t)pid * nheap + heap - 1] = hit >= 0 ? (int32_t)orig : -1;
+      }
+    }
+
+    // ---- interaction, return, children
+    bool has_r = false, has_t = false;
+    float rdx = 0, rdy = 0, rdz = 0, tdx = 0, tdy = 0, tdz = 0;
+    float rox = 0, roy = 0, roz = 0, tox = 0, toy = 0, toz = 0;
+    double e_refl = 0.0, e_refr = 0.0;
+    float range = 0.0f;
+    uint32_t t_medium = kAir;
+    if (active && hit >= 0) {
+      float4 ax = A.aux[hit];
+      uint32_t mat = __float_as_uint(ax.w);
+      const DevMaterial M = A.mats[mat];
+      float dn = dot3(dx, dy, dz, ax.x, ax.y, ax.z);
+      bool entering = dn < 0.0f;
+      float nfx = entering ? ax.x : -ax.x;
+      float nfy = entering ? ax.y : -ax.y;
+      float nfz = entering ? ax.z : -ax.z;
+      float dnf = dot3(dx, dy, dz, nfx, nfy, nfz);
+      float cosi = -dnf;
+      float k2 = 2.0f * dnf;
+      rdx = dx - k2 * nfx;
+      rdy = dy - k2 * nfy;
+      rdz = dz - k2 * nfz;
+      normalize3(rdx, rdy, rdz);
+      double R, T;
+      double ci = (double)cosi;
+      bool refract = false;
+      if (M.kind == 0u) {
+        float n1 = n_cur, n2 = entering ? M.n : 1.0f;
+        float eta = n1 / n2;
+        float kappa = 1.0f - (eta * eta) * (1.0f - cosi * cosi);
+        if (kappa < 0.0f) {
+          R = 1.0;
+          T = 0.0;
+        } else {
+          float cost = sqrtf(kappa);
+          float aa = eta * cosi - cost;
+          float ex = eta * dx, ey = eta * dy, ez = eta * dz;
+          tdx = ex + aa * nfx;
+          tdy = ey + aa * nfy;
+          tdz = ez + aa * nfz;
+          normalize3(tdx, tdy, tdz);
+          refract = true;
+          t_medium = entering ? mat : kAir;
+          double N1 = n1, N2 = n2;
+          double e = N1 / N2;
+          double k64 = 1.0 - e * e * (1.0 - ci * ci);
+          double ct = sqrt(k64 > 0.0 ? k64 : 0.0);
+          double dsum = N1 * ci + N2 * ct, psum = N2 * ci + N1 * ct;
+          if (dsum == 0.0 || psum == 0.0) {
+            R = 1.0;
+          } else {
+            double rs = (N1 * ci - N2 * ct) / dsum;
+            double rp = (N2 * ci - N1 * ct) / psum;
+            R = 0.5 * (rs * rs + rp * rp);
+          }
+          T = 1.0 - R;
+        }
+      } else {
+        R = (double)M.refl;
+        T = 0.0;
+      }
+      double w;
+      if (S->flags & 8u) {
+        w = 1.0;
+      } else {
+        double c = 2.0 * ci * ci - 1.0;
+        if (c < 0.0) c = 0.0;
+        w = M.a + M.beta * c + M.s * pow(c, (double)M.C);
+        w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+      }
+      double e_ret = E * R * w;
+      range = L + n_cur * t;
+      float q = range / S->bin_size;
+      if (q < (float)S->n_bins) {
+        uint32_t bin = (uint32_t)q;
+        unsigned long long qv = __double2ull_rn(e_ret * (double)g * kFixedScale);
+        if (qv) {
+          uint32_t k = pid / n_s;
+          atomicAdd(A.acc + S->acc_base + (size_t)k * S->n_bins + bin, qv);
+        }
+      }
+      if (A.depth + 1 < max_b) {
+        double ecut = (double)S->e_cut;
+        e_refl = E * R - e_ret;
+        e_refr = refract ? E * T : 0.0;
+        float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
+        if (e_refl > ecut) {
+          has_r = true;
+          rox = offset1(px, nfx);
+          roy = offset1(py, nfy);
+          roz = offset1(pz, nfz);
+        }
+        if (refract && e_refr > ecut) {
+          has_t = true;
+          tox = offset1(px, -nfx);
+          toy = offset1(py, -nfy);
+          toz = offset1(pz, -nfz);
+        }
+      }
+    }
+
+    // ---- append children: one atomic per wave
+    const uint64_t mr = __ballot(has_r);
+    const uint64_t mt = __ballot(has_t);
+    const uint32_t nr = (uint32_t)__popcll(mr);
+    const uint32_t total = nr + (uint32_t)__popcll(mt);
+    if (total) {
+      uint32_t ob = 0;
+      if (lane == 0) ob = atomicAdd(A.counters + kCtrCount + A.depth + 1, total);
+      ob = __shfl(ob, 0);
+      const uint32_t mbase = (scan << 16) | (medium << 8);
+      if (has_r) {
+        uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
+        if (slot < A.out_cap) {
+          A.out.a[slot] = make_float4(rox, roy, roz, range);
+          A.out.b[slot] = make_float4(rdx, rdy, rdz, g);
+          A.out.c[slot] = make_uint4((uint32_t)__double2loint(e_refl), (uint32_t)__double2hiint(e_refl),
+                                     pid, (uint32_t)hit);
+          A.out.m[slot] = mbase | (2u * heap);
+        } else {
+          atomicOr(A.counters + kCtrOverflow, 1u);
+        }
+      }
+      if (has_t) {
+        uint32_t slot = ob + nr + (uint32_t)__popcll(mt & lanes_below);
+        if (slot < A.out_cap) {
+          A.out.a[slot] = make_float4(tox, toy, toz, range);
+          A.out.b[slot] = make_float4(tdx, tdy, tdz, g);
+          A.out.c[slot] = make_uint4((uint32_t)__double2loint(e_refr), (uint32_t)__double2hiint(e_refr),
+                                     pid, (uint32_t)hit);
+          A.out.m[slot] = (scan << 16) | (t_medium << 8) | (2u * heap + 1u);
+        } else {
+          atomicOr(A.counters + kCtrOverflow, 1u);
+        }
+      }
+    }
+  }
+  if (kCount) {
+    atomicAdd(A.prof + 0, (unsigned long long)cnt_nodes);
+    atomicAdd(A.prof + 1, (unsigned long long)cnt_tris);
+    atomicAdd(A.prof + 2, (unsigned long long)cnt_rays);
+  }
+}
+
+// ---------------------------------------------------------------- helpers
+struct Blob {
+  uint32_t n_words;
+  uint32_t w[760];
+};
+
+__global__ void k_put(uint32_t* dst, Blob b) {
+  for (uint32_t i = threadIdx.x; i < b.n_words; i += blockDim.x) dst[i] = b.w[i];
+}
+
+__global__ void k_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t n_first) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t j = i; j < n_acc; j += stride) acc[j] = 0ull;
+  if (i < (size_t)kCtrWords) counters[i] = (i == (size_t)kCtrCount) ? n_first : 0u;
+}
+
+__global__ void k_fill_i32(int32_t* p, size_t n, int32_t v) {
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) p[j] = v;
+}
+
+__global__ void k_finalize(const DevScan* scans, const unsigned long long* acc) {
+  const DevScan& s = scans[blockIdx.y];
+  size_t n = (size_t)s.n_az * s.n_bins;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+    s.image[j] = (float)((double)acc[s.acc_base + j] * kFixedInv);
+}
+
+hipError_t put_blob(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const uint32_t* w = static_cast<const uint32_t*>(src);
+  size_t words = bytes / 4;
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  Blob b;
+  for (size_t off = 0; off < words; off += 760) {
+    size_t n = words - off < 760 ? words - off : 760;
+    b.n_words = (uint32_t)n;
+    for (size_t i = 0; i < n; ++i) b.w[i] = w[off + i];
+    hipLaunchKernelGGL(k_put, dim3(1), dim3(256), 0, st, d + off, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t n_first,
+                        hipStream_t st) {
+  size_t blocks = (n_acc + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, acc, n_acc, counters, n_first);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_bounce(const BounceArgs& a, uint32_t grid, hipStream_t st) {
+  if (grid < 1) grid = 1;
+  if (a.prof) {
+    if (a.depth == 0)
+      hipLaunchKernelGGL((k_bounce<true, true>), dim3(grid), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_bounce<false, true>), dim3(grid), dim3(kBlock), 0, st, a);
+  } else {
+    if (a.depth == 0)
+      hipLaunchKernelGGL((k_bounce<true, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_bounce<false, false>), dim3(grid), dim3(kBlock), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevScan* scans, uint32_t n_scans, const unsigned long long* acc,
+                           uint32_t max_cells, hipStream_t st) {
+  uint32_t blocks = (max_cells + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_finalize, dim3(blocks, n_scans), dim3(256), 0, st, scans, acc);
+  return hipGetLastError();
+}
+
+}  // namespace rr

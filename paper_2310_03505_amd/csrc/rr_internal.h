@@ -1,0 +1,171 @@
+// rr_internal.h -- layouts shared by the host side (BVH builder, C ABI) and
+// the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define RR_HD __host__ __device__ __forceinline__
+#else
+#include <cmath>
+#define RR_HD inline
+struct alignas(16) float4 {
+  float x, y, z, w;
+};
+struct alignas(16) int4 {
+  int x, y, z, w;
+};
+struct alignas(16) uint4 {
+  unsigned x, y, z, w;
+};
+#endif
+
+namespace rr {
+
+// BVH2 node, 64 bytes: the boxes of both children are stored in the parent
+// so one 64-byte fetch decides both (Aila & Laine 2009 layout).
+//   n0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//   n1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   n2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//   n3 = (child0, child1, count0, count1)
+// child >= 0: inner node index; child < 0: leaf whose triangles start at
+// ~child in the leaf-ordered triangle array, count in n3.z / n3.w.
+struct alignas(64) Node {
+  float4 n0, n1, n2;
+  int4 n3;
+};
+static_assert(sizeof(Node) == 64, "node layout");
+
+constexpr int kMaxDepth = 32;  // inner-node depth bound enforced by the builder
+constexpr int kStack = 32;     // traversal stack entries per lane
+
+// Leaf-ordered triangle, 48 bytes: v0 with the original id in w, then the
+// edges e1 = v1 - v0 and e2 = v2 - v0 (float32, computed on the host).
+// A second 16-byte array holds (geometric unit normal, material id bits).
+
+// Material table entry on the device.  a, beta, s: beam-window coefficients
+// of the normalised standard BRDF (Eq. 3-5), see api.cpp.
+struct DevMaterial {
+  uint32_t kind;
+  float n;
+  float refl;
+  float C;
+  double a, beta, s;
+  double pad;
+};
+static_assert(sizeof(DevMaterial) == 48, "material layout");
+
+// Per-scan constants on the device.
+struct DevScan {
+  double R[9];      // sensor-to-world rotation (row-major)
+  double sigma_r;   // Eq. 2 radius scale
+  float pos[3];     // sensor position
+  float e0;         // 1/N_s, float32
+  float bin_size;
+  float r_max;      // n_bins * bin_size, float32
+  float e_cut;
+  uint32_t n_az, n_s, max_b, n_bins, flags, scan_id;
+  uint64_t seed;
+  uint32_t prim_base;  // first global primary of this scan
+  uint32_t n_prim;     // n_az * n_s
+  uint64_t acc_base;   // first accumulator cell of this scan
+  float* image;
+  int32_t* records;
+  const uint8_t* mask;
+};
+
+// Ray-queue entry, split in four arrays:
+//   a = (o.x, o.y, o.z, L)        L = optical path length so far
+//   b = (d.x, d.y, d.z, g)        g = receive gain of the primary
+//   c = (E lo, E hi, pid, excl)   E float64 energy; pid = primary within the
+//                                 scan; excl = leaf index of the last hit
+//   m = heap | medium << 8 | scan << 16   (medium 255 = air)
+constexpr uint32_t kAir = 255u;
+constexpr size_t kRayBytes = 16 + 16 + 16 + 4;
+
+// counters block (uint32): [0..8] rays per depth, [16..24] work cursors,
+// [32] overflow flag
+constexpr int kCtrCount = 0;
+constexpr int kCtrWork = 16;
+constexpr int kCtrOverflow = 32;
+constexpr int kCtrWords = 64;
+
+constexpr double kFixedScale = 72057594037927936.0;  // 2^56
+constexpr double kFixedInv = 1.0 / 72057594037927936.0;
+
+// ---------------------------------------------------------------- geometry
+// float32, fixed operation order, no contraction: the closest-hit decision
+// must be identical wherever it is evaluated.
+RR_HD float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+  float xy = ax * bx + ay * by;
+  return xy + az * bz;
+}
+
+// Moller & Trumbore 1997 on (v0, e1, e2), both faces, inclusive bounds,
+// accepts 0 < t <= tmax.
+RR_HD bool ray_tri(float ox, float oy, float oz, float dx, float dy, float dz, float v0x,
+                   float v0y, float v0z, float e1x, float e1y, float e1z, float e2x, float e2y,
+                   float e2z, float tmax, float& t_out) {
+  float px = dy * e2z - dz * e2y;
+  float py = dz * e2x - dx * e2z;
+  float pz = dx * e2y - dy * e2x;
+  float det = dot3(e1x, e1y, e1z, px, py, pz);
+  if (det == 0.0f) return false;
+  float inv = 1.0f / det;
+  float sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
+  float u = dot3(sx, sy, sz, px, py, pz) * inv;
+  if (u < 0.0f || u > 1.0f) return false;
+  float qx = sy * e1z - sz * e1y;
+  float qy = sz * e1x - sx * e1z;
+  float qz = sx * e1y - sy * e1x;
+  float v = dot3(dx, dy, dz, qx, qy, qz) * inv;
+  if (v < 0.0f || u + v > 1.0f) return false;
+  float t = dot3(e2x, e2y, e2z, qx, qy, qz) * inv;
+  if (!(t > 0.0f && t <= tmax)) return false;
+  t_out = t;
+  return true;
+}
+
+// ---------------------------------------------------------------- boxes
+// Slab test of both child boxes of a node.  The builder pads every box by a
+// fixed absolute margin and the far distance gets a relative slack, so a
+// triangle hit accepted by ray_tri is never culled by rounding here.
+constexpr float kSlabSlack = 1.0f + 1.0f / 1048576.0f;
+
+struct RayBox {
+  float ix, iy, iz;     // 1 / d (zero components replaced by +-1e-20)
+  float oix, oiy, oiz;  // o / d
+};
+
+RR_HD void ray_box_setup(float ox, float oy, float oz, float dx, float dy, float dz, RayBox& r) {
+  const float tiny = 1e-20f;
+  float sx = fabsf(dx) > tiny ? dx : copysignf(tiny, dx);
+  float sy = fabsf(dy) > tiny ? dy : copysignf(tiny, dy);
+  float sz = fabsf(dz) > tiny ? dz : copysignf(tiny, dz);
+  r.ix = 1.0f / sx;
+  r.iy = 1.0f / sy;
+  r.iz = 1.0f / sz;
+  r.oix = ox * r.ix;
+  r.oiy = oy * r.iy;
+  r.oiz = oz * r.iz;
+}
+
+RR_HD void node_boxes(const float4& n0, const float4& n1, const float4& n2, const RayBox& r,
+                      float tmax, bool& hit0, bool& hit1, float& tn0, float& tn1) {
+  float l0x = fmaf(n0.x, r.ix, -r.oix), h0x = fmaf(n0.y, r.ix, -r.oix);
+  float l0y = fmaf(n0.z, r.iy, -r.oiy), h0y = fmaf(n0.w, r.iy, -r.oiy);
+  float l0z = fmaf(n2.x, r.iz, -r.oiz), h0z = fmaf(n2.y, r.iz, -r.oiz);
+  float l1x = fmaf(n1.x, r.ix, -r.oix), h1x = fmaf(n1.y, r.ix, -r.oix);
+  float l1y = fmaf(n1.z, r.iy, -r.oiy), h1y = fmaf(n1.w, r.iy, -r.oiy);
+  float l1z = fmaf(n2.z, r.iz, -r.oiz), h1z = fmaf(n2.w, r.iz, -r.oiz);
+  tn0 = fmaxf(fmaxf(fminf(l0x, h0x), fminf(l0y, h0y)), fmaxf(fminf(l0z, h0z), 0.0f));
+  float tf0 = fminf(fminf(fmaxf(l0x, h0x), fmaxf(l0y, h0y)), fminf(fmaxf(l0z, h0z), tmax));
+  tn1 = fmaxf(fmaxf(fminf(l1x, h1x), fminf(l1y, h1y)), fmaxf(fminf(l1z, h1z), 0.0f));
+  float tf1 = fminf(fminf(fmaxf(l1x, h1x), fmaxf(l1y, h1y)), fminf(fmaxf(l1z, h1z), tmax));
+  hit0 = tn0 <= tf0 * kSlabSlack;
+  hit1 = tn1 <= tf1 * kSlabSlack;
+}
+
+}  // namespace rr

@@ -1,0 +1,131 @@
+"""Host-side checks of the HIP library that need no GPU: the shared library
+loads and exports every symbol its header declares, arguments are
+validated, and the host-built BVH agrees with brute force."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2310_03505_amd as lib
+    lib.load_library()
+    return lib
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "radarays_hip.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:rr_status|const char\*)\s+(rr_\w+)\s*\(", txt, re.M)))
+
+
+def test_exports_every_declared_symbol(R):
+    lib = R.load_library()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(R.EXPORTS)
+
+
+def test_status_strings(R):
+    lib = R.load_library()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.rr_status_str(s)
+
+
+def test_no_device_is_reported(R):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(R.RadarError) as e:
+        R.rr_create(0)
+    assert e.value.status == R.RR_EDEVICE
+
+
+def test_workspace_query_and_validation(R):
+    p = W.urban_block().params
+    n = R.rr_workspace_query(p)
+    # two queues of N_p * 2^(B-1) rays of 52 bytes + the accumulator
+    n_p = 400 * 1024
+    assert n >= 2 * n_p * 8 * 52 + 400 * 3776 * 8
+    assert n < 2 * n_p * 8 * 52 + 400 * 3776 * 8 + (1 << 20)
+    for bad in [dict(p, max_bounces=9), dict(p, n_azimuth=0), dict(p, beam_prob=0.0),
+                dict(p, beam_width_rad=4.0), dict(p, rays_per_beam=(1 << 20) + 1),
+                dict(p, n_azimuth=65535, rays_per_beam=4096)]:
+        with pytest.raises(R.RadarError) as e:
+            R.rr_workspace_query(bad)
+        assert e.value.status == R.RR_EINVAL
+
+
+def test_scene_upload_validation(R):
+    V = np.zeros((3, 3), np.float32)
+    with pytest.raises(R.RadarError):
+        R.rr_scene_upload(None, V, np.array([[0, 1, 3]], np.uint32), np.zeros(1, np.uint16))
+    Vn = V.copy()
+    Vn[1, 1] = np.nan
+    with pytest.raises(R.RadarError):
+        R.rr_scene_upload(None, Vn, np.array([[0, 1, 2]], np.uint32), np.zeros(1, np.uint16))
+
+
+@pytest.mark.parametrize("name", ["tiny_room", "urban_block", "thin_pillars", "slab", "empty",
+                                  "single", "degenerate_only"])
+def test_host_bvh_matches_brute_force(R, name):
+    if name == "tiny_room":
+        s, n = W.tiny_room(), 20000
+    elif name == "urban_block":
+        s, n = W.urban_block(), 1500
+    elif name == "thin_pillars":
+        s, n = W.thin_pillars_scene(), 20000
+    elif name == "slab":
+        s, n = W.slab_scene(2.0, 0.01, W.material_dielectric(2.0)), 5000
+    elif name == "empty":
+        s, n = W.tiny_room(), 100
+        s.indices, s.tri_material = s.indices[:0], s.tri_material[:0]
+    elif name == "single":
+        s, n = W.single_triangle_scene((3, -2, -2), (3, 0, 3), (3, 2, -2), W.material_metal()), 1000
+    else:
+        V = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32)
+        s = W.Scene("deg", V, np.array([[0, 1, 2]], np.uint32), np.zeros(1, np.uint16), [], {}, {})
+        n = 100
+    sc = R.Scene(None, s.vertices, s.indices, s.tri_material)
+    info = sc.info()
+    assert info["max_depth"] < 32
+    assert info["n_tris"] == s.n_tris
+    if name == "degenerate_only":
+        assert info["n_hittable"] == 0
+    assert sc.selfcheck(n, 7) == 0
+    sc.release()
+
+
+@pytest.mark.parametrize("leaf,bins", [(1, 4), (2, 8), (8, 32), (16, 64)])
+def test_host_bvh_options(R, leaf, bins):
+    s = W.tiny_room()
+    sc = R.Scene(None, s.vertices, s.indices, s.tri_material, max_leaf_size=leaf, sah_bins=bins)
+    assert sc.selfcheck(5000, 3) == 0
+    sc.release()
+
+
+def test_deep_median_fallback_bounds_depth(R):
+    """A pathological mesh (triangles in a geometric progression along x)
+    would give a very deep SAH tree; the builder caps inner depth below the
+    traversal stack size."""
+    n = 5000
+    xs = np.cumsum(1.05 ** np.arange(n)) * 1e-3
+    xs = np.minimum(xs, 1e6)
+    V = np.zeros((3 * n, 3), np.float32)
+    V[0::3, 0] = xs
+    V[1::3, 0] = xs + 1e-3
+    V[1::3, 1] = 0.5
+    V[2::3, 0] = xs
+    V[2::3, 2] = 0.5
+    F = np.arange(3 * n, dtype=np.uint32).reshape(n, 3)
+    sc = R.Scene(None, V, F, np.zeros(n, np.uint16), max_leaf_size=1)
+    assert sc.info()["max_depth"] < 32
+    assert sc.selfcheck(3000, 11) == 0
+    sc.release()
