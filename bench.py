@@ -23,16 +23,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic bytes per unit of work
-NODE_BYTES = 64      # one two-child node: both child boxes + child refs
-TRI_BYTES = 48       # v0 | e1 | e2 of a leaf triangle
-HIT_BYTES = 16       # normal + material of the hit triangle
-RAY_BYTES = 52       # one queued ray (read once, written once)
-BIN_BYTES = 8        # one 64-bit fixed-point atomic
+# algorithmic bytes per unit of work of the trace kernel
+NODE_BYTES = 64        # one two-child node: both child boxes + child refs
+TRI_BYTES = 48         # v0 | e1 | e2 of a leaf triangle
+TRACE_RAY_BYTES = 52   # origin, L, direction, excluded leaf, medium/scan of a queued ray
+HIT_RECORD_BYTES = 8   # (t, leaf) written per ray
 # algorithmic float operations (fused multiply-add = 2)
-NODE_FLOPS = 42      # two slab tests: 12 FMA, 18 min/max, 2 scaled compares
-TRI_FLOPS = 46       # Moller-Trumbore (all stages)
-SHADE_FLOPS = 160    # normal orientation, mirror/refraction directions, Fresnel, lobe
+NODE_FLOPS = 42        # two slab tests: 12 FMA, 18 min/max, 2 scaled compares
+TRI_FLOPS = 46         # Moller-Trumbore (all stages)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
@@ -142,15 +140,13 @@ def main():
     seg_rate = segs * args.steps / (ms / 1e3) / 1e6
     scans_per_s = args.steps / (ms / 1e3)
 
-    # roofline of the bounce kernel: algorithmic bytes and flops per launch
+    # roofline of the dominant kernel (k_trace): algorithmic bytes and flops
+    # per launch from the counting pass, time per launch from the live events
     launches_per_scan = p["max_bounces"]
-    rays = sum(st["rays_per_depth"])
-    queued = rays - st["rays_per_depth"][0]           # rays read from a queue (= children written)
-    hits = cnt["rays"]                                 # upper bound on shaded hits
     bytes_scan = (cnt["node_visits"] * NODE_BYTES + cnt["tri_tests"] * TRI_BYTES
-                  + hits * (HIT_BYTES + BIN_BYTES) + 2 * queued * RAY_BYTES)
-    flops_scan = cnt["node_visits"] * NODE_FLOPS + cnt["tri_tests"] * TRI_FLOPS + hits * SHADE_FLOPS
-    launch_ms = prof["bounce_ms"] / max(prof["launches"], 1)
+                  + cnt["rays"] * (TRACE_RAY_BYTES + HIT_RECORD_BYTES))
+    flops_scan = cnt["node_visits"] * NODE_FLOPS + cnt["tri_tests"] * TRI_FLOPS
+    launch_ms = prof["trace_ms"] / max(prof["trace_launches"], 1)
     bytes_launch = bytes_scan / launches_per_scan
     flops_launch = flops_scan / launches_per_scan
     gbs = bytes_launch / (launch_ms / 1e3) / 1e9
@@ -162,12 +158,15 @@ def main():
     else:
         roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(alu_frac, 4), traffic=None)
-    roof.update(kernel="k_bounce", launch_ms=round(launch_ms, 4),
+    roof.update(kernel="k_trace", launch_ms=round(launch_ms, 4),
                 bytes_per_launch=int(bytes_launch), flops_per_launch=int(flops_launch),
                 other_fraction=round(alu_frac if roof["bound"] == "hbm" else mem_frac, 4),
                 node_visits_per_segment=round(cnt["node_visits"] / max(cnt["rays"], 1), 2),
                 tri_tests_per_segment=round(cnt["tri_tests"] / max(cnt["rays"], 1), 2),
-                level_ms=[round(x / args.steps, 4) for x in prof["level_ms"][:p["max_bounces"]]])
+                trace_level_ms=[round(x / args.steps, 4)
+                                for x in prof["trace_level_ms"][:p["max_bounces"]]],
+                shade_ms_per_scan=round(prof["shade_ms"] / args.steps, 4),
+                raygen_ms_per_scan=round(prof["raygen_ms"] / args.steps, 4))
 
     out = {
         "metric": "Mray-segments/s", "value": round(seg_rate, 2), "unit": "Mray-segments/s",

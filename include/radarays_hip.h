@@ -233,17 +233,32 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* scene, const rr_s
 /* Workspace bytes rr_radar_scan_batch needs for these scans. */
 rr_status rr_batch_workspace_query(const rr_scan_desc* scans, uint32_t n_scans, size_t* bytes);
 
+/* ---------------------------------------------------------------- tuning */
+/* Launch parameters of the traversal kernel (all zero = defaults).  They
+ * change speed only, never results. */
+typedef struct {
+  uint32_t refill_lanes;   /* a wave takes new rays once this many lanes are idle (1..64) */
+  uint32_t trace_waves_per_cu; /* persistent trace waves per compute unit (1..32) */
+  uint32_t reserved[6];
+} rr_tuning;
+
+rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t);
+rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out);
+
 /* ---------------------------------------------------------------- profiling */
-#define RR_PROFILE_TIME 1u  /* bracket every bounce launch with HIP events */
-#define RR_PROFILE_COUNT 2u /* use the counting kernel: node visits, triangle tests */
+#define RR_PROFILE_TIME 1u  /* bracket every kernel launch of a scan with HIP events */
+#define RR_PROFILE_COUNT 2u /* use the counting kernels: node visits, triangle tests */
 
 typedef struct {
-  uint64_t launches;           /* bounce launches recorded */
-  double bounce_ms;            /* summed event time of those launches */
-  double level_ms[RR_MAX_BOUNCES];
+  uint64_t trace_launches;     /* closest-hit (trace) launches recorded */
+  double trace_ms;             /* summed event time of those launches */
+  double trace_level_ms[RR_MAX_BOUNCES];
+  double shade_ms;             /* interaction / binning / child launches */
+  double raygen_ms;            /* primary generation launches */
   uint64_t node_visits;        /* inner nodes fetched (RR_PROFILE_COUNT) */
   uint64_t tri_tests;          /* ray-triangle tests (RR_PROFILE_COUNT) */
   uint64_t rays;               /* rays traced by the counted launches */
+  uint64_t hits;               /* rays that hit a triangle */
 } rr_profile;
 
 /* Measurement hooks for benchmarks (not needed for scans).  Enabling with

@@ -60,12 +60,18 @@ class rr_scan_stats(C.Structure):
 
 
 class rr_profile(C.Structure):
-    _fields_ = [("launches", C.c_uint64), ("bounce_ms", C.c_double),
-                ("level_ms", C.c_double * RR_MAX_BOUNCES), ("node_visits", C.c_uint64),
-                ("tri_tests", C.c_uint64), ("rays", C.c_uint64)]
+    _fields_ = [("trace_launches", C.c_uint64), ("trace_ms", C.c_double),
+                ("trace_level_ms", C.c_double * RR_MAX_BOUNCES), ("shade_ms", C.c_double),
+                ("raygen_ms", C.c_double), ("node_visits", C.c_uint64),
+                ("tri_tests", C.c_uint64), ("rays", C.c_uint64), ("hits", C.c_uint64)]
 
 
 RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
+
+
+class rr_tuning(C.Structure):
+    _fields_ = [("refill_lanes", C.c_uint32), ("trace_waves_per_cu", C.c_uint32),
+                ("reserved", C.c_uint32 * 6)]
 
 
 class rr_scan_desc(C.Structure):
@@ -77,6 +83,7 @@ EXPORTS = (
     "rr_bvh_build", "rr_bvh_get_info", "rr_bvh_selfcheck", "rr_scene_release",
     "rr_workspace_query", "rr_radar_scan", "rr_radar_scan_ws", "rr_radar_scan_records",
     "rr_radar_scan_batch", "rr_batch_workspace_query", "rr_profile_enable", "rr_profile_read",
+    "rr_set_tuning", "rr_get_tuning",
 )
 
 _lib = None
@@ -116,6 +123,8 @@ def load_library():
         "rr_batch_workspace_query": (st, [P(rr_scan_desc), C.c_uint32, P(C.c_size_t)]),
         "rr_profile_enable": (st, [vp, C.c_uint32]),
         "rr_profile_read": (st, [vp, P(rr_profile)]),
+        "rr_set_tuning": (st, [vp, P(rr_tuning)]),
+        "rr_get_tuning": (st, [vp, P(rr_tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -304,6 +313,17 @@ def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, 
     return images, (_stats_dict(st) if st is not None else None)
 
 
+def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0):
+    t = rr_tuning(refill_lanes, trace_waves_per_cu)
+    _check(load_library().rr_set_tuning(ctx, C.byref(t)), ctx)
+
+
+def rr_get_tuning(ctx) -> dict:
+    t = rr_tuning()
+    _check(load_library().rr_get_tuning(ctx, C.byref(t)), ctx)
+    return dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu))
+
+
 def rr_profile_enable(ctx, flags: int):
     _check(load_library().rr_profile_enable(ctx, flags), ctx)
 
@@ -311,9 +331,10 @@ def rr_profile_enable(ctx, flags: int):
 def rr_profile_read(ctx) -> dict:
     p = rr_profile()
     _check(load_library().rr_profile_read(ctx, C.byref(p)), ctx)
-    return dict(launches=int(p.launches), bounce_ms=float(p.bounce_ms),
-                level_ms=[float(x) for x in p.level_ms], node_visits=int(p.node_visits),
-                tri_tests=int(p.tri_tests), rays=int(p.rays))
+    return dict(trace_launches=int(p.trace_launches), trace_ms=float(p.trace_ms),
+                trace_level_ms=[float(x) for x in p.trace_level_ms], shade_ms=float(p.shade_ms),
+                raygen_ms=float(p.raygen_ms), node_visits=int(p.node_visits),
+                tri_tests=int(p.tri_tests), rays=int(p.rays), hits=int(p.hits))
 
 
 # ------------------------------------------------------------------ convenience

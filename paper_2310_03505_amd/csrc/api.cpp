@@ -34,10 +34,14 @@ struct rr_context {
   struct EvPair {
     hipEvent_t a, b;
     uint32_t depth;
+    int kind;  // 0 raygen, 1 trace, 2 shade
   };
   std::vector<hipEvent_t> ev_free;
   std::vector<EvPair> ev_used;
   unsigned long long* d_prof = nullptr;
+  // tuning
+  uint32_t refill_lanes = 48;
+  uint32_t trace_waves_per_cu = 20;
 };
 
 struct rr_scene {
@@ -217,7 +221,7 @@ void make_materials(const rr_material* m, uint32_t n, float beam_width, std::vec
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0;
+  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0;
   size_t off_q[2][4] = {};
   size_t total = 0;
   uint64_t cap = 0;       // rays per queue
@@ -226,8 +230,9 @@ struct Layout {
   uint32_t max_b = 0;
 };
 
-// Queue d holds level d; level d of a scan has at most N_p * 2^d rays, and
-// only scans with B > d have a level d.
+// Levels alternate between two queues; level d of a scan has at most
+// N_p * 2^d rays, and only scans with B > d have a level d.  The hit buffer
+// holds one (t, leaf) pair per ray of the current level.
 void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L) {
   uint64_t level[RR_MAX_BOUNCES] = {};
   L = Layout();
@@ -239,6 +244,7 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L) {
     L.max_b = std::max(L.max_b, p.max_bounces);
     for (uint32_t d = 1; d < p.max_bounces; ++d) level[d] += np << d;
   }
+  L.cap = L.n_first;
   for (uint32_t d = 1; d < RR_MAX_BOUNCES; ++d) L.cap = std::max(L.cap, level[d]);
   size_t o = 0;
   L.off_scans = o;
@@ -250,6 +256,8 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L) {
   L.off_acc = o;
   o += align256(8 * L.acc_cells);
   size_t cap = (size_t)std::max<uint64_t>(L.cap, 1);
+  L.off_hits = o;
+  o += align256(8 * cap);
   for (int q = 0; q < 2; ++q) {
     L.off_q[q][0] = o;
     o += align256(16 * cap);
@@ -304,33 +312,32 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   auto* d_acc = reinterpret_cast<unsigned long long*>(ws + L.off_acc);
   HIP_TRY(ctx, put_blob(d_scans, scans.data(), sizeof(DevScan) * scans.size(), st));
   HIP_TRY(ctx, put_blob(d_mats, dm.data(), sizeof(DevMaterial) * dm.size(), st));
-  HIP_TRY(ctx, launch_clear(d_acc, (size_t)L.acc_cells, d_ctr, (uint32_t)L.n_first, st));
+  HIP_TRY(ctx, launch_clear(d_acc, (size_t)L.acc_cells, d_ctr, st));
   for (size_t i = 0; i < scans.size(); ++i)
     if (scans[i].records)
       HIP_TRY(ctx, launch_fill_i32(scans[i].records,
                                    (size_t)scans[i].n_prim * ((1u << scans[i].max_b) - 1u), -2, st));
-  BounceArgs a{};
+  LevelArgs a{};
   a.nodes = sc->d_nodes;
   a.n_nodes = (uint32_t)sc->bvh.nodes.size();
   a.tris = sc->d_tris;
   a.aux = sc->d_aux;
   a.scans = d_scans;
   a.n_scans = (uint32_t)scans.size();
+  a.cap = (uint32_t)L.cap;
   a.mats = d_mats;
   a.acc = d_acc;
-  a.out_cap = (uint32_t)L.cap;
+  a.hits = reinterpret_cast<uint2*>(ws + L.off_hits);
   a.n_first = (uint32_t)L.n_first;
   a.counters = d_ctr;
   a.prof = (ctx->prof_flags & RR_PROFILE_COUNT) ? ctx->d_prof : nullptr;
   const bool timed = (ctx->prof_flags & RR_PROFILE_TIME) != 0;
-  uint32_t persistent = (uint32_t)ctx->n_cu * 8u;
-  uint64_t level_bound = L.n_first;
-  for (uint32_t d = 0; d < L.max_b; ++d) {
-    a.depth = d;
-    a.in = queue_at(ws, L, d & 1);
-    a.out = queue_at(ws, L, (d + 1) & 1);
-    uint64_t blocks = (level_bound + kBlock - 1) / kBlock;
-    uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(blocks, 1), persistent);
+  // trace: persistent, enough waves to fill every CU; raygen/shade: grid-stride
+  const uint32_t trace_grid =
+      std::max(1u, (uint32_t)ctx->n_cu * ctx->trace_waves_per_cu / (kTraceBlock / 64u));
+  a.refill = ctx->refill_lanes;
+  const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
+  auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
     rr_context::EvPair ev{};
     if (timed) {
       for (hipEvent_t* e : {&ev.a, &ev.b}) {
@@ -342,14 +349,36 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
         *e = ctx->ev_free.back();
         ctx->ev_free.pop_back();
       }
-      ev.depth = d;
+      ev.depth = depth;
+      ev.kind = kind;
       HIP_TRY(ctx, hipEventRecord(ev.a, st));
     }
-    HIP_TRY(ctx, launch_bounce(a, grid, st));
+    HIP_TRY(ctx, fn());
     if (timed) {
       HIP_TRY(ctx, hipEventRecord(ev.b, st));
       ctx->ev_used.push_back(ev);
     }
+    return RR_OK;
+  };
+  rr_status rs;
+  a.depth = 0;
+  a.out = queue_at(ws, L, 0);
+  {
+    uint64_t blocks = (L.n_first + kBlock - 1) / kBlock;
+    uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(blocks, 1), flat_cap);
+    if ((rs = timed_launch(0, 0, [&] { return launch_raygen(a, grid, st); }))) return rs;
+  }
+  uint64_t level_bound = L.n_first;
+  for (uint32_t d = 0; d < L.max_b; ++d) {
+    a.depth = d;
+    a.in = queue_at(ws, L, d & 1);
+    a.out = queue_at(ws, L, (d + 1) & 1);
+    uint64_t tblocks = (level_bound + kTraceBlock - 1) / kTraceBlock;
+    uint32_t tgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
+    if ((rs = timed_launch(1, d, [&] { return launch_trace(a, tgrid, st); }))) return rs;
+    uint64_t sblocks = (level_bound + kBlock - 1) / kBlock;
+    uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), flat_cap);
+    if ((rs = timed_launch(2, d, [&] { return launch_shade(a, sgrid, st); }))) return rs;
     level_bound = std::min<uint64_t>(level_bound * 2, L.cap);
   }
   HIP_TRY(ctx, launch_finalize(d_scans, (uint32_t)scans.size(), d_acc, max_cells, st));
@@ -666,6 +695,25 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
              static_cast<hipStream_t>(stream), nullptr, descs[0].params.beam_width_rad);
 }
 
+rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
+  if (!ctx || !t) return fail(ctx, RR_EINVAL, "NULL argument");
+  uint32_t rl = t->refill_lanes ? t->refill_lanes : 48u;
+  uint32_t wc = t->trace_waves_per_cu ? t->trace_waves_per_cu : 20u;
+  if (rl > 64) return fail(ctx, RR_EINVAL, "refill_lanes out of [1, 64]");
+  if (wc > 32) return fail(ctx, RR_EINVAL, "trace_waves_per_cu out of [1, 32]");
+  ctx->refill_lanes = rl;
+  ctx->trace_waves_per_cu = wc;
+  return RR_OK;
+}
+
+rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
+  if (!ctx || !out) return fail(nullptr, RR_EINVAL, "NULL argument");
+  std::memset(out, 0, sizeof *out);
+  out->refill_lanes = ctx->refill_lanes;
+  out->trace_waves_per_cu = ctx->trace_waves_per_cu;
+  return RR_OK;
+}
+
 rr_status rr_profile_enable(rr_context* ctx, uint32_t flags) {
   if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
   if (flags & ~(RR_PROFILE_TIME | RR_PROFILE_COUNT)) return fail(ctx, RR_EINVAL, "unknown profile flags");
@@ -686,9 +734,15 @@ rr_status rr_profile_read(rr_context* ctx, rr_profile* out) {
     HIP_TRY(ctx, hipEventSynchronize(p.b));
     float ms = 0.0f;
     HIP_TRY(ctx, hipEventElapsedTime(&ms, p.a, p.b));
-    out->bounce_ms += ms;
-    if (p.depth < RR_MAX_BOUNCES) out->level_ms[p.depth] += ms;
-    out->launches++;
+    if (p.kind == 1) {
+      out->trace_ms += ms;
+      if (p.depth < RR_MAX_BOUNCES) out->trace_level_ms[p.depth] += ms;
+      out->trace_launches++;
+    } else if (p.kind == 2) {
+      out->shade_ms += ms;
+    } else {
+      out->raygen_ms += ms;
+    }
     ctx->ev_free.push_back(p.a);
     ctx->ev_free.push_back(p.b);
   }
@@ -701,6 +755,7 @@ rr_status rr_profile_read(rr_context* ctx, rr_profile* out) {
     out->node_visits = h[0];
     out->tri_tests = h[1];
     out->rays = h[2];
+    out->hits = h[3];
   }
   return RR_OK;
 }

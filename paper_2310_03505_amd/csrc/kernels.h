@@ -14,21 +14,24 @@ struct QueueView {
   uint32_t* m;
 };
 
-struct BounceArgs {
+// Arguments shared by the per-level kernels.
+struct LevelArgs {
   const Node* nodes;
   uint32_t n_nodes;  // inner nodes (bounds the traversal loop)
+  uint32_t depth;
   const float4* tris;
   const float4* aux;
   const DevScan* scans;
   uint32_t n_scans;
-  uint32_t depth;
+  uint32_t cap;       // capacity of each of the two ray queues and of the hit buffer
   const DevMaterial* mats;
   unsigned long long* acc;
-  QueueView in, out;
-  uint32_t out_cap;  // capacity of each of the two queues
-  uint32_t n_first;  // rays of the first level (primaries of every scan)
+  QueueView in, out;  // rays of this level / children appended for the next
+  uint2* hits;        // per ray of this level: (t bits, leaf index or -1)
+  uint32_t n_first;   // primaries of every scan (raygen work items)
+  uint32_t refill;    // trace: refill a wave once this many lanes are idle
   uint32_t* counters;
-  unsigned long long* prof;  // non-null: counting kernel (node visits, triangle tests, rays)
+  unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)
 };
 
 // Copies `bytes` (multiple of 4) from host memory into device memory by
@@ -36,13 +39,15 @@ struct BounceArgs {
 // return.
 hipError_t put_blob(void* dst_dev, const void* src, size_t bytes, hipStream_t st);
 
-hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t n_first,
-                        hipStream_t st);
+hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
-hipError_t launch_bounce(const BounceArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_finalize(const DevScan* scans, uint32_t n_scans, const unsigned long long* acc,
                            uint32_t max_cells, hipStream_t st);
 
 constexpr int kBlock = 256;
+constexpr int kTraceBlock = 128;  // trace workgroup (LDS stack of kStack words per lane)
 
 }  // namespace rr

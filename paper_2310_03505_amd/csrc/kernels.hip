@@ -1,17 +1,14 @@
 // kernels.hip -- the radar-scan hot path on CDNA4 (gfx950).
 //
-// One bounce level per launch, wavefront style:
-//   level 0: every work item is a primary ray, generated in registers from
-//            the counter-based generator (Sec. III-A, Eq. 2) and traced at
-//            once -- the primaries never touch memory;
-//   level d: work items are the rays the previous level appended to its
-//            output queue.
-// Per ray: closest hit through the BVH (per-lane stack in LDS), then the
-// interaction (Snell, Fresnel, standard BRDF return, Sec. III-A), the return
-// binned into the polar image with a 64-bit fixed-point atomic (Sec. III-B),
-// and up to two children appended to the next queue with one atomic per
-// wave.  Workgroups are persistent: each wave pulls 64 rays at a time from a
-// per-level cursor, so the level's cost is balanced across the chip.
+// Wavefront organisation, three kernels per bounce level:
+//   k_raygen  primaries of every scan from the counter-based generator
+//             (Sec. III-A, Eq. 2), appended to ray queue 0;
+//   k_trace   closest hit of every queued ray through the BVH: persistent
+//             lanes that take a new ray as soon as theirs is done;
+//   k_shade   the interaction at each hit (Snell, Fresnel, standard BRDF
+//             return, Sec. III-A), the return binned into the polar image with
+//             a 64-bit fixed-point atomic (Sec. III-B), and up to two
+//             children appended to the next queue with one atomic per wave.
 //
 // Floating-point rules: no contraction except where fmaf is written; the
 // closest-hit, bin and total-internal-reflection decisions and the child
@@ -98,317 +95,140 @@ __device__ __forceinline__ void normalize3(float& x, float& y, float& z) {
   z = z / len;
 }
 
-// Closest hit through the BVH.  The per-lane stack lives in LDS with a
-// stride of the block size (entry s of lane t at stk[s * kBlock]), so the 64
-// lanes of a wave touch 64 consecutive words.
+// Closest-hit traversal, persistent and replenishing (after Aila & Laine,
+// "Understanding the efficiency of ray traversal on GPUs", HPG 2009): every
+// lane owns one ray at a time and advances it one inner node per loop
+// iteration; lanes whose ray has finished take new rays from the level's
+// cursor (one atomic per wave) as soon as a quarter of the wave is idle, so
+// the wave does not wait for its slowest ray.  The per-lane stack lives in
+// LDS with a stride of the block size (entry s of lane t at stk[s * B]).
 template <bool kCount>
-__device__ __forceinline__ int32_t traverse(const Node* __restrict__ nodes,
-                                            const float4* __restrict__ tris, float ox, float oy,
-                                            float oz, float dx, float dy, float dz, float tmax,
-                                            int32_t excl, int32_t* __restrict__ stk, float& t_hit,
-                                            uint32_t& orig_hit, uint32_t& n_nodes,
-                                            uint32_t& n_tris, uint32_t max_visits) {
-  RayBox rb;
-  ray_box_setup(ox, oy, oz, dx, dy, dz, rb);
-  float best_t = tmax;
-  int32_t best = -1;
-  uint32_t best_orig = 0xffffffffu;
-  int sp = 0;
-  int32_t cur = 0;
-  // every inner node is entered at most once per ray; the bound only guards
-  // against a malformed tree
-  for (uint32_t visit = 0; visit < max_visits; ++visit) {
-    const float4* np = reinterpret_cast<const float4*>(nodes + cur);
-    float4 n0 = np[0], n1 = np[1], n2 = np[2];
-    int4 n3 = reinterpret_cast<const int4*>(np)[3];
-    if (kCount) ++n_nodes;
-    bool h0, h1;
-    float t0, t1;
-    node_boxes(n0, n1, n2, rb, best_t, h0, h1, t0, t1);
-    int32_t c0 = n3.x, c1 = n3.y;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      bool hs = side ? h1 : h0;
-      int32_t cs = side ? c1 : c0;
-      if (hs && cs < 0) {
-        uint32_t start = (uint32_t)~cs, cnt = (uint32_t)(side ? n3.w : n3.z);
-        for (uint32_t q = 0; q < cnt; ++q) {
-          uint32_t li = start + q;
-          if ((int32_t)li == excl) continue;
-          if (kCount) ++n_tris;
-          float4 a = tris[3 * li + 0];
-          float4 e1 = tris[3 * li + 1];
-          float4 e2 = tris[3 * li + 2];
-          float t;
-          if (!ray_tri(ox, oy, oz, dx, dy, dz, a.x, a.y, a.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
-                       best_t, t))
-            continue;
-          uint32_t orig = __float_as_uint(a.w);
-          if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
-            best_t = t;
-            best = (int32_t)li;
-            best_orig = orig;
-          }
-        }
-        if (side)
-          h1 = false;
-        else
-          h0 = false;
-      }
-    }
-    if (h0 && h1) {
-      if (t1 < t0) {
-        int32_t tmp = c0;
-        c0 = c1;
-        c1 = tmp;
-      }
-      // the builder bounds inner-node depth below kStack, so sp < kStack here
-      if (sp < kStack) {
-        stk[sp * kBlock] = c1;
-        ++sp;
-      }
-      cur = c0;
-    } else if (h0) {
-      cur = c0;
-    } else if (h1) {
-      cur = c1;
-    } else {
-      if (sp == 0) break;
-      --sp;
-      cur = stk[sp * kBlock];
-    }
-  }
-  t_hit = best_t;
-  orig_hit = best_orig;
-  return best;
-}
-
-template <bool kFirst, bool kCount>
-__global__ void __launch_bounds__(kBlock) k_bounce(BounceArgs A) {
-  __shared__ int32_t lds_stack[kStack * kBlock];
+__global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
+  __shared__ int32_t lds_stack[kStack * kTraceBlock];
   int32_t* stk = lds_stack + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
-  // a level never holds more rays than its queue (an overflowing append is
-  // dropped and flagged, but its count still grows)
-  const uint32_t n_in = kFirst ? A.n_first : min(A.counters[kCtrCount + A.depth], A.out_cap);
-  uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0;
-  uint32_t* cursor = A.counters + kCtrWork + A.depth;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+  const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
+  uint32_t* cursor = A.counters + kCtrWork + A.depth;
+  const Node* __restrict__ nodes = A.nodes;
+  const float4* __restrict__ tris = A.tris;
+
+  bool valid = false, exhausted = false;
+  uint32_t ridx = 0, visits = 0, best_orig = 0;
+  float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0;
+  RayBox rb{};
+  int32_t best = -1, excl = -1, cur = 0;
+  int sp = 0;
+  uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0;
 
   for (;;) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(cursor, 64u);
-    base = __shfl(base, 0);
-    if (base >= n_in) break;
-    const uint32_t idx = base + lane;
-    bool active = idx < n_in;
-
-    // ---- ray state
-    float ox = 0, oy = 0, oz = 0, L = 0, dx = 1, dy = 0, dz = 0, g = 1;
-    double E = 0;
-    uint32_t pid = 0, heap = 1, medium = kAir, scan = 0;
-    int32_t excl = -1;
-    if (active) {
-      if (kFirst) {
-        // primary: find its scan (scans are ordered by prim_base)
-        uint32_t lo = 0, hi = A.n_scans - 1;
-        while (lo < hi) {
-          uint32_t mid = (lo + hi + 1) >> 1;
-          if (A.scans[mid].prim_base <= idx)
-            lo = mid;
-          else
-            hi = mid - 1;
+    // ---- refill idle lanes (wave-uniform decision)
+    const uint64_t idle = __ballot(!valid);
+    if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
+      const uint32_t n = (uint32_t)__popcll(idle);
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(cursor, n);
+      base = __shfl(base, 0);
+      if (base + n >= n_in) exhausted = true;
+      if (!valid) {
+        const uint32_t my = base + (uint32_t)__popcll(idle & lanes_below);
+        if (my < n_in) {
+          const float4 a = A.in.a[my];
+          const float4 b = A.in.b[my];
+          const uint32_t m = A.in.m[my];
+          excl = (int32_t)A.in.c[my].w;
+          const uint32_t medium = (m >> 8) & 0xffu;
+          const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
+          best_t = (A.scans[m >> 16].r_max - a.w) / n_cur;
+          ox = a.x;
+          oy = a.y;
+          oz = a.z;
+          dx = b.x;
+          dy = b.y;
+          dz = b.z;
+          ray_box_setup(ox, oy, oz, dx, dy, dz, rb);
+          ridx = my;
+          best = -1;
+          best_orig = 0xffffffffu;
+          cur = 0;
+          sp = 0;
+          visits = 0;
+          valid = true;
+          if (kCount) ++cnt_rays;
         }
-        scan = lo;
-        const DevScan& s = A.scans[scan];
-        pid = idx - s.prim_base;
-        if (s.mask && !s.mask[pid]) {
-          active = false;
-        } else {
-          uint32_t k = pid / s.n_s, i = pid - k * s.n_s;
-          gen_primary(s, k, i, dx, dy, dz, g);
-          ox = s.pos[0];
-          oy = s.pos[1];
-          oz = s.pos[2];
-          E = (double)s.e0;
-        }
-      } else {
-        float4 a = A.in.a[idx];
-        float4 b = A.in.b[idx];
-        uint4 c = A.in.c[idx];
-        uint32_t m = A.in.m[idx];
-        ox = a.x;
-        oy = a.y;
-        oz = a.z;
-        L = a.w;
-        dx = b.x;
-        dy = b.y;
-        dz = b.z;
-        g = b.w;
-        E = __hiloint2double((int)c.y, (int)c.x);
-        pid = c.z;
-        excl = (int32_t)c.w;
-        heap = m & 0xffu;
-        medium = (m >> 8) & 0xffu;
-        scan = m >> 16;
       }
     }
+    if (__ballot(valid) == 0ull) break;  // only once the level is exhausted
 
-    // ---- closest hit
-    const DevScan* S = A.scans + scan;
-    float n_cur = 1.0f;
-    int32_t hit = -1;
-    float t = 0.0f;
-    uint32_t orig = 0;
-    uint32_t max_b = 1, n_s = 1;
-    if (active) {
-      max_b = S->max_b;
-      n_s = S->n_s;
-      n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
-      float tmax = (S->r_max - L) / n_cur;
-      hit = traverse<kCount>(A.nodes, A.tris, ox, oy, oz, dx, dy, dz, tmax, excl, stk, t, orig,
-                             cnt_nodes, cnt_tris, A.n_nodes);
-      if (kCount) ++cnt_rays;
-      if (S->records) {
-        size_t nheap = (1u << max_b) - 1u;
-        S->records[(size_t)pid * nheap + heap - 1] = hit >= 0 ? (int32_t)orig : -1;
-      }
-    }
-
-    // ---- interaction, return, children
-    bool has_r = false, has_t = false;
-    float rdx = 0, rdy = 0, rdz = 0, tdx = 0, tdy = 0, tdz = 0;
-    float rox = 0, roy = 0, roz = 0, tox = 0, toy = 0, toz = 0;
-    double e_refl = 0.0, e_refr = 0.0;
-    float range = 0.0f;
-    uint32_t t_medium = kAir;
-    if (active && hit >= 0) {
-      float4 ax = A.aux[hit];
-      uint32_t mat = __float_as_uint(ax.w);
-      const DevMaterial M = A.mats[mat];
-      float dn = dot3(dx, dy, dz, ax.x, ax.y, ax.z);
-      bool entering = dn < 0.0f;
-      float nfx = entering ? ax.x : -ax.x;
-      float nfy = entering ? ax.y : -ax.y;
-      float nfz = entering ? ax.z : -ax.z;
-      float dnf = dot3(dx, dy, dz, nfx, nfy, nfz);
-      float cosi = -dnf;
-      float k2 = 2.0f * dnf;
-      rdx = dx - k2 * nfx;
-      rdy = dy - k2 * nfy;
-      rdz = dz - k2 * nfz;
-      normalize3(rdx, rdy, rdz);
-      double R, T;
-      double ci = (double)cosi;
-      bool refract = false;
-      if (M.kind == 0u) {
-        float n1 = n_cur, n2 = entering ? M.n : 1.0f;
-        float eta = n1 / n2;
-        float kappa = 1.0f - (eta * eta) * (1.0f - cosi * cosi);
-        if (kappa < 0.0f) {
-          R = 1.0;
-          T = 0.0;
-        } else {
-          float cost = sqrtf(kappa);
-          float aa = eta * cosi - cost;
-          float ex = eta * dx, ey = eta * dy, ez = eta * dz;
-          tdx = ex + aa * nfx;
-          tdy = ey + aa * nfy;
-          tdz = ez + aa * nfz;
-          normalize3(tdx, tdy, tdz);
-          refract = true;
-          t_medium = entering ? mat : kAir;
-          double N1 = n1, N2 = n2;
-          double e = N1 / N2;
-          double k64 = 1.0 - e * e * (1.0 - ci * ci);
-          double ct = sqrt(k64 > 0.0 ? k64 : 0.0);
-          double dsum = N1 * ci + N2 * ct, psum = N2 * ci + N1 * ct;
-          if (dsum == 0.0 || psum == 0.0) {
-            R = 1.0;
-          } else {
-            double rs = (N1 * ci - N2 * ct) / dsum;
-            double rp = (N2 * ci - N1 * ct) / psum;
-            R = 0.5 * (rs * rs + rp * rp);
+    // ---- one inner node per valid lane
+    if (valid) {
+      const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+      const float4 n0 = np[0], n1 = np[1], n2 = np[2];
+      const int4 n3 = reinterpret_cast<const int4*>(np)[3];
+      if (kCount) ++cnt_nodes;
+      bool h0, h1;
+      float t0, t1;
+      node_boxes(n0, n1, n2, rb, best_t, h0, h1, t0, t1);
+      int32_t c0 = n3.x, c1 = n3.y;
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const bool hs = side ? h1 : h0;
+        const int32_t cs = side ? c1 : c0;
+        if (hs && cs < 0) {
+          const uint32_t start = (uint32_t)~cs, cnt = (uint32_t)(side ? n3.w : n3.z);
+          for (uint32_t q = 0; q < cnt; ++q) {
+            const uint32_t li = start + q;
+            if ((int32_t)li == excl) continue;
+            if (kCount) ++cnt_tris;
+            const float4 ta = tris[3 * li + 0];
+            const float4 e1 = tris[3 * li + 1];
+            const float4 e2 = tris[3 * li + 2];
+            float t;
+            if (!ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y,
+                         e2.z, best_t, t))
+              continue;
+            const uint32_t orig = __float_as_uint(ta.w);
+            if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
+              best_t = t;
+              best = (int32_t)li;
+              best_orig = orig;
+            }
           }
-          T = 1.0 - R;
+          if (side)
+            h1 = false;
+          else
+            h0 = false;
         }
+      }
+      bool done = false;
+      if (h0 && h1) {
+        if (t1 < t0) {
+          const int32_t tmp = c0;
+          c0 = c1;
+          c1 = tmp;
+        }
+        // the builder bounds inner-node depth below kStack, so sp < kStack
+        if (sp < kStack) {
+          stk[sp * kTraceBlock] = c1;
+          ++sp;
+        }
+        cur = c0;
+      } else if (h0) {
+        cur = c0;
+      } else if (h1) {
+        cur = c1;
+      } else if (sp > 0) {
+        --sp;
+        cur = stk[sp * kTraceBlock];
       } else {
-        R = (double)M.refl;
-        T = 0.0;
+        done = true;
       }
-      double w;
-      if (S->flags & 8u) {
-        w = 1.0;
-      } else {
-        double c = 2.0 * ci * ci - 1.0;
-        if (c < 0.0) c = 0.0;
-        w = M.a + M.beta * c + M.s * pow(c, (double)M.C);
-        w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
-      }
-      double e_ret = E * R * w;
-      range = L + n_cur * t;
-      float q = range / S->bin_size;
-      if (q < (float)S->n_bins) {
-        uint32_t bin = (uint32_t)q;
-        unsigned long long qv = __double2ull_rn(e_ret * (double)g * kFixedScale);
-        if (qv) {
-          uint32_t k = pid / n_s;
-          atomicAdd(A.acc + S->acc_base + (size_t)k * S->n_bins + bin, qv);
-        }
-      }
-      if (A.depth + 1 < max_b) {
-        double ecut = (double)S->e_cut;
-        e_refl = E * R - e_ret;
-        e_refr = refract ? E * T : 0.0;
-        float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
-        if (e_refl > ecut) {
-          has_r = true;
-          rox = offset1(px, nfx);
-          roy = offset1(py, nfy);
-          roz = offset1(pz, nfz);
-        }
-        if (refract && e_refr > ecut) {
-          has_t = true;
-          tox = offset1(px, -nfx);
-          toy = offset1(py, -nfy);
-          toz = offset1(pz, -nfz);
-        }
-      }
-    }
-
-    // ---- append children: one atomic per wave
-    const uint64_t mr = __ballot(has_r);
-    const uint64_t mt = __ballot(has_t);
-    const uint32_t nr = (uint32_t)__popcll(mr);
-    const uint32_t total = nr + (uint32_t)__popcll(mt);
-    if (total) {
-      uint32_t ob = 0;
-      if (lane == 0) ob = atomicAdd(A.counters + kCtrCount + A.depth + 1, total);
-      ob = __shfl(ob, 0);
-      const uint32_t mbase = (scan << 16) | (medium << 8);
-      if (has_r) {
-        uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
-        if (slot < A.out_cap) {
-          A.out.a[slot] = make_float4(rox, roy, roz, range);
-          A.out.b[slot] = make_float4(rdx, rdy, rdz, g);
-          A.out.c[slot] = make_uint4((uint32_t)__double2loint(e_refl), (uint32_t)__double2hiint(e_refl),
-                                     pid, (uint32_t)hit);
-          A.out.m[slot] = mbase | (2u * heap);
-        } else {
-          atomicOr(A.counters + kCtrOverflow, 1u);
-        }
-      }
-      if (has_t) {
-        uint32_t slot = ob + nr + (uint32_t)__popcll(mt & lanes_below);
-        if (slot < A.out_cap) {
-          A.out.a[slot] = make_float4(tox, toy, toz, range);
-          A.out.b[slot] = make_float4(tdx, tdy, tdz, g);
-          A.out.c[slot] = make_uint4((uint32_t)__double2loint(e_refr), (uint32_t)__double2hiint(e_refr),
-                                     pid, (uint32_t)hit);
-          A.out.m[slot] = (scan << 16) | (t_medium << 8) | (2u * heap + 1u);
-        } else {
-          atomicOr(A.counters + kCtrOverflow, 1u);
-        }
+      // every inner node is entered at most once per ray; the bound only
+      // guards against a malformed tree
+      if (++visits > A.n_nodes) done = true;
+      if (done) {
+        A.hits[ridx] = make_uint2(__float_as_uint(best_t), (uint32_t)best);
+        valid = false;
       }
     }
   }
@@ -417,6 +237,244 @@ __global__ void __launch_bounds__(kBlock) k_bounce(BounceArgs A) {
     atomicAdd(A.prof + 1, (unsigned long long)cnt_tris);
     atomicAdd(A.prof + 2, (unsigned long long)cnt_rays);
   }
+}
+
+// Wave-aggregated append of up to one ray per lane into a queue: one atomic
+// per wave.  Returns the slot of this lane (valid only if `want`).
+__device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter, uint32_t lane,
+                                                uint64_t lanes_below, uint64_t& mask) {
+  mask = __ballot(want);
+  const uint32_t total = (uint32_t)__popcll(mask);
+  uint32_t base = 0;
+  if (total) {
+    if (lane == 0) base = atomicAdd(counter, total);
+    base = __shfl(base, 0);
+  }
+  return base + (uint32_t)__popcll(mask & lanes_below);
+}
+
+__device__ __forceinline__ void put_ray(const QueueView& q, uint32_t slot, float ox, float oy, float oz,
+                                        float L, float dx, float dy, float dz, float g, double E,
+                                        uint32_t pid, uint32_t excl, uint32_t meta) {
+  q.a[slot] = make_float4(ox, oy, oz, L);
+  q.b[slot] = make_float4(dx, dy, dz, g);
+  q.c[slot] = make_uint4((uint32_t)__double2loint(E), (uint32_t)__double2hiint(E), pid, excl);
+  q.m[slot] = meta;
+}
+
+// Primary rays of every scan (level 0).  Work items are global primary
+// indices; masked primaries are skipped; the rest are appended to queue 0.
+__global__ void __launch_bounds__(kBlock) k_raygen(LevelArgs A) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t base = wave * 64u; base < A.n_first; base += n_waves * 64u) {
+    const uint32_t gp = base + lane;
+    bool active = gp < A.n_first;
+    uint32_t scan = 0, pid = 0;
+    float dx = 1, dy = 0, dz = 0, g = 1, ox = 0, oy = 0, oz = 0;
+    double E = 0.0;
+    if (active) {
+      uint32_t lo = 0, hi = A.n_scans - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (A.scans[mid].prim_base <= gp)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      scan = lo;
+      const DevScan& s = A.scans[scan];
+      pid = gp - s.prim_base;
+      if (s.mask && !s.mask[pid]) {
+        active = false;
+      } else {
+        const uint32_t k = pid / s.n_s, i = pid - k * s.n_s;
+        gen_primary(s, k, i, dx, dy, dz, g);
+        ox = s.pos[0];
+        oy = s.pos[1];
+        oz = s.pos[2];
+        E = (double)s.e0;
+      }
+    }
+    uint64_t mask;
+    const uint32_t slot = wave_append(active, A.counters + kCtrCount, lane, lanes_below, mask);
+    if (active && slot < A.cap)
+      put_ray(A.out, slot, ox, oy, oz, 0.0f, dx, dy, dz, g, E, pid, 0xffffffffu,
+              (scan << 16) | (kAir << 8) | 1u);
+    else if (active)
+      atomicOr(A.counters + kCtrOverflow, 1u);
+  }
+}
+
+// Interaction at the hit of every ray of the level (Sec. III-A): Snell and
+// Fresnel split, the retrace return through the beam window of the standard
+// BRDF, range binning (Sec. III-B) and the two children.
+template <bool kCount>
+__global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
+  uint32_t cnt_hits = 0;
+  for (uint32_t base = wave * 64u; base < n_in; base += n_waves * 64u) {
+    const uint32_t idx = base + lane;
+    const bool active = idx < n_in;
+    bool has_r = false, has_t = false;
+    float rdx = 0, rdy = 0, rdz = 0, tdx = 0, tdy = 0, tdz = 0;
+    float rox = 0, roy = 0, roz = 0, tox = 0, toy = 0, toz = 0;
+    double e_refl = 0.0, e_refr = 0.0;
+    float range = 0.0f, g = 1.0f;
+    uint32_t pid = 0, heap = 1, medium = kAir, scan = 0, t_medium = kAir;
+    int32_t hit = -1;
+    if (active) {
+      const uint2 h = A.hits[idx];
+      const uint32_t m = A.in.m[idx];
+      heap = m & 0xffu;
+      medium = (m >> 8) & 0xffu;
+      scan = m >> 16;
+      const uint4 c = A.in.c[idx];
+      pid = c.z;
+      hit = (int32_t)h.y;
+      const DevScan* S = A.scans + scan;
+      if (S->records) {
+        const size_t nheap = (1u << S->max_b) - 1u;
+        S->records[(size_t)pid * nheap + heap - 1] =
+            hit >= 0 ? (int32_t)__float_as_uint(A.tris[3 * (uint32_t)hit].w) : -1;
+      }
+      if (hit >= 0) {
+        if (kCount) ++cnt_hits;
+        const float t = __uint_as_float(h.x);
+        const float4 a = A.in.a[idx];
+        const float4 b = A.in.b[idx];
+        const double E = __hiloint2double((int)c.y, (int)c.x);
+        const float ox = a.x, oy = a.y, oz = a.z, L = a.w;
+        const float dx = b.x, dy = b.y, dz = b.z;
+        g = b.w;
+        const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
+        const float4 ax = A.aux[hit];
+        const uint32_t mat = __float_as_uint(ax.w);
+        const DevMaterial M = A.mats[mat];
+        const float dn = dot3(dx, dy, dz, ax.x, ax.y, ax.z);
+        const bool entering = dn < 0.0f;
+        const float nfx = entering ? ax.x : -ax.x;
+        const float nfy = entering ? ax.y : -ax.y;
+        const float nfz = entering ? ax.z : -ax.z;
+        const float dnf = dot3(dx, dy, dz, nfx, nfy, nfz);
+        const float cosi = -dnf;
+        const float k2 = 2.0f * dnf;
+        rdx = dx - k2 * nfx;
+        rdy = dy - k2 * nfy;
+        rdz = dz - k2 * nfz;
+        normalize3(rdx, rdy, rdz);
+        double R, T;
+        const double ci = (double)cosi;
+        bool refract = false;
+        if (M.kind == 0u) {
+          const float n1 = n_cur, n2 = entering ? M.n : 1.0f;
+          const float eta = n1 / n2;
+          const float kappa = 1.0f - (eta * eta) * (1.0f - cosi * cosi);
+          if (kappa < 0.0f) {
+            R = 1.0;
+            T = 0.0;
+          } else {
+            const float cost = sqrtf(kappa);
+            const float aa = eta * cosi - cost;
+            const float ex = eta * dx, ey = eta * dy, ez = eta * dz;
+            tdx = ex + aa * nfx;
+            tdy = ey + aa * nfy;
+            tdz = ez + aa * nfz;
+            normalize3(tdx, tdy, tdz);
+            refract = true;
+            t_medium = entering ? mat : kAir;
+            const double N1 = n1, N2 = n2;
+            const double e = N1 / N2;
+            const double k64 = 1.0 - e * e * (1.0 - ci * ci);
+            const double ct = sqrt(k64 > 0.0 ? k64 : 0.0);
+            const double dsum = N1 * ci + N2 * ct, psum = N2 * ci + N1 * ct;
+            if (dsum == 0.0 || psum == 0.0) {
+              R = 1.0;
+            } else {
+              const double rs = (N1 * ci - N2 * ct) / dsum;
+              const double rp = (N2 * ci - N1 * ct) / psum;
+              R = 0.5 * (rs * rs + rp * rp);
+            }
+            T = 1.0 - R;
+          }
+        } else {
+          R = (double)M.refl;
+          T = 0.0;
+        }
+        double w;
+        if (S->flags & 8u) {
+          w = 1.0;
+        } else {
+          double cw = 2.0 * ci * ci - 1.0;
+          if (cw < 0.0) cw = 0.0;
+          w = M.a + M.beta * cw + M.s * pow(cw, (double)M.C);
+          w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+        }
+        const double e_ret = E * R * w;
+        range = L + n_cur * t;
+        const float q = range / S->bin_size;
+        if (q < (float)S->n_bins) {
+          const uint32_t bin = (uint32_t)q;
+          const unsigned long long qv = __double2ull_rn(e_ret * (double)g * kFixedScale);
+          if (qv) {
+            const uint32_t k = pid / S->n_s;
+            atomicAdd(A.acc + S->acc_base + (size_t)k * S->n_bins + bin, qv);
+          }
+        }
+        if (A.depth + 1 < S->max_b) {
+          const double ecut = (double)S->e_cut;
+          e_refl = E * R - e_ret;
+          e_refr = refract ? E * T : 0.0;
+          const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
+          if (e_refl > ecut) {
+            has_r = true;
+            rox = offset1(px, nfx);
+            roy = offset1(py, nfy);
+            roz = offset1(pz, nfz);
+          }
+          if (refract && e_refr > ecut) {
+            has_t = true;
+            tox = offset1(px, -nfx);
+            toy = offset1(py, -nfy);
+            toz = offset1(pz, -nfz);
+          }
+        }
+      }
+    }
+    // ---- children: one atomic per wave for both kinds
+    const uint64_t mr = __ballot(has_r);
+    const uint64_t mt = __ballot(has_t);
+    const uint32_t nr = (uint32_t)__popcll(mr);
+    const uint32_t total = nr + (uint32_t)__popcll(mt);
+    if (total) {
+      uint32_t ob = 0;
+      if (lane == 0) ob = atomicAdd(A.counters + kCtrCount + A.depth + 1, total);
+      ob = __shfl(ob, 0);
+      if (has_r) {
+        const uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
+        if (slot < A.cap)
+          put_ray(A.out, slot, rox, roy, roz, range, rdx, rdy, rdz, g, e_refl, pid, (uint32_t)hit,
+                  (scan << 16) | (medium << 8) | (2u * heap));
+        else
+          atomicOr(A.counters + kCtrOverflow, 1u);
+      }
+      if (has_t) {
+        const uint32_t slot = ob + nr + (uint32_t)__popcll(mt & lanes_below);
+        if (slot < A.cap)
+          put_ray(A.out, slot, tox, toy, toz, range, tdx, tdy, tdz, g, e_refr, pid, (uint32_t)hit,
+                  (scan << 16) | (t_medium << 8) | (2u * heap + 1u));
+        else
+          atomicOr(A.counters + kCtrOverflow, 1u);
+      }
+    }
+  }
+  if (kCount) atomicAdd(A.prof + 3, (unsigned long long)cnt_hits);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -429,11 +487,11 @@ __global__ void k_put(uint32_t* dst, Blob b) {
   for (uint32_t i = threadIdx.x; i < b.n_words; i += blockDim.x) dst[i] = b.w[i];
 }
 
-__global__ void k_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t n_first) {
+__global__ void k_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t j = i; j < n_acc; j += stride) acc[j] = 0ull;
-  if (i < (size_t)kCtrWords) counters[i] = (i == (size_t)kCtrCount) ? n_first : 0u;
+  if (i < (size_t)kCtrWords) counters[i] = 0u;
 }
 
 __global__ void k_fill_i32(int32_t* p, size_t n, int32_t v) {
@@ -465,12 +523,11 @@ hipError_t put_blob(void* dst, const void* src, size_t bytes, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t n_first,
-                        hipStream_t st) {
+hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, hipStream_t st) {
   size_t blocks = (n_acc + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, acc, n_acc, counters, n_first);
+  hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, acc, n_acc, counters);
   return hipGetLastError();
 }
 
@@ -482,19 +539,24 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_bounce(const BounceArgs& a, uint32_t grid, hipStream_t st) {
-  if (grid < 1) grid = 1;
-  if (a.prof) {
-    if (a.depth == 0)
-      hipLaunchKernelGGL((k_bounce<true, true>), dim3(grid), dim3(kBlock), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_bounce<false, true>), dim3(grid), dim3(kBlock), 0, st, a);
-  } else {
-    if (a.depth == 0)
-      hipLaunchKernelGGL((k_bounce<true, false>), dim3(grid), dim3(kBlock), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_bounce<false, false>), dim3(grid), dim3(kBlock), 0, st, a);
-  }
+hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_raygen, dim3(grid ? grid : 1), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
+  if (a.prof)
+    hipLaunchKernelGGL(k_trace<true>, dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_trace<false>, dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st) {
+  if (a.prof)
+    hipLaunchKernelGGL(k_shade<true>, dim3(grid ? grid : 1), dim3(kBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_shade<false>, dim3(grid ? grid : 1), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 

@@ -51,10 +51,11 @@ def test_no_device_is_reported(R):
 def test_workspace_query_and_validation(R):
     p = W.urban_block().params
     n = R.rr_workspace_query(p)
-    # two queues of N_p * 2^(B-1) rays of 52 bytes + the accumulator
-    n_p = 400 * 1024
-    assert n >= 2 * n_p * 8 * 52 + 400 * 3776 * 8
-    assert n < 2 * n_p * 8 * 52 + 400 * 3776 * 8 + (1 << 20)
+    # two queues of N_p * 2^(B-1) rays of 52 bytes, one 8-byte hit per ray
+    # of a level, and the accumulator
+    cap = 400 * 1024 * 8
+    want = 2 * cap * 52 + cap * 8 + 400 * 3776 * 8
+    assert want <= n < want + (1 << 20)
     for bad in [dict(p, max_bounces=9), dict(p, n_azimuth=0), dict(p, beam_prob=0.0),
                 dict(p, beam_width_rad=4.0), dict(p, rays_per_beam=(1 << 20) + 1),
                 dict(p, n_azimuth=65535, rays_per_beam=4096)]:
