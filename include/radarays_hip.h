@@ -116,10 +116,10 @@ typedef struct {
 typedef struct {
   uint32_t n_tris;        /* triangles in the scene */
   uint32_t n_hittable;    /* non-degenerate triangles placed in the BVH */
-  uint32_t n_nodes;       /* inner nodes */
+  uint32_t n_nodes;       /* four-wide inner nodes */
   uint32_t n_leaves;
-  uint32_t max_depth;
-  uint32_t reserved;
+  uint32_t max_depth;     /* deepest inner node (root = 0) */
+  uint32_t max_stack;     /* worst-case traversal stack entries */
   uint64_t device_bytes;  /* nodes + triangles resident on the GPU */
   double sah_cost;
   double build_ms;
@@ -163,8 +163,9 @@ rr_status rr_scene_upload(rr_context* ctx, const float* vertices, uint32_t nv,
                           const uint32_t* indices, uint32_t nt, const uint16_t* tri_material,
                           rr_scene** out);
 
-/* Build the bounding-volume hierarchy on the host (binned SAH, depth <= 32)
- * and copy nodes and triangles to the context's GPU.  Synchronous.  After it
+/* Build the bounding-volume hierarchy on the host (binned SAH, collapsed to
+ * four-wide nodes with 8-bit quantised child boxes) and copy nodes and
+ * triangles to the context's GPU.  Synchronous.  After it
  * the scene is immutable and may be shared by concurrent scans.  opt may be
  * NULL.  Calling it again rebuilds. */
 rr_status rr_bvh_build(rr_context* ctx, rr_scene* scene, const rr_bvh_options* opt);

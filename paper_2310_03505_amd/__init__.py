@@ -50,7 +50,7 @@ class rr_bvh_options(C.Structure):
 
 class rr_bvh_info(C.Structure):
     _fields_ = [("n_tris", C.c_uint32), ("n_hittable", C.c_uint32), ("n_nodes", C.c_uint32),
-                ("n_leaves", C.c_uint32), ("max_depth", C.c_uint32), ("reserved", C.c_uint32),
+                ("n_leaves", C.c_uint32), ("max_depth", C.c_uint32), ("max_stack", C.c_uint32),
                 ("device_bytes", C.c_uint64), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
 
 

@@ -53,7 +53,7 @@ struct rr_scene {
   uint32_t max_mat = 0;
   bool built = false;
   BuiltBvh bvh;
-  Node* d_nodes = nullptr;
+  Node4* d_nodes = nullptr;
   float4* d_tris = nullptr;
   float4* d_aux = nullptr;
   uint64_t dev_bytes = 0;
@@ -220,8 +220,12 @@ void make_materials(const rr_material* m, uint32_t n, float beam_width, std::vec
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// lanes whose traversal stack may spill into the workspace: 256 compute
+// units x 32 waves x 64 lanes
+constexpr uint32_t kSpillLanes = 256u * 32u * 64u;
+
 struct Layout {
-  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0;
+  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0;
   size_t off_q[2][4] = {};
   size_t total = 0;
   uint64_t cap = 0;       // rays per queue
@@ -258,6 +262,8 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L) {
   size_t cap = (size_t)std::max<uint64_t>(L.cap, 1);
   L.off_hits = o;
   o += align256(8 * cap);
+  L.off_spill = o;
+  o += align256(sizeof(int32_t) * (size_t)kSpill * kSpillLanes);
   for (int q = 0; q < 2; ++q) {
     L.off_q[q][0] = o;
     o += align256(16 * cap);
@@ -333,9 +339,10 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   a.prof = (ctx->prof_flags & RR_PROFILE_COUNT) ? ctx->d_prof : nullptr;
   const bool timed = (ctx->prof_flags & RR_PROFILE_TIME) != 0;
   // trace: persistent, enough waves to fill every CU; raygen/shade: grid-stride
-  const uint32_t trace_grid =
-      std::max(1u, (uint32_t)ctx->n_cu * ctx->trace_waves_per_cu / (kTraceBlock / 64u));
+  uint32_t trace_grid = std::max(1u, (uint32_t)ctx->n_cu * ctx->trace_waves_per_cu / (kTraceBlock / 64u));
+  trace_grid = std::min(trace_grid, kSpillLanes / (uint32_t)kTraceBlock);
   a.refill = ctx->refill_lanes;
+  a.spill = reinterpret_cast<int32_t*>(ws + L.off_spill);
   const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
   auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
     rr_context::EvPair ev{};
@@ -532,8 +539,9 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
   } catch (const std::bad_alloc&) {
     return fail(ctx, RR_ENOMEM, "host memory for the BVH");
   }
-  if (sc->bvh.max_depth >= (uint32_t)kStack)
-    return fail(ctx, RR_EOVERFLOW, "BVH depth %u exceeds the traversal stack", sc->bvh.max_depth);
+  if (sc->bvh.max_stack > (uint32_t)(kStack + kSpill))
+    return fail(ctx, RR_EOVERFLOW, "BVH needs %u stack entries, more than %d", sc->bvh.max_stack,
+                kStack + kSpill);
   sc->built = true;
   if (!ctx) return RR_OK;
   DeviceGuard g(ctx->device);
@@ -543,7 +551,7 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
   sc->d_nodes = nullptr;
   sc->d_tris = nullptr;
   sc->d_aux = nullptr;
-  size_t bn = sizeof(Node) * sc->bvh.nodes.size();
+  size_t bn = sizeof(Node4) * sc->bvh.nodes.size();
   size_t bt = sizeof(float4) * std::max<size_t>(sc->bvh.tris.size(), 3);
   size_t ba = sizeof(float4) * std::max<size_t>(sc->bvh.aux.size(), 1);
   HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&sc->d_nodes), bn));
@@ -569,6 +577,7 @@ rr_status rr_bvh_get_info(const rr_scene* sc, rr_bvh_info* out) {
   out->n_nodes = (uint32_t)sc->bvh.nodes.size();
   out->n_leaves = sc->bvh.n_leaves;
   out->max_depth = sc->bvh.max_depth;
+  out->max_stack = sc->bvh.max_stack;
   out->device_bytes = sc->dev_bytes;
   out->sah_cost = sc->bvh.sah_cost;
   out->build_ms = sc->bvh.build_ms;

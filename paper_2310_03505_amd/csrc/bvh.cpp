@@ -1,12 +1,13 @@
-// bvh.cpp -- host construction of the two-wide bounding-volume hierarchy
-// the GPU traverses, and a host self-check of it.
+// bvh.cpp -- host construction of the bounding-volume hierarchy the GPU
+// traverses, and a host self-check of it.
 //
 // Binned surface-area heuristic (Wald 2007) over triangle centroids, all
-// three axes, built top-down; the upper levels run on several host threads
-// and the result is flattened in depth-first order, so the output does not
-// depend on the thread count.  Inner-node depth is bounded by kMaxDepth - 1
-// by switching to object-median splits when the remaining depth budget gets
-// tight, which bounds the traversal stack.
+// three axes, built top-down as a two-wide tree; the upper levels run on
+// several host threads and the result is emitted in depth-first order, so
+// the output does not depend on the thread count.  Build depth is bounded by
+// kMaxDepth - 1 by switching to object-median splits when the remaining
+// depth budget gets tight.  The tree is then collapsed into four-wide nodes
+// with 8-bit child boxes quantised outward in the node's frame.
 #include "bvh.h"
 
 #include <algorithm>
@@ -169,62 +170,134 @@ struct Builder {
   }
 };
 
-struct Flattener {
+// Collapses the two-wide build tree into four-wide quantised nodes: each
+// output node takes the two children of a build node and repeatedly opens
+// its largest-area inner child until it has four children.  Children are
+// emitted after their parent (preorder), so child indices exceed parents'.
+struct Flattener4 {
   const std::vector<Ref>& refs;
-  const std::vector<float4>& tri3;  // per original triangle: v0, e1, e2
-  const std::vector<float4>& aux0;  // per original triangle: normal, material
+  const std::vector<float4>& tri3;
+  const std::vector<float4>& aux0;
   BuiltBvh& out;
   float pad;
   double root_area;
 
-  void put_box(Node& nd, int which, const Box& b) {
-    float lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = b.empty() ? 0.0f : b.lo[a] - pad;
-      hi[a] = b.empty() ? 0.0f : b.hi[a] + pad;
+  static void quantise_axis(float lo, float hi, float& origin, uint32_t& ebyte) {
+    origin = lo;
+    double ext = (double)hi - (double)lo;
+    // smallest e with ext <= 255 * 2^e, so every child fits in 8 bits
+    int e = -126;
+    if (ext > 0.0) {
+      std::frexp(ext / 255.0, &e);
+      while (e > -126 && ext <= 255.0 * std::ldexp(1.0, e - 1)) --e;
+      while (ext > 255.0 * std::ldexp(1.0, e)) ++e;
+      e = std::max(e, -126);
     }
-    if (which == 0) {
-      nd.n0 = float4{lo[0], hi[0], lo[1], hi[1]};
-      nd.n2.x = lo[2];
-      nd.n2.y = hi[2];
-    } else {
-      nd.n1 = float4{lo[0], hi[0], lo[1], hi[1]};
-      nd.n2.z = lo[2];
-      nd.n2.w = hi[2];
-    }
+    ebyte = (uint32_t)(e + 127);
   }
 
-  // returns the child reference for a subtree; emits inner nodes preorder
-  int32_t emit(const BNode* b, uint32_t depth, int32_t* count) {
-    if (b->leaf()) {
-      uint32_t start = (uint32_t)(out.tris.size() / 3);
-      for (uint32_t i = 0; i < b->count; ++i) {
-        uint32_t id = refs[b->begin + i].id;
-        out.tris.push_back(tri3[3 * id + 0]);
-        out.tris.push_back(tri3[3 * id + 1]);
-        out.tris.push_back(tri3[3 * id + 2]);
-        out.aux.push_back(aux0[id]);
-      }
-      out.n_leaves++;
-      if (root_area > 0.0) out.sah_cost += (b->box.empty() ? 0.0 : b->box.area()) / root_area * b->count;
-      *count = (int32_t)b->count;
-      return ~(int32_t)start;
+  uint32_t leaf_ref(const BNode* b, int32_t* ref, uint32_t* count) {
+    if (b->count == 0) {
+      *ref = kEmpty;
+      *count = 0;
+      return 0;
+    }
+    uint32_t start = (uint32_t)(out.tris.size() / 3);
+    for (uint32_t i = 0; i < b->count; ++i) {
+      uint32_t id = refs[b->begin + i].id;
+      out.tris.push_back(tri3[3 * id + 0]);
+      out.tris.push_back(tri3[3 * id + 1]);
+      out.tris.push_back(tri3[3 * id + 2]);
+      out.aux.push_back(aux0[id]);
+    }
+    out.n_leaves++;
+    if (root_area > 0.0) out.sah_cost += b->box.area() / root_area * b->count;
+    *ref = ~(int32_t)start;
+    *count = b->count;
+    return 0;
+  }
+
+  // returns the worst-case stack need of the subtree
+  uint32_t emit(const BNode* b, uint32_t depth, int32_t* ref_out) {
+    std::vector<const BNode*> kids{b->l.get(), b->r.get()};
+    while (kids.size() < 4) {
+      int best = -1;
+      double ba = -1.0;
+      for (size_t i = 0; i < kids.size(); ++i)
+        if (!kids[i]->leaf() && kids[i]->box.area() > ba) {
+          ba = kids[i]->box.area();
+          best = (int)i;
+        }
+      if (best < 0) break;
+      const BNode* o = kids[(size_t)best];
+      kids[(size_t)best] = o->l.get();
+      kids.insert(kids.begin() + best + 1, o->r.get());
     }
     uint32_t idx = (uint32_t)out.nodes.size();
     out.nodes.emplace_back();
     out.max_depth = std::max(out.max_depth, depth);
     if (root_area > 0.0) out.sah_cost += b->box.area() / root_area;
-    Node nd{};
-    put_box(nd, 0, b->l->box);
-    put_box(nd, 1, b->r->box);
-    int32_t c0 = 0, c1 = 0;
-    int32_t r0 = emit(b->l.get(), depth + 1, &c0);
-    int32_t r1 = emit(b->r.get(), depth + 1, &c1);
-    nd.n3 = int4{r0, r1, c0, c1};
+    // padded child boxes and the node frame
+    float clo[4][3], chi[4][3];
+    float nlo[3] = {INFINITY, INFINITY, INFINITY}, nhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (size_t j = 0; j < kids.size(); ++j) {
+      const Box& cb = kids[j]->box;
+      for (int a = 0; a < 3; ++a) {
+        clo[j][a] = cb.empty() ? 0.0f : cb.lo[a] - pad;
+        chi[j][a] = cb.empty() ? 0.0f : cb.hi[a] + pad;
+        if (!cb.empty()) {
+          nlo[a] = std::min(nlo[a], clo[j][a]);
+          nhi[a] = std::max(nhi[a], chi[j][a]);
+        }
+      }
+    }
+    for (int a = 0; a < 3; ++a)
+      if (!(nlo[a] <= nhi[a])) nlo[a] = nhi[a] = 0.0f;
+    float origin[3];
+    uint32_t eb[3];
+    for (int a = 0; a < 3; ++a) quantise_axis(nlo[a], nhi[a], origin[a], eb[a]);
+    uint32_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0}, counts = 0;
+    int32_t ref[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+    uint32_t need_max = 0, n_inner = 0;
+    for (size_t j = 0; j < kids.size(); ++j) {
+      const BNode* k = kids[j];
+      for (int a = 0; a < 3; ++a) {
+        double sc = std::ldexp(1.0, (int)eb[a] - 127);
+        double lo = std::floor(((double)clo[j][a] - (double)origin[a]) / sc);
+        double hi = std::ceil(((double)chi[j][a] - (double)origin[a]) / sc);
+        uint32_t ql = (uint32_t)std::min(255.0, std::max(0.0, lo));
+        uint32_t qh = (uint32_t)std::min(255.0, std::max(0.0, hi));
+        qlo[a] |= ql << (8 * j);
+        qhi[a] |= qh << (8 * j);
+      }
+      if (k->leaf()) {
+        uint32_t cnt;
+        leaf_ref(k, &ref[j], &cnt);
+        counts |= cnt << (8 * j);
+      } else {
+        uint32_t need = emit(k, depth + 1, &ref[j]);
+        need_max = std::max(need_max, need);
+        ++n_inner;
+      }
+    }
+    Node4 nd{};
+    uint32_t ebits = eb[0] | (eb[1] << 8) | (eb[2] << 16);
+    float ebf;
+    std::memcpy(&ebf, &ebits, 4);
+    nd.w0 = float4{origin[0], origin[1], origin[2], ebf};
+    nd.w1 = uint4{qlo[0], qhi[0], qlo[1], qhi[1]};
+    nd.w2 = uint4{qlo[2], qhi[2], counts, 0u};
+    nd.w3 = int4{ref[0], ref[1], ref[2], ref[3]};
     out.nodes[idx] = nd;
-    return (int32_t)idx;
+    *ref_out = (int32_t)idx;
+    return (n_inner ? n_inner - 1 : 0) + need_max;
   }
 };
+
+uint32_t depth_of(const BNode* b) {
+  if (b->leaf()) return 0;
+  return 1 + std::max(depth_of(b->l.get()), depth_of(b->r.get()));
+}
 
 inline uint32_t fbits(float f) {
   uint32_t u;
@@ -308,8 +381,10 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
     r->r = bld.make_leaf(n, 0, Box());
     root = std::move(r);
   }
-  Flattener fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area()};
-  fl.emit(root.get(), 0, nullptr);
+  out.max_depth2 = depth_of(root.get()) - 1;
+  Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area()};
+  int32_t root_ref;
+  out.max_stack = fl.emit(root.get(), 0, &root_ref);
   auto t1 = std::chrono::steady_clock::now();
   out.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 }
@@ -346,32 +421,43 @@ int32_t host_traverse(const BuiltBvh& b, const float o[3], const float d[3], flo
   float best_t = tmax;
   int32_t best = -1;
   uint32_t best_orig = 0xffffffffu;
-  int32_t stack[kStack];
+  int32_t stack[kStack + kSpill];
   int sp = 0;
   int32_t cur = 0;
   for (;;) {
-    const Node& nd = b.nodes[(size_t)cur];
-    bool h0, h1;
-    float t0, t1;
-    node_boxes(nd.n0, nd.n1, nd.n2, rb, best_t, h0, h1, t0, t1);
-    int32_t c0 = nd.n3.x, c1 = nd.n3.y;
-    if (h0 && c0 < 0) {
-      leaf_test(b, (uint32_t)~c0, (uint32_t)nd.n3.z, o, d, excl, best_t, best, best_orig);
-      h0 = false;
+    const Node4& nd = b.nodes[(size_t)cur];
+    float tn[4];
+    uint32_t mask = node4_boxes(nd.w0, nd.w1, nd.w2, nd.w3, rb, best_t, tn);
+    const int32_t ref[4] = {nd.w3.x, nd.w3.y, nd.w3.z, nd.w3.w};
+    float key[4];
+    int32_t val[4];
+    for (int j = 0; j < 4; ++j) {
+      key[j] = INFINITY;
+      val[j] = -1;
+      if (!((mask >> j) & 1u)) continue;
+      if (ref[j] < 0) {
+        leaf_test(b, (uint32_t)~ref[j], (nd.w2.z >> (8 * j)) & 0xffu, o, d, excl, best_t, best,
+                  best_orig);
+      } else {
+        key[j] = tn[j];
+        val[j] = ref[j];
+      }
     }
-    if (h1 && c1 < 0) {
-      leaf_test(b, (uint32_t)~c1, (uint32_t)nd.n3.w, o, d, excl, best_t, best, best_orig);
-      h1 = false;
-    }
-    if (h0 && h1) {
-      if (t1 < t0) std::swap(c0, c1);
-      if (sp >= kStack) return -2;  // cannot happen with depth <= kMaxDepth - 1
-      stack[sp++] = c1;
-      cur = c0;
-    } else if (h0) {
-      cur = c0;
-    } else if (h1) {
-      cur = c1;
+    // sort the inner children by entry distance (5 compare-exchanges)
+    const int pairs[5][2] = {{0, 1}, {2, 3}, {0, 2}, {1, 3}, {1, 2}};
+    for (auto& pr : pairs)
+      if (key[pr[1]] < key[pr[0]]) {
+        std::swap(key[pr[0]], key[pr[1]]);
+        std::swap(val[pr[0]], val[pr[1]]);
+      }
+    int n = 0;
+    while (n < 4 && val[n] >= 0) ++n;
+    if (n > 0) {
+      for (int j = n - 1; j >= 1; --j) {
+        if (sp >= kStack + kSpill) return -2;  // exceeds the bound computed at build time
+        stack[sp++] = val[j];
+      }
+      cur = val[0];
     } else {
       if (sp == 0) break;
       cur = stack[--sp];

@@ -16,13 +16,15 @@ struct BvhBuildOptions {
 };
 
 struct BuiltBvh {
-  std::vector<Node> nodes;        // inner nodes, node 0 is the root
+  std::vector<Node4> nodes;       // four-wide inner nodes, node 0 is the root
   std::vector<float4> tris;       // 3 per leaf triangle: (v0, orig), (e1, 0), (e2, 0)
   std::vector<float4> aux;        // 1 per leaf triangle: (unit normal, material bits)
   uint32_t n_tris = 0;            // triangles in the scene
   uint32_t n_hittable = 0;        // non-degenerate triangles in the leaves
   uint32_t n_leaves = 0;
-  uint32_t max_depth = 0;         // deepest inner node (root = 0)
+  uint32_t max_depth = 0;         // deepest four-wide inner node (root = 0)
+  uint32_t max_depth2 = 0;        // deepest node of the two-wide build tree
+  uint32_t max_stack = 0;         // worst-case traversal stack entries
   float pad = 0.0f;               // absolute box padding
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // scene bounds (unpadded)
   double sah_cost = 0.0;

@@ -16,7 +16,7 @@ struct QueueView {
 
 // Arguments shared by the per-level kernels.
 struct LevelArgs {
-  const Node* nodes;
+  const Node4* nodes;
   uint32_t n_nodes;  // inner nodes (bounds the traversal loop)
   uint32_t depth;
   const float4* tris;
@@ -30,6 +30,7 @@ struct LevelArgs {
   uint2* hits;        // per ray of this level: (t bits, leaf index or -1)
   uint32_t n_first;   // primaries of every scan (raygen work items)
   uint32_t refill;    // trace: refill a wave once this many lanes are idle
+  int32_t* spill;     // trace: stack entries beyond kStack, kSpill per lane (lane-major)
   uint32_t* counters;
   unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)
 };

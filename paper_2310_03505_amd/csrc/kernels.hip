@@ -110,8 +110,10 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
   const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
   uint32_t* cursor = A.counters + kCtrWork + A.depth;
-  const Node* __restrict__ nodes = A.nodes;
+  const Node4* __restrict__ nodes = A.nodes;
   const float4* __restrict__ tris = A.tris;
+  const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t spill_stride = gridDim.x * blockDim.x;
 
   bool valid = false, exhausted = false;
   uint32_t ridx = 0, visits = 0, best_orig = 0;
@@ -163,63 +165,77 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
     // ---- one inner node per valid lane
     if (valid) {
       const float4* np = reinterpret_cast<const float4*>(nodes + cur);
-      const float4 n0 = np[0], n1 = np[1], n2 = np[2];
-      const int4 n3 = reinterpret_cast<const int4*>(np)[3];
+      const float4 w0 = np[0];
+      const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
+      const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
+      const int4 w3 = reinterpret_cast<const int4*>(np)[3];
       if (kCount) ++cnt_nodes;
-      bool h0, h1;
-      float t0, t1;
-      node_boxes(n0, n1, n2, rb, best_t, h0, h1, t0, t1);
-      int32_t c0 = n3.x, c1 = n3.y;
+      float tn[4];
+      uint32_t mask = node4_boxes(w0, w1, w2, w3, rb, best_t, tn);
+      const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
+      float key[4];
+      int32_t val[4];
 #pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        const bool hs = side ? h1 : h0;
-        const int32_t cs = side ? c1 : c0;
-        if (hs && cs < 0) {
-          const uint32_t start = (uint32_t)~cs, cnt = (uint32_t)(side ? n3.w : n3.z);
-          for (uint32_t q = 0; q < cnt; ++q) {
-            const uint32_t li = start + q;
-            if ((int32_t)li == excl) continue;
-            if (kCount) ++cnt_tris;
-            const float4 ta = tris[3 * li + 0];
-            const float4 e1 = tris[3 * li + 1];
-            const float4 e2 = tris[3 * li + 2];
-            float t;
-            if (!ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y,
-                         e2.z, best_t, t))
-              continue;
-            const uint32_t orig = __float_as_uint(ta.w);
-            if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
-              best_t = t;
-              best = (int32_t)li;
-              best_orig = orig;
+      for (int j = 0; j < 4; ++j) {
+        key[j] = INFINITY;
+        val[j] = -1;
+        if ((mask >> j) & 1u) {
+          if (ref[j] < 0) {
+            const uint32_t start = (uint32_t)~ref[j], cnt = (w2.z >> (8 * j)) & 0xffu;
+            for (uint32_t q = 0; q < cnt; ++q) {
+              const uint32_t li = start + q;
+              if ((int32_t)li == excl) continue;
+              if (kCount) ++cnt_tris;
+              const float4 ta = tris[3 * li + 0];
+              const float4 e1 = tris[3 * li + 1];
+              const float4 e2 = tris[3 * li + 2];
+              float t;
+              if (!ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y,
+                           e2.z, best_t, t))
+                continue;
+              const uint32_t orig = __float_as_uint(ta.w);
+              if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
+                best_t = t;
+                best = (int32_t)li;
+                best_orig = orig;
+              }
             }
+          } else {
+            key[j] = tn[j];
+            val[j] = ref[j];
           }
-          if (side)
-            h1 = false;
-          else
-            h0 = false;
         }
       }
+      // inner children near to far: 5 compare-exchanges
+#define RR_CX(i, j)                     \
+  if (key[j] < key[i]) {                \
+    const float tk = key[i];            \
+    key[i] = key[j];                    \
+    key[j] = tk;                        \
+    const int32_t tv = val[i];          \
+    val[i] = val[j];                    \
+    val[j] = tv;                        \
+  }
+      RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
+#undef RR_CX
       bool done = false;
-      if (h0 && h1) {
-        if (t1 < t0) {
-          const int32_t tmp = c0;
-          c0 = c1;
-          c1 = tmp;
+      if (val[0] >= 0) {
+        // push the farther hit children, nearest of them last; the builder
+        // bounds the worst-case depth by kStack + kSpill
+#pragma unroll
+        for (int j = 3; j >= 1; --j) {
+          if (val[j] >= 0 && sp < kStack + kSpill) {
+            if (sp < kStack)
+              stk[sp * kTraceBlock] = val[j];
+            else
+              A.spill[(size_t)(sp - kStack) * spill_stride + gtid] = val[j];
+            ++sp;
+          }
         }
-        // the builder bounds inner-node depth below kStack, so sp < kStack
-        if (sp < kStack) {
-          stk[sp * kTraceBlock] = c1;
-          ++sp;
-        }
-        cur = c0;
-      } else if (h0) {
-        cur = c0;
-      } else if (h1) {
-        cur = c1;
+        cur = val[0];
       } else if (sp > 0) {
         --sp;
-        cur = stk[sp * kTraceBlock];
+        cur = sp < kStack ? stk[sp * kTraceBlock] : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
       } else {
         done = true;
       }

@@ -38,8 +38,25 @@ struct alignas(64) Node {
 };
 static_assert(sizeof(Node) == 64, "node layout");
 
-constexpr int kMaxDepth = 32;  // inner-node depth bound enforced by the builder
-constexpr int kStack = 32;     // traversal stack entries per lane
+constexpr int kMaxDepth = 32;  // two-wide build: inner-node depth bound
+constexpr int kStack = 32;     // traversal stack entries per lane held in LDS
+constexpr int kSpill = 64;     // further entries per lane in workspace memory
+
+// Four-wide node with quantised child boxes, 64 bytes (four 16-byte loads):
+//   w0 = (origin.x, origin.y, origin.z, exponent bytes ex | ey << 8 | ez << 16)
+//   w1 = (qlo.x[4], qhi.x[4], qlo.y[4], qhi.y[4])   one byte per child
+//   w2 = (qlo.z[4], qhi.z[4], leaf counts[4], 0)
+//   w3 = child refs: >= 0 inner node, kEmpty no child, otherwise a leaf whose
+//        triangles start at ~ref
+// Child j covers origin + q * 2^(e - 127) on each axis, rounded outward from
+// the padded float box, so decoding never shrinks a box.
+struct alignas(64) Node4 {
+  float4 w0;
+  uint4 w1, w2;
+  int4 w3;
+};
+static_assert(sizeof(Node4) == 64, "node layout");
+constexpr int32_t kEmpty = (int32_t)0x80000000;
 
 // Leaf-ordered triangle, 48 bytes: v0 with the original id in w, then the
 // edges e1 = v1 - v0 and e2 = v2 - v0 (float32, computed on the host).
@@ -129,6 +146,20 @@ RR_HD bool ray_tri(float ox, float oy, float oz, float dx, float dy, float dz, f
 }
 
 // ---------------------------------------------------------------- boxes
+// Entry and exit distances of the four children of a quantised node.
+// hit[j] is set for children whose (conservative) box meets [0, tmax].
+RR_HD float byte_f(uint32_t w, int j) { return (float)((w >> (8 * j)) & 0xffu); }
+
+RR_HD float pow2_from_byte(uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __uint_as_float(b << 23);
+#else
+  uint32_t u = b << 23;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+#endif
+}
 // Slab test of both child boxes of a node.  The builder pads every box by a
 // fixed absolute margin and the far distance gets a relative slack, so a
 // triangle hit accepted by ray_tri is never culled by rounding here.
@@ -150,6 +181,38 @@ RR_HD void ray_box_setup(float ox, float oy, float oz, float dx, float dy, float
   r.oix = ox * r.ix;
   r.oiy = oy * r.iy;
   r.oiz = oz * r.iz;
+}
+
+// Entry distances of the four children of a quantised node; returns the mask
+// of children whose box meets [0, tmax].  Per axis the child bounds decode as
+// t = q * (2^e / d) + (origin - o) / d, one fused multiply-add per bound.
+RR_HD uint32_t node4_boxes(const float4& w0, const uint4& w1, const uint4& w2, const int4& w3,
+                           const RayBox& r, float tmax, float tn[4]) {
+  uint32_t eb;
+#if defined(__HIP_DEVICE_COMPILE__)
+  eb = __float_as_uint(w0.w);
+#else
+  __builtin_memcpy(&eb, &w0.w, 4);
+#endif
+  const float sx = pow2_from_byte(eb & 0xffu) * r.ix;
+  const float sy = pow2_from_byte((eb >> 8) & 0xffu) * r.iy;
+  const float sz = pow2_from_byte((eb >> 16) & 0xffu) * r.iz;
+  const float bx = fmaf(w0.x, r.ix, -r.oix);
+  const float by = fmaf(w0.y, r.iy, -r.oiy);
+  const float bz = fmaf(w0.z, r.iz, -r.oiz);
+  const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
+  uint32_t mask = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float lx = fmaf(byte_f(w1.x, j), sx, bx), hx = fmaf(byte_f(w1.y, j), sx, bx);
+    const float ly = fmaf(byte_f(w1.z, j), sy, by), hy = fmaf(byte_f(w1.w, j), sy, by);
+    const float lz = fmaf(byte_f(w2.x, j), sz, bz), hz = fmaf(byte_f(w2.y, j), sz, bz);
+    const float a = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), 0.0f));
+    const float f = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fminf(fmaxf(lz, hz), tmax));
+    tn[j] = a;
+    if (a <= f * kSlabSlack && ref[j] != kEmpty) mask |= 1u << j;
+  }
+  return mask;
 }
 
 RR_HD void node_boxes(const float4& n0, const float4& n1, const float4& n2, const RayBox& r,

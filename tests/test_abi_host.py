@@ -52,9 +52,10 @@ def test_workspace_query_and_validation(R):
     p = W.urban_block().params
     n = R.rr_workspace_query(p)
     # two queues of N_p * 2^(B-1) rays of 52 bytes, one 8-byte hit per ray
-    # of a level, and the accumulator
+    # of a level, the accumulator, and the traversal-stack spill area
+    # (64 entries x 256 CUs x 32 waves x 64 lanes)
     cap = 400 * 1024 * 8
-    want = 2 * cap * 52 + cap * 8 + 400 * 3776 * 8
+    want = 2 * cap * 52 + cap * 8 + 400 * 3776 * 8 + 4 * 64 * 256 * 32 * 64
     assert want <= n < want + (1 << 20)
     for bad in [dict(p, max_bounces=9), dict(p, n_azimuth=0), dict(p, beam_prob=0.0),
                 dict(p, beam_width_rad=4.0), dict(p, rays_per_beam=(1 << 20) + 1),
@@ -96,7 +97,7 @@ def test_host_bvh_matches_brute_force(R, name):
         n = 100
     sc = R.Scene(None, s.vertices, s.indices, s.tri_material)
     info = sc.info()
-    assert info["max_depth"] < 32
+    assert info["max_stack"] <= 96
     assert info["n_tris"] == s.n_tris
     if name == "degenerate_only":
         assert info["n_hittable"] == 0
@@ -127,6 +128,6 @@ def test_deep_median_fallback_bounds_depth(R):
     V[2::3, 2] = 0.5
     F = np.arange(3 * n, dtype=np.uint32).reshape(n, 3)
     sc = R.Scene(None, V, F, np.zeros(n, np.uint16), max_leaf_size=1)
-    assert sc.info()["max_depth"] < 32
+    assert sc.info()["max_stack"] <= 96
     assert sc.selfcheck(3000, 11) == 0
     sc.release()
