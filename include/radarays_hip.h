@@ -240,7 +240,8 @@ rr_status rr_batch_workspace_query(const rr_scan_desc* scans, uint32_t n_scans, 
 typedef struct {
   uint32_t refill_lanes;   /* a wave takes new rays once this many lanes are idle (1..64) */
   uint32_t trace_waves_per_cu; /* persistent trace waves per compute unit (1..32) */
-  uint32_t reserved[6];
+  uint32_t pool_rays;      /* rays a trace wave claims per atomic (64..4096) */
+  uint32_t reserved[5];
 } rr_tuning;
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t);

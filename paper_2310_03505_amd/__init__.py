@@ -71,7 +71,7 @@ RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
 
 class rr_tuning(C.Structure):
     _fields_ = [("refill_lanes", C.c_uint32), ("trace_waves_per_cu", C.c_uint32),
-                ("reserved", C.c_uint32 * 6)]
+                ("pool_rays", C.c_uint32), ("reserved", C.c_uint32 * 5)]
 
 
 class rr_scan_desc(C.Structure):
@@ -313,15 +313,16 @@ def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, 
     return images, (_stats_dict(st) if st is not None else None)
 
 
-def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0):
-    t = rr_tuning(refill_lanes, trace_waves_per_cu)
+def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0, pool_rays: int = 0):
+    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays)
     _check(load_library().rr_set_tuning(ctx, C.byref(t)), ctx)
 
 
 def rr_get_tuning(ctx) -> dict:
     t = rr_tuning()
     _check(load_library().rr_get_tuning(ctx, C.byref(t)), ctx)
-    return dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu))
+    return dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
+                pool_rays=int(t.pool_rays))
 
 
 def rr_profile_enable(ctx, flags: int):

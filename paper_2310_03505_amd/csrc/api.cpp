@@ -40,8 +40,9 @@ struct rr_context {
   std::vector<EvPair> ev_used;
   unsigned long long* d_prof = nullptr;
   // tuning
-  uint32_t refill_lanes = 48;
+  uint32_t refill_lanes = 16;
   uint32_t trace_waves_per_cu = 20;
+  uint32_t pool_rays = 64;
 };
 
 struct rr_scene {
@@ -301,6 +302,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     return fail(ctx, RR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
   if (L.cap >= (1ull << 31) || L.n_first >= (1ull << 31))
     return fail(ctx, RR_ENOMEM, "ray queues exceed 2^31 entries");
+  if (L.acc_cells >= 0xffffffffull) return fail(ctx, RR_ENOMEM, "image cells exceed 2^32 - 1");
   uint64_t pb = 0, ab = 0;
   uint32_t max_cells = 0;
   for (size_t i = 0; i < scans.size(); ++i) {
@@ -318,7 +320,10 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   auto* d_acc = reinterpret_cast<unsigned long long*>(ws + L.off_acc);
   HIP_TRY(ctx, put_blob(d_scans, scans.data(), sizeof(DevScan) * scans.size(), st));
   HIP_TRY(ctx, put_blob(d_mats, dm.data(), sizeof(DevMaterial) * dm.size(), st));
-  HIP_TRY(ctx, launch_clear(d_acc, (size_t)L.acc_cells, d_ctr, st));
+  bool masked = false;
+  for (const DevScan& q : scans) masked = masked || q.mask != nullptr;
+  // without masks every primary has a fixed queue slot and level 0 is full
+  HIP_TRY(ctx, launch_clear(d_acc, (size_t)L.acc_cells, d_ctr, masked ? 0u : (uint32_t)L.n_first, st));
   for (size_t i = 0; i < scans.size(); ++i)
     if (scans[i].records)
       HIP_TRY(ctx, launch_fill_i32(scans[i].records,
@@ -326,6 +331,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   LevelArgs a{};
   a.nodes = sc->d_nodes;
   a.n_nodes = (uint32_t)sc->bvh.nodes.size();
+  a.n_leaf_tris = (uint32_t)sc->bvh.aux.size();
   a.tris = sc->d_tris;
   a.aux = sc->d_aux;
   a.scans = d_scans;
@@ -335,6 +341,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   a.acc = d_acc;
   a.hits = reinterpret_cast<uint2*>(ws + L.off_hits);
   a.n_first = (uint32_t)L.n_first;
+  a.masked = masked ? 1u : 0u;
   a.counters = d_ctr;
   a.prof = (ctx->prof_flags & RR_PROFILE_COUNT) ? ctx->d_prof : nullptr;
   const bool timed = (ctx->prof_flags & RR_PROFILE_TIME) != 0;
@@ -342,6 +349,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   uint32_t trace_grid = std::max(1u, (uint32_t)ctx->n_cu * ctx->trace_waves_per_cu / (kTraceBlock / 64u));
   trace_grid = std::min(trace_grid, kSpillLanes / (uint32_t)kTraceBlock);
   a.refill = ctx->refill_lanes;
+  a.pool = ctx->pool_rays;
   a.spill = reinterpret_cast<int32_t*>(ws + L.off_spill);
   const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
   auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
@@ -384,7 +392,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     uint32_t tgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
     if ((rs = timed_launch(1, d, [&] { return launch_trace(a, tgrid, st); }))) return rs;
     uint64_t sblocks = (level_bound + kBlock - 1) / kBlock;
-    uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), flat_cap);
+    uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), (uint64_t)ctx->n_cu * 4u);
     if ((rs = timed_launch(2, d, [&] { return launch_shade(a, sgrid, st); }))) return rs;
     level_bound = std::min<uint64_t>(level_bound * 2, L.cap);
   }
@@ -539,6 +547,8 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
   } catch (const std::bad_alloc&) {
     return fail(ctx, RR_ENOMEM, "host memory for the BVH");
   }
+  if (sc->bvh.n_hittable >= kMaxLeafTris)
+    return fail(ctx, RR_EINVAL, "scene has %u triangles, more than 2^27", sc->bvh.n_hittable);
   if (sc->bvh.max_stack > (uint32_t)(kStack + kSpill))
     return fail(ctx, RR_EOVERFLOW, "BVH needs %u stack entries, more than %d", sc->bvh.max_stack,
                 kStack + kSpill);
@@ -706,12 +716,15 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   if (!ctx || !t) return fail(ctx, RR_EINVAL, "NULL argument");
-  uint32_t rl = t->refill_lanes ? t->refill_lanes : 48u;
+  uint32_t rl = t->refill_lanes ? t->refill_lanes : 16u;
   uint32_t wc = t->trace_waves_per_cu ? t->trace_waves_per_cu : 20u;
+  uint32_t pr = t->pool_rays ? t->pool_rays : 64u;
   if (rl > 64) return fail(ctx, RR_EINVAL, "refill_lanes out of [1, 64]");
   if (wc > 32) return fail(ctx, RR_EINVAL, "trace_waves_per_cu out of [1, 32]");
+  if (pr < 64 || pr > 4096) return fail(ctx, RR_EINVAL, "pool_rays out of [64, 4096]");
   ctx->refill_lanes = rl;
   ctx->trace_waves_per_cu = wc;
+  ctx->pool_rays = pr;
   return RR_OK;
 }
 
@@ -720,6 +733,7 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
   std::memset(out, 0, sizeof *out);
   out->refill_lanes = ctx->refill_lanes;
   out->trace_waves_per_cu = ctx->trace_waves_per_cu;
+  out->pool_rays = ctx->pool_rays;
   return RR_OK;
 }
 

@@ -212,7 +212,7 @@ struct Flattener4 {
     }
     out.n_leaves++;
     if (root_area > 0.0) out.sah_cost += b->box.area() / root_area * b->count;
-    *ref = ~(int32_t)start;
+    *ref = leaf_ref_encode(start, b->count);
     *count = b->count;
     return 0;
   }
@@ -256,9 +256,9 @@ struct Flattener4 {
     float origin[3];
     uint32_t eb[3];
     for (int a = 0; a < 3; ++a) quantise_axis(nlo[a], nhi[a], origin[a], eb[a]);
-    uint32_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0}, counts = 0;
+    uint32_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
     int32_t ref[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
-    uint32_t need_max = 0, n_inner = 0;
+    uint32_t need_max = 0, n_kids = 0;
     for (size_t j = 0; j < kids.size(); ++j) {
       const BNode* k = kids[j];
       for (int a = 0; a < 3; ++a) {
@@ -273,11 +273,11 @@ struct Flattener4 {
       if (k->leaf()) {
         uint32_t cnt;
         leaf_ref(k, &ref[j], &cnt);
-        counts |= cnt << (8 * j);
+        if (cnt) ++n_kids;
       } else {
         uint32_t need = emit(k, depth + 1, &ref[j]);
         need_max = std::max(need_max, need);
-        ++n_inner;
+        ++n_kids;
       }
     }
     Node4 nd{};
@@ -286,11 +286,13 @@ struct Flattener4 {
     std::memcpy(&ebf, &ebits, 4);
     nd.w0 = float4{origin[0], origin[1], origin[2], ebf};
     nd.w1 = uint4{qlo[0], qhi[0], qlo[1], qhi[1]};
-    nd.w2 = uint4{qlo[2], qhi[2], counts, 0u};
+    nd.w2 = uint4{qlo[2], qhi[2], 0u, 0u};
     nd.w3 = int4{ref[0], ref[1], ref[2], ref[3]};
     out.nodes[idx] = nd;
     *ref_out = (int32_t)idx;
-    return (n_inner ? n_inner - 1 : 0) + need_max;
+    // every hit child but the nearest is pushed (leaves too); the deepest
+    // inner child adds its own need on top
+    return (n_kids ? n_kids - 1 : 0) + need_max;
   }
 };
 
@@ -425,6 +427,15 @@ int32_t host_traverse(const BuiltBvh& b, const float o[3], const float d[3], flo
   int sp = 0;
   int32_t cur = 0;
   for (;;) {
+    if (cur == kEmpty) {
+      if (sp == 0) break;
+      cur = stack[--sp];
+    }
+    if (cur < 0) {  // a leaf
+      leaf_test(b, leaf_start(cur), leaf_count(cur), o, d, excl, best_t, best, best_orig);
+      cur = kEmpty;
+      continue;
+    }
     const Node4& nd = b.nodes[(size_t)cur];
     float tn[4];
     uint32_t mask = node4_boxes(nd.w0, nd.w1, nd.w2, nd.w3, rb, best_t, tn);
@@ -432,36 +443,23 @@ int32_t host_traverse(const BuiltBvh& b, const float o[3], const float d[3], flo
     float key[4];
     int32_t val[4];
     for (int j = 0; j < 4; ++j) {
-      key[j] = INFINITY;
-      val[j] = -1;
-      if (!((mask >> j) & 1u)) continue;
-      if (ref[j] < 0) {
-        leaf_test(b, (uint32_t)~ref[j], (nd.w2.z >> (8 * j)) & 0xffu, o, d, excl, best_t, best,
-                  best_orig);
-      } else {
-        key[j] = tn[j];
-        val[j] = ref[j];
-      }
+      bool h = (mask >> j) & 1u;
+      key[j] = h ? tn[j] : INFINITY;
+      val[j] = h ? ref[j] : kEmpty;
     }
-    // sort the inner children by entry distance (5 compare-exchanges)
+    // near to far (5 compare-exchanges); misses sink to the end
     const int pairs[5][2] = {{0, 1}, {2, 3}, {0, 2}, {1, 3}, {1, 2}};
     for (auto& pr : pairs)
       if (key[pr[1]] < key[pr[0]]) {
         std::swap(key[pr[0]], key[pr[1]]);
         std::swap(val[pr[0]], val[pr[1]]);
       }
-    int n = 0;
-    while (n < 4 && val[n] >= 0) ++n;
-    if (n > 0) {
-      for (int j = n - 1; j >= 1; --j) {
-        if (sp >= kStack + kSpill) return -2;  // exceeds the bound computed at build time
-        stack[sp++] = val[j];
-      }
-      cur = val[0];
-    } else {
-      if (sp == 0) break;
-      cur = stack[--sp];
+    for (int j = 3; j >= 1; --j) {
+      if (val[j] == kEmpty) continue;
+      if (sp >= kStack + kSpill) return -2;  // exceeds the bound computed at build time
+      stack[sp++] = val[j];
     }
+    cur = val[0];
   }
   if (t_out) *t_out = best_t;
   return best;

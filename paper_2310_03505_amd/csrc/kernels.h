@@ -17,7 +17,8 @@ struct QueueView {
 // Arguments shared by the per-level kernels.
 struct LevelArgs {
   const Node4* nodes;
-  uint32_t n_nodes;  // inner nodes (bounds the traversal loop)
+  uint32_t n_nodes;  // inner nodes (with n_leaf_tris, bounds the traversal loop)
+  uint32_t n_leaf_tris;
   uint32_t depth;
   const float4* tris;
   const float4* aux;
@@ -29,7 +30,9 @@ struct LevelArgs {
   QueueView in, out;  // rays of this level / children appended for the next
   uint2* hits;        // per ray of this level: (t bits, leaf index or -1)
   uint32_t n_first;   // primaries of every scan (raygen work items)
+  uint32_t masked;    // some scan has a primary mask: raygen compacts with atomics
   uint32_t refill;    // trace: refill a wave once this many lanes are idle
+  uint32_t pool;      // trace: rays a wave claims per atomic
   int32_t* spill;     // trace: stack entries beyond kStack, kSpill per lane (lane-major)
   uint32_t* counters;
   unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)
@@ -40,7 +43,8 @@ struct LevelArgs {
 // return.
 hipError_t put_blob(void* dst_dev, const void* src, size_t bytes, hipStream_t st);
 
-hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, hipStream_t st);
+hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t count0,
+                        hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st);

@@ -21,6 +21,10 @@
 
 namespace rr {
 
+constexpr uint32_t kHashBits = 11;     // shade: LDS table of 2048 accumulator cells
+constexpr uint32_t kHashSlots = 1u << kHashBits;
+constexpr uint32_t kHashEmpty = 0xffffffffu;
+
 // ---------------------------------------------------------------- Philox
 // Philox4x64-10, Salmon et al., "Parallel random numbers: as easy as 1, 2, 3"
 // (SC'11).
@@ -116,25 +120,38 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const uint32_t spill_stride = gridDim.x * blockDim.x;
 
   bool valid = false, exhausted = false;
+  uint32_t pool_next = 0, pool_end = 0;  // wave-uniform: claimed, not yet started rays
   uint32_t ridx = 0, visits = 0, best_orig = 0;
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0;
   RayBox rb{};
   int32_t best = -1, excl = -1, cur = 0;
   int sp = 0;
+  uint32_t tri_i = 0, tri_n = 0;
   uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0;
 
   for (;;) {
-    // ---- refill idle lanes (wave-uniform decision)
-    const uint64_t idle = __ballot(!valid);
+    // ---- refill idle lanes (wave-uniform decision) from the wave's pool of
+    // claimed rays; the pool is refilled A.pool rays at a time with one atomic
+    uint64_t idle = __ballot(!valid);
     if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
-      const uint32_t n = (uint32_t)__popcll(idle);
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(cursor, n);
-      base = __shfl(base, 0);
-      if (base + n >= n_in) exhausted = true;
-      if (!valid) {
-        const uint32_t my = base + (uint32_t)__popcll(idle & lanes_below);
-        if (my < n_in) {
+#pragma unroll 1
+      for (int pass = 0; pass < 2 && idle; ++pass) {
+        if (pool_next >= pool_end) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(cursor, A.pool);
+          base = __shfl(base, 0);
+          pool_next = base;
+          pool_end = min(base + A.pool, n_in);
+          if (base >= n_in) {
+            exhausted = true;
+            break;
+          }
+        }
+        const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
+        const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+        const bool mine = !valid && rank < take;
+        if (mine) {
+          const uint32_t my = pool_next + rank;
           const float4 a = A.in.a[my];
           const float4 b = A.in.b[my];
           const uint32_t m = A.in.m[my];
@@ -154,59 +171,76 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           best_orig = 0xffffffffu;
           cur = 0;
           sp = 0;
+          tri_n = 0;
           visits = 0;
           valid = true;
           if (kCount) ++cnt_rays;
         }
+        pool_next += take;
+        idle = __ballot(!valid);
+        if (pool_next >= pool_end && pool_end >= n_in) exhausted = true;
       }
     }
     if (__ballot(valid) == 0ull) break;  // only once the level is exhausted
 
-    // ---- one inner node per valid lane
+    // ---- one unit of work per valid lane: a node visit or a triangle test
     if (valid) {
-      const float4* np = reinterpret_cast<const float4*>(nodes + cur);
-      const float4 w0 = np[0];
-      const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
-      const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
-      const int4 w3 = reinterpret_cast<const int4*>(np)[3];
-      if (kCount) ++cnt_nodes;
-      float tn[4];
-      uint32_t mask = node4_boxes(w0, w1, w2, w3, rb, best_t, tn);
-      const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
-      float key[4];
-      int32_t val[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        key[j] = INFINITY;
-        val[j] = -1;
-        if ((mask >> j) & 1u) {
-          if (ref[j] < 0) {
-            const uint32_t start = (uint32_t)~ref[j], cnt = (w2.z >> (8 * j)) & 0xffu;
-            for (uint32_t q = 0; q < cnt; ++q) {
-              const uint32_t li = start + q;
-              if ((int32_t)li == excl) continue;
-              if (kCount) ++cnt_tris;
-              const float4 ta = tris[3 * li + 0];
-              const float4 e1 = tris[3 * li + 1];
-              const float4 e2 = tris[3 * li + 2];
-              float t;
-              if (!ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y,
-                           e2.z, best_t, t))
-                continue;
-              const uint32_t orig = __float_as_uint(ta.w);
-              if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
-                best_t = t;
-                best = (int32_t)li;
-                best_orig = orig;
-              }
-            }
+      bool done = false;
+      if (tri_n == 0) {
+        if (cur == kEmpty) {
+          if (sp > 0) {
+            --sp;
+            cur = sp < kStack ? stk[sp * kTraceBlock]
+                              : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
           } else {
-            key[j] = tn[j];
-            val[j] = ref[j];
+            done = true;
           }
         }
+        if (cur < 0) {  // a leaf: its triangles are tested one per iteration
+          tri_i = leaf_start(cur);
+          tri_n = leaf_count(cur);
+          cur = kEmpty;
+        }
       }
-      // inner children near to far: 5 compare-exchanges
+      if (tri_n > 0) {
+        const uint32_t li = tri_i;
+        ++tri_i;
+        --tri_n;
+        if ((int32_t)li != excl) {
+          if (kCount) ++cnt_tris;
+          const float4 ta = tris[3 * li + 0];
+          const float4 e1 = tris[3 * li + 1];
+          const float4 e2 = tris[3 * li + 2];
+          float t;
+          if (ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
+                      best_t, t)) {
+            const uint32_t orig = __float_as_uint(ta.w);
+            if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
+              best_t = t;
+              best = (int32_t)li;
+              best_orig = orig;
+            }
+          }
+        }
+      } else if (!done) {
+        const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+        const float4 w0 = np[0];
+        const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
+        const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
+        const int4 w3 = reinterpret_cast<const int4*>(np)[3];
+        if (kCount) ++cnt_nodes;
+        float tn[4];
+        const uint32_t mask = node4_boxes(w0, w1, w2, w3, rb, best_t, tn);
+        const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
+        float key[4];
+        int32_t val[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool h = (mask >> j) & 1u;
+          key[j] = h ? tn[j] : INFINITY;
+          val[j] = h ? ref[j] : kEmpty;
+        }
+        // hit children (leaves and inner nodes) near to far: 5 compare-exchanges
 #define RR_CX(i, j)                     \
   if (key[j] < key[i]) {                \
     const float tk = key[i];            \
@@ -216,15 +250,13 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
     val[i] = val[j];                    \
     val[j] = tv;                        \
   }
-      RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
+        RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
 #undef RR_CX
-      bool done = false;
-      if (val[0] >= 0) {
-        // push the farther hit children, nearest of them last; the builder
-        // bounds the worst-case depth by kStack + kSpill
+        // push the farther ones, nearest of them last; the builder bounds the
+        // worst-case depth by kStack + kSpill
 #pragma unroll
         for (int j = 3; j >= 1; --j) {
-          if (val[j] >= 0 && sp < kStack + kSpill) {
+          if (val[j] != kEmpty && sp < kStack + kSpill) {
             if (sp < kStack)
               stk[sp * kTraceBlock] = val[j];
             else
@@ -233,15 +265,10 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           }
         }
         cur = val[0];
-      } else if (sp > 0) {
-        --sp;
-        cur = sp < kStack ? stk[sp * kTraceBlock] : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
-      } else {
-        done = true;
       }
-      // every inner node is entered at most once per ray; the bound only
+      // every node and leaf is entered at most once per ray; the bound only
       // guards against a malformed tree
-      if (++visits > A.n_nodes) done = true;
+      if (++visits > A.n_nodes + A.n_leaf_tris) done = true;
       if (done) {
         A.hits[ridx] = make_uint2(__float_as_uint(best_t), (uint32_t)best);
         valid = false;
@@ -314,8 +341,11 @@ __global__ void __launch_bounds__(kBlock) k_raygen(LevelArgs A) {
         E = (double)s.e0;
       }
     }
-    uint64_t mask;
-    const uint32_t slot = wave_append(active, A.counters + kCtrCount, lane, lanes_below, mask);
+    uint32_t slot = gp;  // no mask: primary gp sits at slot gp (count preset)
+    if (A.masked) {
+      uint64_t mask;
+      slot = wave_append(active, A.counters + kCtrCount, lane, lanes_below, mask);
+    }
     if (active && slot < A.cap)
       put_ray(A.out, slot, ox, oy, oz, 0.0f, dx, dy, dz, g, E, pid, 0xffffffffu,
               (scan << 16) | (kAir << 8) | 1u);
@@ -329,15 +359,30 @@ __global__ void __launch_bounds__(kBlock) k_raygen(LevelArgs A) {
 // BRDF, range binning (Sec. III-B) and the two children.
 template <bool kCount>
 __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
+  // returns of the block's rays are summed in an LDS hash table keyed by
+  // accumulator cell and flushed with one global atomic per cell at the end;
+  // the block works on a contiguous range of the level, whose rays mostly
+  // share azimuths and so few cells
+  __shared__ uint32_t h_key[kHashSlots];
+  __shared__ unsigned long long h_val[kHashSlots];
+  __shared__ uint32_t s_cnt[kBlock / 64][2];
+  __shared__ uint32_t s_base;
   const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = threadIdx.x >> 6;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
+  for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
+    h_key[i] = kHashEmpty;
+    h_val[i] = 0ull;
+  }
+  __syncthreads();
+  const uint32_t per_block = ((n_in + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+  const uint32_t begin = min(blockIdx.x * per_block, n_in);
+  const uint32_t end = min(begin + per_block, n_in);
   uint32_t cnt_hits = 0;
-  for (uint32_t base = wave * 64u; base < n_in; base += n_waves * 64u) {
-    const uint32_t idx = base + lane;
-    const bool active = idx < n_in;
+  for (uint32_t base = begin; base < end; base += kBlock) {
+    const uint32_t idx = base + threadIdx.x;
+    const bool active = idx < end;
     bool has_r = false, has_t = false;
     float rdx = 0, rdy = 0, rdz = 0, tdx = 0, tdy = 0, tdz = 0;
     float rox = 0, roy = 0, roz = 0, tox = 0, toy = 0, toz = 0;
@@ -345,6 +390,9 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
     float range = 0.0f, g = 1.0f;
     uint32_t pid = 0, heap = 1, medium = kAir, scan = 0, t_medium = kAir;
     int32_t hit = -1;
+    bool has_q = false;            // a return to bin
+    unsigned long long qv = 0;     // its fixed-point energy
+    uint32_t cell = 0;             // its accumulator cell
     if (active) {
       const uint2 h = A.hits[idx];
       const uint32_t m = A.in.m[idx];
@@ -437,10 +485,11 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
         const float q = range / S->bin_size;
         if (q < (float)S->n_bins) {
           const uint32_t bin = (uint32_t)q;
-          const unsigned long long qv = __double2ull_rn(e_ret * (double)g * kFixedScale);
+          qv = __double2ull_rn(e_ret * (double)g * kFixedScale);
           if (qv) {
             const uint32_t k = pid / S->n_s;
-            atomicAdd(A.acc + S->acc_base + (size_t)k * S->n_bins + bin, qv);
+            cell = (uint32_t)(S->acc_base + (uint64_t)k * S->n_bins + bin);
+            has_q = true;
           }
         }
         if (A.depth + 1 < S->max_b) {
@@ -463,33 +512,62 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
         }
       }
     }
-    // ---- children: one atomic per wave for both kinds
+    // ---- return into the block's table (global atomic if its probe fails)
+    if (has_q) {
+      uint32_t h = (cell * 2654435761u) >> (32 - kHashBits);
+      bool done = false;
+#pragma unroll 1
+      for (int probe = 0; probe < 8 && !done; ++probe) {
+        const uint32_t prev = atomicCAS(&h_key[h], kHashEmpty, cell);
+        if (prev == kHashEmpty || prev == cell) {
+          atomicAdd(&h_val[h], qv);
+          done = true;
+        }
+        h = (h + 1u) & (kHashSlots - 1u);
+      }
+      if (!done) atomicAdd(A.acc + cell, qv);
+    }
+
+    // ---- children: one atomic per block iteration for both kinds
     const uint64_t mr = __ballot(has_r);
     const uint64_t mt = __ballot(has_t);
     const uint32_t nr = (uint32_t)__popcll(mr);
-    const uint32_t total = nr + (uint32_t)__popcll(mt);
-    if (total) {
-      uint32_t ob = 0;
-      if (lane == 0) ob = atomicAdd(A.counters + kCtrCount + A.depth + 1, total);
-      ob = __shfl(ob, 0);
-      if (has_r) {
-        const uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
-        if (slot < A.cap)
-          put_ray(A.out, slot, rox, roy, roz, range, rdx, rdy, rdz, g, e_refl, pid, (uint32_t)hit,
-                  (scan << 16) | (medium << 8) | (2u * heap));
-        else
-          atomicOr(A.counters + kCtrOverflow, 1u);
-      }
-      if (has_t) {
-        const uint32_t slot = ob + nr + (uint32_t)__popcll(mt & lanes_below);
-        if (slot < A.cap)
-          put_ray(A.out, slot, tox, toy, toz, range, tdx, tdy, tdz, g, e_refr, pid, (uint32_t)hit,
-                  (scan << 16) | (t_medium << 8) | (2u * heap + 1u));
-        else
-          atomicOr(A.counters + kCtrOverflow, 1u);
-      }
+    const uint32_t nt = (uint32_t)__popcll(mt);
+    if (lane == 0) {
+      s_cnt[wid][0] = nr;
+      s_cnt[wid][1] = nt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t total = 0;
+      for (uint32_t w = 0; w < kBlock / 64; ++w) total += s_cnt[w][0] + s_cnt[w][1];
+      s_base = total ? atomicAdd(A.counters + kCtrCount + A.depth + 1, total) : 0u;
+    }
+    __syncthreads();
+    uint32_t ob = s_base;
+    for (uint32_t w = 0; w < wid; ++w) ob += s_cnt[w][0] + s_cnt[w][1];
+    __syncthreads();  // s_cnt / s_base are rewritten by the next iteration
+    if (has_r) {
+      const uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
+      if (slot < A.cap)
+        put_ray(A.out, slot, rox, roy, roz, range, rdx, rdy, rdz, g, e_refl, pid, (uint32_t)hit,
+                (scan << 16) | (medium << 8) | (2u * heap));
+      else
+        atomicOr(A.counters + kCtrOverflow, 1u);
+    }
+    if (has_t) {
+      const uint32_t slot = ob + nr + (uint32_t)__popcll(mt & lanes_below);
+      if (slot < A.cap)
+        put_ray(A.out, slot, tox, toy, toz, range, tdx, tdy, tdz, g, e_refr, pid, (uint32_t)hit,
+                (scan << 16) | (t_medium << 8) | (2u * heap + 1u));
+      else
+        atomicOr(A.counters + kCtrOverflow, 1u);
     }
   }
+  // ---- flush the table
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock)
+    if (h_key[i] != kHashEmpty) atomicAdd(A.acc + h_key[i], h_val[i]);
   if (kCount) atomicAdd(A.prof + 3, (unsigned long long)cnt_hits);
 }
 
@@ -503,11 +581,11 @@ __global__ void k_put(uint32_t* dst, Blob b) {
   for (uint32_t i = threadIdx.x; i < b.n_words; i += blockDim.x) dst[i] = b.w[i];
 }
 
-__global__ void k_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters) {
+__global__ void k_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t count0) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t j = i; j < n_acc; j += stride) acc[j] = 0ull;
-  if (i < (size_t)kCtrWords) counters[i] = 0u;
+  if (i < (size_t)kCtrWords) counters[i] = (i == (size_t)kCtrCount) ? count0 : 0u;
 }
 
 __global__ void k_fill_i32(int32_t* p, size_t n, int32_t v) {
@@ -539,11 +617,12 @@ hipError_t put_blob(void* dst, const void* src, size_t bytes, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, hipStream_t st) {
+hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t count0,
+                        hipStream_t st) {
   size_t blocks = (n_acc + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, acc, n_acc, counters);
+  hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, acc, n_acc, counters, count0);
   return hipGetLastError();
 }
 

@@ -45,9 +45,9 @@ constexpr int kSpill = 64;     // further entries per lane in workspace memory
 // Four-wide node with quantised child boxes, 64 bytes (four 16-byte loads):
 //   w0 = (origin.x, origin.y, origin.z, exponent bytes ex | ey << 8 | ez << 16)
 //   w1 = (qlo.x[4], qhi.x[4], qlo.y[4], qhi.y[4])   one byte per child
-//   w2 = (qlo.z[4], qhi.z[4], leaf counts[4], 0)
-//   w3 = child refs: >= 0 inner node, kEmpty no child, otherwise a leaf whose
-//        triangles start at ~ref
+//   w2 = (qlo.z[4], qhi.z[4], 0, 0)
+//   w3 = child refs: inner node index (< 2^30), kEmpty for no child, or a
+//        leaf: bit 31 | (count - 1) << 27 | first leaf triangle (< 2^27)
 // Child j covers origin + q * 2^(e - 127) on each axis, rounded outward from
 // the padded float box, so decoding never shrinks a box.
 struct alignas(64) Node4 {
@@ -56,7 +56,13 @@ struct alignas(64) Node4 {
   int4 w3;
 };
 static_assert(sizeof(Node4) == 64, "node layout");
-constexpr int32_t kEmpty = (int32_t)0x80000000;
+constexpr int32_t kEmpty = 0x7fffffff;
+constexpr uint32_t kMaxLeafTris = 1u << 27;
+RR_HD int32_t leaf_ref_encode(uint32_t start, uint32_t count) {
+  return (int32_t)(0x80000000u | ((count - 1u) << 27) | start);
+}
+RR_HD uint32_t leaf_start(int32_t ref) { return (uint32_t)ref & (kMaxLeafTris - 1u); }
+RR_HD uint32_t leaf_count(int32_t ref) { return (((uint32_t)ref >> 27) & 15u) + 1u; }
 
 // Leaf-ordered triangle, 48 bytes: v0 with the original id in w, then the
 // edges e1 = v1 - v0 and e2 = v2 - v0 (float32, computed on the host).
