@@ -65,12 +65,69 @@ def cpu_baseline(scene, threads: int, n_cols: int):
                 scans_per_s=(segs / dt) / (segs / n_cols * naz))
 
 
+def bench_trajectory(args):
+    """64 poses along a spline through the 2M-triangle scene, each with its
+    own azimuth count and rays per beam (B = 5): one batched call against the
+    same 64 scans issued one rr_radar_scan at a time."""
+    import torch
+    import paper_2310_03505_amd as R
+    import workloads as W
+    scene = W.large_scene()
+    scans = W.spline_poses()
+    log(f"bench: trajectory, {len(scans)} scans on {scene.n_tris} tris")
+    ctx = R.Context(0)
+    sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+    c, s = ctx.handle, sc.handle
+    imgs = [torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+            for _, p in scans]
+    singles = [torch.empty_like(x) for x in imgs]
+    _, st = R.rr_radar_scan_batch(c, s, scans, scene.materials, images=imgs, stats=True)
+    segs = st["segments"]
+    steps = max(1, min(args.steps, 3))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        R.rr_radar_scan_batch(c, s, scans, scene.materials, images=imgs)
+    e1.record()
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / steps
+    for (pose, p), im in zip(scans, singles):           # warm the single-scan workspace
+        R.rr_radar_scan(c, s, pose, p, scene.materials, image=im)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        for (pose, p), im in zip(scans, singles):
+            R.rr_radar_scan(c, s, pose, p, scene.materials, image=im)
+    e1.record()
+    torch.cuda.synchronize()
+    single_ms = e0.elapsed_time(e1) / steps
+    same = all(torch.equal(a, b) for a, b in zip(imgs, singles))
+    out = {
+        "metric": "Mray-segments/s", "value": round(segs / (batch_ms / 1e3) / 1e6, 2),
+        "unit": "Mray-segments/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": round(batch_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "trajectory_64_poses_large_scene_2m", "n_tris": scene.n_tris,
+                   "n_scans": len(scans), "primaries": sum(p["n_azimuth"] * p["rays_per_beam"]
+                                                            for _, p in scans),
+                   "segments_per_step": segs, "scans_per_s": round(len(scans) / (batch_ms / 1e3), 2),
+                   "single_scan_ms_per_step": round(single_ms, 3),
+                   "single_scan_mseg_per_s": round(segs / (single_ms / 1e3) / 1e6, 2),
+                   "batch_speedup": round(single_ms / batch_ms, 3),
+                   "batch_images_equal_single": same},
+    }
+    sc.release()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large"])
+    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -95,6 +152,8 @@ def main():
     import paper_2310_03505_amd as R
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.workload == "trajectory":
+        return bench_trajectory(args)
     scene, wname = workload(args.workload)
     p = scene.params
     log(f"bench: {wname}, {scene.n_tris} tris, {p['n_azimuth']}x{p['rays_per_beam']}, "

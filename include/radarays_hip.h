@@ -223,10 +223,13 @@ rr_status rr_radar_scan_records(rr_context* ctx, const rr_scene* scene, const rr
                                 rr_scan_stats* stats, void* stream);
 
 /* Many scans (poses, azimuth counts, rays per beam and bounce limits may all
- * differ; the beam width must be shared) traced together: one ray-generation launch, one persistent
- * bounce launch per depth over the rays of every scan, one finalize.  Each
- * image equals what rr_radar_scan gives for that scan, bit for bit.
- * stats (optional) sums over the batch. */
+ * differ; the beam width must be shared) traced together: per group of
+ * scans one ray-generation launch, one trace and one shade launch per bounce
+ * level over the rays of every scan of the group, one finalize.  Groups are
+ * consecutive scans whose workspace fits the context's batch budget
+ * (rr_tuning.batch_budget_mb, default 24 GiB).  Each image equals what
+ * rr_radar_scan gives for that scan, bit for bit.  stats (optional) sums
+ * over the batch. */
 rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* scene, const rr_scan_desc* scans,
                               uint32_t n_scans, const rr_material* materials,
                               uint32_t n_materials, rr_scan_stats* stats, void* stream);
@@ -241,7 +244,8 @@ typedef struct {
   uint32_t refill_lanes;   /* a wave takes new rays once this many lanes are idle (1..64) */
   uint32_t trace_waves_per_cu; /* persistent trace waves per compute unit (1..32) */
   uint32_t pool_rays;      /* rays a trace wave claims per atomic (64..4096) */
-  uint32_t reserved[5];
+  uint32_t batch_budget_mb; /* workspace budget of one batch group, MiB (>= 64) */
+  uint32_t reserved[4];
 } rr_tuning;
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t);

@@ -71,7 +71,8 @@ RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
 
 class rr_tuning(C.Structure):
     _fields_ = [("refill_lanes", C.c_uint32), ("trace_waves_per_cu", C.c_uint32),
-                ("pool_rays", C.c_uint32), ("reserved", C.c_uint32 * 5)]
+                ("pool_rays", C.c_uint32), ("batch_budget_mb", C.c_uint32),
+                ("reserved", C.c_uint32 * 4)]
 
 
 class rr_scan_desc(C.Structure):
@@ -313,8 +314,9 @@ def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, 
     return images, (_stats_dict(st) if st is not None else None)
 
 
-def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0, pool_rays: int = 0):
-    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays)
+def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0, pool_rays: int = 0,
+                  batch_budget_mb: int = 0):
+    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb)
     _check(load_library().rr_set_tuning(ctx, C.byref(t)), ctx)
 
 
@@ -322,7 +324,7 @@ def rr_get_tuning(ctx) -> dict:
     t = rr_tuning()
     _check(load_library().rr_get_tuning(ctx, C.byref(t)), ctx)
     return dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
-                pool_rays=int(t.pool_rays))
+                pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb))
 
 
 def rr_profile_enable(ctx, flags: int):

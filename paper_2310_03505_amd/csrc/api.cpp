@@ -43,6 +43,7 @@ struct rr_context {
   uint32_t refill_lanes = 16;
   uint32_t trace_waves_per_cu = 20;
   uint32_t pool_rays = 64;
+  size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group
 };
 
 struct rr_scene {
@@ -695,23 +696,60 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
   if (!descs || n == 0 || n > 65535) return fail(ctx, RR_EINVAL, "need 1..65535 scans");
   rr_status s;
   if ((s = check_scene(ctx, sc)) || (s = check_materials(ctx, mats, n_mats, sc))) return s;
-  std::vector<const rr_sensor_params*> ps(n);
-  std::vector<DevScan> scans(n);
   for (uint32_t i = 0; i < n; ++i) {
     if ((s = check_params(ctx, &descs[i].params)) || (s = check_pose(ctx, &descs[i].pose))) return s;
     if (!descs[i].image_dev) return fail(ctx, RR_EINVAL, "scan %u: image_dev is NULL", i);
     if (descs[i].params.beam_width_rad != descs[0].params.beam_width_rad)
       return fail(ctx, RR_EINVAL, "scans of a batch must share the beam width");
-    ps[i] = &descs[i].params;
-    make_scan(descs[i].pose, descs[i].params, scans[i]);
-    scans[i].image = descs[i].image_dev;
   }
   DeviceGuard g(ctx->device);
-  Layout L;
-  make_layout(ps.data(), n, L);
-  if ((s = ensure_ws(ctx, L.total))) return s;
-  return run(ctx, sc, scans, ps.data(), mats, n_mats, static_cast<char*>(ctx->ws), ctx->ws_bytes, stats,
-             static_cast<hipStream_t>(stream), nullptr, descs[0].params.beam_width_rad);
+  // consecutive groups whose workspace stays within the context's budget
+  // (a single scan larger than the budget forms a group of its own)
+  std::vector<std::pair<uint32_t, uint32_t>> groups;
+  for (uint32_t i = 0; i < n;) {
+    uint32_t j = i + 1;
+    std::vector<const rr_sensor_params*> ps{&descs[i].params};
+    while (j < n) {
+      ps.push_back(&descs[j].params);
+      Layout L;
+      make_layout(ps.data(), (uint32_t)ps.size(), L);
+      if (L.total > ctx->batch_budget) break;
+      ++j;
+    }
+    groups.emplace_back(i, j);
+    i = j;
+  }
+  size_t need = 0;
+  for (auto& gr : groups) {
+    std::vector<const rr_sensor_params*> ps;
+    for (uint32_t i = gr.first; i < gr.second; ++i) ps.push_back(&descs[i].params);
+    Layout L;
+    make_layout(ps.data(), (uint32_t)ps.size(), L);
+    need = std::max(need, L.total);
+  }
+  if ((s = ensure_ws(ctx, need))) return s;
+  rr_scan_stats total{};
+  for (auto& gr : groups) {
+    std::vector<const rr_sensor_params*> ps;
+    std::vector<DevScan> scans;
+    for (uint32_t i = gr.first; i < gr.second; ++i) {
+      ps.push_back(&descs[i].params);
+      scans.emplace_back();
+      make_scan(descs[i].pose, descs[i].params, scans.back());
+      scans.back().image = descs[i].image_dev;
+    }
+    rr_scan_stats st{};
+    s = run(ctx, sc, scans, ps.data(), mats, n_mats, static_cast<char*>(ctx->ws), ctx->ws_bytes,
+            stats ? &st : nullptr, static_cast<hipStream_t>(stream), nullptr, descs[0].params.beam_width_rad);
+    if (s) return s;
+    if (stats) {
+      total.segments += st.segments;
+      for (uint32_t d = 0; d < RR_MAX_BOUNCES; ++d) total.rays_per_depth[d] += st.rays_per_depth[d];
+      total.overflow |= st.overflow;
+    }
+  }
+  if (stats) *stats = total;
+  return RR_OK;
 }
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
@@ -722,6 +760,8 @@ rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   if (rl > 64) return fail(ctx, RR_EINVAL, "refill_lanes out of [1, 64]");
   if (wc > 32) return fail(ctx, RR_EINVAL, "trace_waves_per_cu out of [1, 32]");
   if (pr < 64 || pr > 4096) return fail(ctx, RR_EINVAL, "pool_rays out of [64, 4096]");
+  if (t->batch_budget_mb && t->batch_budget_mb < 64) return fail(ctx, RR_EINVAL, "batch_budget_mb below 64");
+  ctx->batch_budget = t->batch_budget_mb ? (size_t)t->batch_budget_mb << 20 : (size_t)24 << 30;
   ctx->refill_lanes = rl;
   ctx->trace_waves_per_cu = wc;
   ctx->pool_rays = pr;
@@ -734,6 +774,7 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
   out->refill_lanes = ctx->refill_lanes;
   out->trace_waves_per_cu = ctx->trace_waves_per_cu;
   out->pool_rays = ctx->pool_rays;
+  out->batch_budget_mb = (uint32_t)(ctx->batch_budget >> 20);
   return RR_OK;
 }
 
