@@ -122,12 +122,77 @@ def bench_trajectory(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Replays the seeded Poisson stream (200 requests/s from 32 robots,
+    random poses, 100..800 azimuths, 256..4096 rays/beam, 2..5 bounces) into
+    the continuous-batching server on the resident 2M-triangle scene."""
+    import torch
+    import paper_2310_03505_amd as R
+    import workloads as W
+    scene = W.large_scene()
+    reqs = W.request_stream(duration_s=args.serve_seconds * args.serve_rate_scale)
+    for r in reqs:
+        r["t_arrival"] /= args.serve_rate_scale
+    log(f"bench: serve, {len(reqs)} requests over {args.serve_seconds} s "
+        f"(rate x{args.serve_rate_scale})")
+    ctx = R.Context(0)
+    sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+    c, s = ctx.handle, sc.handle
+    one = args.serve_one_per_launch
+    srv = R.rr_server_create(c, s, scene.materials, n_slots=1 if one else 2,
+                             max_batch_scans=1 if one else 256, memory_budget=48 << 30)
+    max_cells = max(r["params"]["n_azimuth"] * r["params"]["n_bins"] for r in reqs)
+    pool = torch.empty((len(reqs), max_cells), dtype=torch.float32, device="cuda")
+    # warm-up: a few requests, then reset the statistics
+    warm = [R.rr_server_submit(srv, r["pose"], r["params"], pool[i]) for i, r in enumerate(reqs[:8])]
+    for t in warm:
+        R.rr_server_wait(srv, t)
+    R.rr_server_reset_stats(srv)
+    t0 = time.perf_counter()
+    tickets = []
+    for i, r in enumerate(reqs):
+        delay = t0 + r["t_arrival"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(R.rr_server_submit(srv, r["pose"], r["params"], pool[i]))
+    for t in tickets:
+        R.rr_server_wait(srv, t)
+    st = R.rr_server_get_stats(srv)
+    R.rr_server_destroy(srv)
+    sc.release()
+    ctx.close()
+    out = {
+        "metric": "Mray-segments/s", "value": round(st["mseg_per_s"], 2), "unit": "Mray-segments/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 8,
+        "ms_per_step": round(st["wall_s"] * 1e3 / max(st["completed"], 1), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serve_poisson_200hz_large_scene_2m" + ("_one_per_launch" if one else ""),
+                   "requests": len(reqs), "stream_seconds": args.serve_seconds,
+                   "arrival_rate_hz": round(200.0 * args.serve_rate_scale, 1),
+                   "completed": st["completed"], "rejected": st["rejected"], "batches": st["batches"],
+                   "scans_per_s": round(st["scans_per_s"], 2),
+                   "latency_p50_ms": round(st["latency_p50_ms"], 2),
+                   "latency_p99_ms": round(st["latency_p99_ms"], 2),
+                   "latency_mean_ms": round(st["latency_mean_ms"], 2),
+                   "latency_max_ms": round(st["latency_max_ms"], 2), "wall_s": round(st["wall_s"], 3),
+                   "segments": st["segments"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory"])
+    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the replayed request stream (serve workload)")
+    ap.add_argument("--serve-rate-scale", type=float, default=1.0,
+                    help="compress the stream's arrival times by this factor (load x scale)")
+    ap.add_argument("--serve-one-per-launch", action="store_true",
+                    help="serve one request per launch on one stream (baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -154,6 +219,8 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.workload == "trajectory":
         return bench_trajectory(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     scene, wname = workload(args.workload)
     p = scene.params
     log(f"bench: {wname}, {scene.n_tris} tris, {p['n_azimuth']}x{p['rays_per_beam']}, "

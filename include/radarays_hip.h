@@ -237,6 +237,50 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* scene, const rr_s
 /* Workspace bytes rr_radar_scan_batch needs for these scans. */
 rr_status rr_batch_workspace_query(const rr_scan_desc* scans, uint32_t n_scans, size_t* bytes);
 
+/* ---------------------------------------------------------------- serving */
+/* A server owns a context and a resident scene and turns a stream of scan
+ * requests into batches (continuous batching).  Requests wait in arrival
+ * order; whenever one of the server's slots is free, the dispatcher admits
+ * the oldest waiting requests whose combined workspace fits the slot's
+ * memory budget (and that share the beam width of the first), and launches
+ * them as one batch on the slot's stream.  Slots run concurrently, so
+ * requests that arrive while others are on the GPU start as soon as a slot
+ * frees up.  Each image is bit-identical to a lone rr_radar_scan of the same
+ * request.  While a server exists, only the server may use its context. */
+typedef struct rr_server rr_server;
+
+typedef struct {
+  uint32_t n_slots;         /* batches in flight, one stream each (1..8, default 2) */
+  uint32_t max_batch_scans; /* requests per batch (1..65535, default 256) */
+  uint64_t memory_budget;   /* workspace bytes over all slots (default 32 GiB) */
+  uint32_t reserved[4];
+} rr_server_options;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, batches, segments;
+  double latency_p50_ms, latency_p99_ms, latency_mean_ms, latency_max_ms;
+  double wall_s;      /* first submission to last completion since the last reset */
+  double scans_per_s; /* completed / wall_s */
+  double mseg_per_s;  /* segments / wall_s / 1e6 */
+} rr_server_stats;
+
+/* The material table is copied; the scene must outlive the server. */
+rr_status rr_server_create(rr_context* ctx, const rr_scene* scene, const rr_material* materials,
+                           uint32_t n_materials, const rr_server_options* opt, rr_server** out);
+/* Thread-safe, non-blocking.  image_dev (n_azimuth x n_bins floats) is
+ * written when the request completes.  ENOMEM if the request alone exceeds
+ * a slot's budget (counted as rejected); EINVAL for invalid parameters. */
+rr_status rr_server_submit(rr_server* srv, const rr_pose* pose, const rr_sensor_params* params,
+                           float* image_dev, uint64_t* ticket);
+/* Blocks until the request is done; latency = completion - submission. */
+rr_status rr_server_wait(rr_server* srv, uint64_t ticket, double* latency_ms);
+/* Non-blocking: *done = 1 once finished (the ticket is then released). */
+rr_status rr_server_poll(rr_server* srv, uint64_t ticket, int* done, double* latency_ms);
+rr_status rr_server_get_stats(rr_server* srv, rr_server_stats* out);
+rr_status rr_server_reset_stats(rr_server* srv);
+/* Finishes every submitted request, then frees the server. */
+rr_status rr_server_destroy(rr_server* srv);
+
 /* ---------------------------------------------------------------- tuning */
 /* Launch parameters of the traversal kernel (all zero = defaults).  They
  * change speed only, never results. */

@@ -75,6 +75,19 @@ class rr_tuning(C.Structure):
                 ("reserved", C.c_uint32 * 4)]
 
 
+class rr_server_options(C.Structure):
+    _fields_ = [("n_slots", C.c_uint32), ("max_batch_scans", C.c_uint32),
+                ("memory_budget", C.c_uint64), ("reserved", C.c_uint32 * 4)]
+
+
+class rr_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("batches", C.c_uint64), ("segments", C.c_uint64),
+                ("latency_p50_ms", C.c_double), ("latency_p99_ms", C.c_double),
+                ("latency_mean_ms", C.c_double), ("latency_max_ms", C.c_double),
+                ("wall_s", C.c_double), ("scans_per_s", C.c_double), ("mseg_per_s", C.c_double)]
+
+
 class rr_scan_desc(C.Structure):
     _fields_ = [("pose", rr_pose), ("params", rr_sensor_params), ("image_dev", C.c_void_p)]
 
@@ -84,7 +97,8 @@ EXPORTS = (
     "rr_bvh_build", "rr_bvh_get_info", "rr_bvh_selfcheck", "rr_scene_release",
     "rr_workspace_query", "rr_radar_scan", "rr_radar_scan_ws", "rr_radar_scan_records",
     "rr_radar_scan_batch", "rr_batch_workspace_query", "rr_profile_enable", "rr_profile_read",
-    "rr_set_tuning", "rr_get_tuning",
+    "rr_set_tuning", "rr_get_tuning", "rr_server_create", "rr_server_submit", "rr_server_wait",
+    "rr_server_poll", "rr_server_get_stats", "rr_server_reset_stats", "rr_server_destroy",
 )
 
 _lib = None
@@ -126,6 +140,13 @@ def load_library():
         "rr_profile_read": (st, [vp, P(rr_profile)]),
         "rr_set_tuning": (st, [vp, P(rr_tuning)]),
         "rr_get_tuning": (st, [vp, P(rr_tuning)]),
+        "rr_server_create": (st, [vp, vp, P(rr_material), C.c_uint32, P(rr_server_options), P(vp)]),
+        "rr_server_submit": (st, [vp, P(rr_pose), P(rr_sensor_params), vp, P(C.c_uint64)]),
+        "rr_server_wait": (st, [vp, C.c_uint64, P(C.c_double)]),
+        "rr_server_poll": (st, [vp, C.c_uint64, P(C.c_int), P(C.c_double)]),
+        "rr_server_get_stats": (st, [vp, P(rr_server_stats)]),
+        "rr_server_reset_stats": (st, [vp]),
+        "rr_server_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -338,6 +359,49 @@ def rr_profile_read(ctx) -> dict:
                 trace_level_ms=[float(x) for x in p.trace_level_ms], shade_ms=float(p.shade_ms),
                 raygen_ms=float(p.raygen_ms), node_visits=int(p.node_visits),
                 tri_tests=int(p.tri_tests), rays=int(p.rays), hits=int(p.hits))
+
+
+def rr_server_create(ctx, scene, materials, n_slots: int = 0, max_batch_scans: int = 0,
+                     memory_budget: int = 0):
+    opt = rr_server_options(n_slots, max_batch_scans, memory_budget)
+    mats = make_materials(materials)
+    h = C.c_void_p()
+    _check(load_library().rr_server_create(ctx, scene, mats, len(materials), C.byref(opt),
+                                           C.byref(h)), ctx)
+    return h
+
+
+def rr_server_submit(srv, pose: dict, params: dict, image) -> int:
+    t = C.c_uint64()
+    pr, ps = make_pose(pose), make_params(params)
+    _check(load_library().rr_server_submit(srv, C.byref(pr), C.byref(ps), _ptr(image), C.byref(t)))
+    return int(t.value)
+
+
+def rr_server_wait(srv, ticket: int) -> float:
+    lat = C.c_double()
+    _check(load_library().rr_server_wait(srv, ticket, C.byref(lat)))
+    return float(lat.value)
+
+
+def rr_server_poll(srv, ticket: int):
+    done, lat = C.c_int(), C.c_double()
+    _check(load_library().rr_server_poll(srv, ticket, C.byref(done), C.byref(lat)))
+    return bool(done.value), float(lat.value)
+
+
+def rr_server_get_stats(srv) -> dict:
+    st = rr_server_stats()
+    _check(load_library().rr_server_get_stats(srv, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in rr_server_stats._fields_}
+
+
+def rr_server_reset_stats(srv):
+    _check(load_library().rr_server_reset_stats(srv))
+
+
+def rr_server_destroy(srv):
+    _check(load_library().rr_server_destroy(srv))
 
 
 # ------------------------------------------------------------------ convenience

@@ -22,46 +22,9 @@
 
 using namespace rr;
 
-struct rr_context {
-  int device = 0;
-  int n_cu = 256;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  uint32_t* h_ctr = nullptr;  // pinned, for stats
-  std::string err;
-  // profiling
-  uint32_t prof_flags = 0;
-  struct EvPair {
-    hipEvent_t a, b;
-    uint32_t depth;
-    int kind;  // 0 raygen, 1 trace, 2 shade
-  };
-  std::vector<hipEvent_t> ev_free;
-  std::vector<EvPair> ev_used;
-  unsigned long long* d_prof = nullptr;
-  // tuning
-  uint32_t refill_lanes = 16;
-  uint32_t trace_waves_per_cu = 20;
-  uint32_t pool_rays = 64;
-  size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group
-};
+#include "api_internal.h"
 
-struct rr_scene {
-  rr_context* ctx = nullptr;
-  std::vector<float> V;
-  std::vector<uint32_t> F;
-  std::vector<uint16_t> M;
-  uint32_t nv = 0, nt = 0;
-  uint32_t max_mat = 0;
-  bool built = false;
-  BuiltBvh bvh;
-  Node4* d_nodes = nullptr;
-  float4* d_tris = nullptr;
-  float4* d_aux = nullptr;
-  uint64_t dev_bytes = 0;
-};
-
-namespace {
+namespace rr {
 
 thread_local std::string g_err;
 
@@ -226,16 +189,6 @@ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // units x 32 waves x 64 lanes
 constexpr uint32_t kSpillLanes = 256u * 32u * 64u;
 
-struct Layout {
-  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0;
-  size_t off_q[2][4] = {};
-  size_t total = 0;
-  uint64_t cap = 0;       // rays per queue
-  uint64_t acc_cells = 0;
-  uint64_t n_first = 0;
-  uint32_t max_b = 0;
-};
-
 // Levels alternate between two queues; level d of a scan has at most
 // N_p * 2^d rays, and only scans with B > d have a level d.  The hit buffer
 // holds one (t, leaf) pair per ray of the current level.
@@ -296,7 +249,7 @@ rr_status check_scene(rr_context* ctx, const rr_scene* sc) {
 rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
-              float beam_width_for_mats) {
+              float beam_width_for_mats, uint32_t* counters_host) {
   Layout L;
   make_layout(ps, (uint32_t)scans.size(), L);
   if (ws_bytes < L.total)
@@ -400,6 +353,8 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   HIP_TRY(ctx, launch_finalize(d_scans, (uint32_t)scans.size(), d_acc, max_cells, st));
   if (accum_out)
     HIP_TRY(ctx, hipMemcpyAsync(accum_out, d_acc, 8 * L.acc_cells, hipMemcpyDeviceToDevice, st));
+  if (counters_host)
+    HIP_TRY(ctx, hipMemcpyAsync(counters_host, d_ctr, 4 * kCtrWords, hipMemcpyDeviceToHost, st));
   if (stats) {
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctr, d_ctr, 4 * kCtrWords, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -431,18 +386,8 @@ rr_status ensure_ws(rr_context* ctx, size_t bytes) {
   return RR_OK;
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
-}  // namespace
+}  // namespace rr
 
 // ====================================================================== ABI
 extern "C" {

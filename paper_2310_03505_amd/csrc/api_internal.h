@@ -1,0 +1,92 @@
+// api_internal.h -- library-private state shared by api.cpp and server.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/radarays_hip.h"
+#include "bvh.h"
+#include "kernels.h"
+#include "rr_internal.h"
+
+struct rr_context {
+  int device = 0;
+  int n_cu = 256;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t* h_ctr = nullptr;  // pinned, for stats
+  std::string err;
+  // profiling
+  uint32_t prof_flags = 0;
+  struct EvPair {
+    hipEvent_t a, b;
+    uint32_t depth;
+    int kind;  // 0 raygen, 1 trace, 2 shade
+  };
+  std::vector<hipEvent_t> ev_free;
+  std::vector<EvPair> ev_used;
+  unsigned long long* d_prof = nullptr;
+  // tuning
+  uint32_t refill_lanes = 16;
+  uint32_t trace_waves_per_cu = 20;
+  uint32_t pool_rays = 64;
+  size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group
+};
+
+struct rr_scene {
+  rr_context* ctx = nullptr;
+  std::vector<float> V;
+  std::vector<uint32_t> F;
+  std::vector<uint16_t> M;
+  uint32_t nv = 0, nt = 0;
+  uint32_t max_mat = 0;
+  bool built = false;
+  rr::BuiltBvh bvh;
+  rr::Node4* d_nodes = nullptr;
+  float4* d_tris = nullptr;
+  float4* d_aux = nullptr;
+  uint64_t dev_bytes = 0;
+};
+
+
+namespace rr {
+
+// Workspace layout of a set of scans (see api.cpp).
+struct Layout {
+  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0;
+  size_t off_q[2][4] = {};
+  size_t total = 0;
+  uint64_t cap = 0;       // rays per queue
+  uint64_t acc_cells = 0;
+  uint64_t n_first = 0;
+  uint32_t max_b = 0;
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L);
+void make_scan(const rr_pose& pose, const rr_sensor_params& p, DevScan& s);
+rr_status check_params(rr_context* ctx, const rr_sensor_params* p);
+rr_status check_pose(rr_context* ctx, const rr_pose* q);
+rr_status check_materials(rr_context* ctx, const rr_material* m, uint32_t n, const rr_scene* sc);
+rr_status check_scene(rr_context* ctx, const rr_scene* sc);
+rr_status fail(rr_context* ctx, rr_status s, const char* fmt, ...);
+// Enqueues the scans on `st` using workspace `ws`; when counters_host is
+// non-null the level counters are copied there (stream-ordered, no wait).
+rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
+              const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
+              size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
+              float beam_width_for_mats, uint32_t* counters_host = nullptr);
+
+}  // namespace rr

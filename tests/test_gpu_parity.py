@@ -258,3 +258,52 @@ def test_invalid_arguments_launch_nothing(R, ctx):
                             s.params, s.materials)
     finally:
         sc.release()
+
+
+# ---------------------------------------------------------------- serving
+def test_server_mix_equals_alone(R, ctx):
+    """Requests served in overlapping batches produce the same images, bit for
+    bit, as the same requests scanned alone; an oversize request is refused
+    by memory admission."""
+    import torch
+    s = W.tiny_room()
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(40):
+        p = dict(s.params, n_azimuth=int(rng.integers(20, 400)),
+                 rays_per_beam=int(rng.integers(4, 80)), max_bounces=int(rng.integers(1, 5)),
+                 scan_id=i)
+        pose = W.yaw_pose((rng.uniform(-1, 1), rng.uniform(-1, 1), 0.0), rng.uniform(-3, 3))
+        reqs.append((pose, p))
+    try:
+        alone = []
+        for pose, p in reqs:
+            im, _ = R.rr_radar_scan(ctx.handle, sc.handle, pose, p, s.materials)
+            alone.append(im)
+        torch.cuda.synchronize()
+        srv = R.rr_server_create(ctx.handle, sc.handle, s.materials, n_slots=2, max_batch_scans=8,
+                                 memory_budget=2 << 30)
+        try:
+            outs, tickets = [], []
+            for pose, p in reqs:
+                out = torch.full((p["n_azimuth"], p["n_bins"]), -1.0, device="cuda")
+                outs.append(out)
+                tickets.append(R.rr_server_submit(srv, pose, p, out))
+            lats = [R.rr_server_wait(srv, t) for t in tickets]
+            big = dict(s.params, n_azimuth=4000, rays_per_beam=4096, max_bounces=8)
+            with pytest.raises(R.RadarError) as e:
+                R.rr_server_submit(srv, s.pose, big, outs[0])
+            assert e.value.status == R.RR_ENOMEM
+            st = R.rr_server_get_stats(srv)
+        finally:
+            R.rr_server_destroy(srv)
+        torch.cuda.synchronize()
+        for a, b in zip(alone, outs):
+            assert torch.equal(a, b)
+        assert st["completed"] == 40 and st["rejected"] == 1
+        assert 1 <= st["batches"] <= 40
+        assert min(lats) > 0 and st["latency_p99_ms"] >= st["latency_p50_ms"] > 0
+        log(f"server: {st['batches']} batches for 40 requests, p50 {st['latency_p50_ms']:.2f} ms")
+    finally:
+        sc.release()
