@@ -289,11 +289,39 @@ typedef struct {
   uint32_t trace_waves_per_cu; /* persistent trace waves per compute unit (1..32) */
   uint32_t pool_rays;      /* rays a trace wave claims per atomic (64..4096) */
   uint32_t batch_budget_mb; /* workspace budget of one batch group, MiB (>= 64) */
-  uint32_t reserved[4];
+  uint32_t leaf_batch_lanes; /* 0: each lane visits a node or tests a triangle per
+                               step; n > 0: lanes park leaves and the wave tests
+                               triangles once n lanes hold one (1..64) */
+  uint32_t reserved[3];
 } rr_tuning;
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t);
 rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out);
+
+/* Autotuner: scans the given workload with candidate launch parameters
+ * (coordinate descent over refill_lanes, trace_waves_per_cu, pool_rays and
+ * leaf_batch_lanes, each candidate timed with HIP events over `reps` scans
+ * on `stream`), keeps the fastest in the context and returns it in *best
+ * with its time per scan.  Every candidate produces the same image. */
+rr_status rr_autotune(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
+                      const rr_sensor_params* params, const rr_material* materials,
+                      uint32_t n_materials, float* image_dev, uint32_t reps, rr_tuning* best,
+                      double* best_ms, void* stream);
+
+/* ---------------------------------------------------------------- graphs */
+/* A HIP graph holding the complete launch sequence of a batch of scans
+ * (clear, ray generation, trace and shade per level, finalize) with its own
+ * workspace.  rr_graph_launch uploads the per-scan constants (poses, seeds,
+ * scan ids and image pointers may change; azimuths, rays per beam, bounces,
+ * bins, bin size, beam width and flags must match the scans the graph was
+ * created with) and replays the graph on `stream`. */
+typedef struct rr_graph rr_graph;
+rr_status rr_graph_create(rr_context* ctx, const rr_scene* scene, const rr_scan_desc* scans,
+                          uint32_t n_scans, const rr_material* materials, uint32_t n_materials,
+                          rr_graph** out);
+/* scans may be NULL to replay the scans given at creation. */
+rr_status rr_graph_launch(rr_graph* g, const rr_scan_desc* scans, void* stream);
+rr_status rr_graph_destroy(rr_graph* g);
 
 /* ---------------------------------------------------------------- profiling */
 #define RR_PROFILE_TIME 1u  /* bracket every kernel launch of a scan with HIP events */

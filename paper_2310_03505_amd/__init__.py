@@ -72,7 +72,7 @@ RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
 class rr_tuning(C.Structure):
     _fields_ = [("refill_lanes", C.c_uint32), ("trace_waves_per_cu", C.c_uint32),
                 ("pool_rays", C.c_uint32), ("batch_budget_mb", C.c_uint32),
-                ("reserved", C.c_uint32 * 4)]
+                ("leaf_batch_lanes", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 class rr_server_options(C.Structure):
@@ -99,6 +99,7 @@ EXPORTS = (
     "rr_radar_scan_batch", "rr_batch_workspace_query", "rr_profile_enable", "rr_profile_read",
     "rr_set_tuning", "rr_get_tuning", "rr_server_create", "rr_server_submit", "rr_server_wait",
     "rr_server_poll", "rr_server_get_stats", "rr_server_reset_stats", "rr_server_destroy",
+    "rr_autotune", "rr_graph_create", "rr_graph_launch", "rr_graph_destroy",
 )
 
 _lib = None
@@ -147,6 +148,12 @@ def load_library():
         "rr_server_get_stats": (st, [vp, P(rr_server_stats)]),
         "rr_server_reset_stats": (st, [vp]),
         "rr_server_destroy": (st, [vp]),
+        "rr_autotune": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material), C.c_uint32,
+                             vp, C.c_uint32, P(rr_tuning), P(C.c_double), vp]),
+        "rr_graph_create": (st, [vp, vp, P(rr_scan_desc), C.c_uint32, P(rr_material), C.c_uint32,
+                                 P(vp)]),
+        "rr_graph_launch": (st, [vp, P(rr_scan_desc), vp]),
+        "rr_graph_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -336,8 +343,8 @@ def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, 
 
 
 def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0, pool_rays: int = 0,
-                  batch_budget_mb: int = 0):
-    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb)
+                  batch_budget_mb: int = 0, leaf_batch_lanes: int = 0):
+    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb, leaf_batch_lanes)
     _check(load_library().rr_set_tuning(ctx, C.byref(t)), ctx)
 
 
@@ -345,7 +352,57 @@ def rr_get_tuning(ctx) -> dict:
     t = rr_tuning()
     _check(load_library().rr_get_tuning(ctx, C.byref(t)), ctx)
     return dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
-                pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb))
+                pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb),
+                leaf_batch_lanes=int(t.leaf_batch_lanes))
+
+
+def rr_autotune(ctx, scene, pose: dict, params: dict, materials, image=None, reps: int = 5,
+                stream=None):
+    """Times candidate launch parameters on this scan and keeps the fastest.
+    Returns (tuning dict, ms per scan)."""
+    import torch
+    if image is None:
+        image = torch.empty((params["n_azimuth"], params["n_bins"]), dtype=torch.float32,
+                            device="cuda")
+    t = rr_tuning()
+    ms = C.c_double()
+    mats = make_materials(materials)
+    _check(load_library().rr_autotune(ctx, scene, C.byref(make_pose(pose)),
+                                      C.byref(make_params(params)), mats, len(materials),
+                                      _ptr(image), reps, C.byref(t), C.byref(ms),
+                                      _stream_handle(stream)), ctx)
+    return (dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
+                 pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb),
+                 leaf_batch_lanes=int(t.leaf_batch_lanes)), float(ms.value))
+
+
+def rr_graph_create(ctx, scene, scans, materials, images=None):
+    """Captures the launch sequence of these (pose, params) scans.  Returns
+    (graph handle, images); the images stay the graph's outputs until a
+    launch passes others."""
+    import torch
+    if images is None:
+        images = [torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+                  for _, p in scans]
+    descs = make_scan_descs(scans, images)
+    mats = make_materials(materials)
+    h = C.c_void_p()
+    _check(load_library().rr_graph_create(ctx, scene, descs, len(scans), mats, len(materials),
+                                          C.byref(h)), ctx)
+    return h, images
+
+
+def rr_graph_launch(graph, scans=None, images=None, stream=None):
+    """Replays the graph; with scans (and their images) the per-scan tables are
+    replaced first."""
+    if scans is not None and images is None:
+        raise ValueError("new scans need their output images")
+    descs = make_scan_descs(scans, images) if scans is not None else None
+    _check(load_library().rr_graph_launch(graph, descs, _stream_handle(stream)))
+
+
+def rr_graph_destroy(graph):
+    _check(load_library().rr_graph_destroy(graph))
 
 
 def rr_profile_enable(ctx, flags: int):

@@ -39,14 +39,6 @@ rr_status fail(rr_context* ctx, rr_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(ctx, expr)                                                                    \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
-    if (e_ != hipSuccess)                                                                     \
-      return fail(ctx, e_ == hipErrorOutOfMemory ? RR_ENOMEM : RR_EDEVICE, "%s: %s", #expr,   \
-                  hipGetErrorString(e_));                                                     \
-  } while (0)
-
 bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
 rr_status check_params(rr_context* ctx, const rr_sensor_params* p) {
@@ -249,7 +241,7 @@ rr_status check_scene(rr_context* ctx, const rr_scene* sc) {
 rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
-              float beam_width_for_mats, uint32_t* counters_host) {
+              float beam_width_for_mats, uint32_t* counters_host, bool upload) {
   Layout L;
   make_layout(ps, (uint32_t)scans.size(), L);
   if (ws_bytes < L.total)
@@ -257,23 +249,17 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   if (L.cap >= (1ull << 31) || L.n_first >= (1ull << 31))
     return fail(ctx, RR_ENOMEM, "ray queues exceed 2^31 entries");
   if (L.acc_cells >= 0xffffffffull) return fail(ctx, RR_ENOMEM, "image cells exceed 2^32 - 1");
-  uint64_t pb = 0, ab = 0;
   uint32_t max_cells = 0;
-  for (size_t i = 0; i < scans.size(); ++i) {
-    scans[i].prim_base = (uint32_t)pb;
-    scans[i].acc_base = ab;
-    pb += scans[i].n_prim;
-    ab += (uint64_t)scans[i].n_az * scans[i].n_bins;
+  for (size_t i = 0; i < scans.size(); ++i)
     max_cells = std::max<uint32_t>(max_cells, scans[i].n_az * scans[i].n_bins);
-  }
-  std::vector<DevMaterial> dm;
-  make_materials(mats, n_mats, beam_width_for_mats, dm);
   DevScan* d_scans = reinterpret_cast<DevScan*>(ws + L.off_scans);
   DevMaterial* d_mats = reinterpret_cast<DevMaterial*>(ws + L.off_mats);
   uint32_t* d_ctr = reinterpret_cast<uint32_t*>(ws + L.off_ctr);
   auto* d_acc = reinterpret_cast<unsigned long long*>(ws + L.off_acc);
-  HIP_TRY(ctx, put_blob(d_scans, scans.data(), sizeof(DevScan) * scans.size(), st));
-  HIP_TRY(ctx, put_blob(d_mats, dm.data(), sizeof(DevMaterial) * dm.size(), st));
+  if (upload) {
+    rr_status us = upload_tables(ctx, scans, ps, mats, n_mats, ws, st, beam_width_for_mats);
+    if (us) return us;
+  }
   bool masked = false;
   for (const DevScan& q : scans) masked = masked || q.mask != nullptr;
   // without masks every primary has a fixed queue slot and level 0 is full
@@ -304,6 +290,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   trace_grid = std::min(trace_grid, kSpillLanes / (uint32_t)kTraceBlock);
   a.refill = ctx->refill_lanes;
   a.pool = ctx->pool_rays;
+  a.leaf_batch = ctx->leaf_batch;
   a.spill = reinterpret_cast<int32_t*>(ws + L.off_spill);
   const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
   auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
@@ -367,6 +354,25 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     stats->overflow = ctx->h_ctr[kCtrOverflow];
     if (stats->overflow) return fail(ctx, RR_EOVERFLOW, "ray queue overflow");
   }
+  return RR_OK;
+}
+
+rr_status upload_tables(rr_context* ctx, std::vector<DevScan>& scans, const rr_sensor_params* const* ps,
+                        const rr_material* mats, uint32_t n_mats, char* ws, hipStream_t st,
+                        float beam_width_for_mats) {
+  Layout L;
+  make_layout(ps, (uint32_t)scans.size(), L);
+  uint64_t pb = 0, ab = 0;
+  for (size_t i = 0; i < scans.size(); ++i) {
+    scans[i].prim_base = (uint32_t)pb;
+    scans[i].acc_base = ab;
+    pb += scans[i].n_prim;
+    ab += (uint64_t)scans[i].n_az * scans[i].n_bins;
+  }
+  std::vector<DevMaterial> dm;
+  make_materials(mats, n_mats, beam_width_for_mats, dm);
+  HIP_TRY(ctx, put_blob(ws + L.off_scans, scans.data(), sizeof(DevScan) * scans.size(), st));
+  HIP_TRY(ctx, put_blob(ws + L.off_mats, dm.data(), sizeof(DevMaterial) * dm.size(), st));
   return RR_OK;
 }
 
@@ -710,6 +716,8 @@ rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   ctx->refill_lanes = rl;
   ctx->trace_waves_per_cu = wc;
   ctx->pool_rays = pr;
+  if (t->leaf_batch_lanes > 64) return fail(ctx, RR_EINVAL, "leaf_batch_lanes out of [0, 64]");
+  ctx->leaf_batch = t->leaf_batch_lanes;
   return RR_OK;
 }
 
@@ -719,6 +727,7 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
   out->refill_lanes = ctx->refill_lanes;
   out->trace_waves_per_cu = ctx->trace_waves_per_cu;
   out->pool_rays = ctx->pool_rays;
+  out->leaf_batch_lanes = ctx->leaf_batch;
   out->batch_budget_mb = (uint32_t)(ctx->batch_budget >> 20);
   return RR_OK;
 }

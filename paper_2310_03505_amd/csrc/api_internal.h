@@ -32,6 +32,7 @@ struct rr_context {
   uint32_t refill_lanes = 16;
   uint32_t trace_waves_per_cu = 20;
   uint32_t pool_rays = 64;
+  uint32_t leaf_batch = 0;
   size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group
 };
 
@@ -52,6 +53,14 @@ struct rr_scene {
 
 
 namespace rr {
+
+#define HIP_TRY(ctx, expr)                                                                    \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? RR_ENOMEM : RR_EDEVICE, "%s: %s", #expr,   \
+                  hipGetErrorString(e_));                                                     \
+  } while (0)
 
 // Workspace layout of a set of scans (see api.cpp).
 struct Layout {
@@ -87,6 +96,13 @@ rr_status fail(rr_context* ctx, rr_status s, const char* fmt, ...);
 rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
-              float beam_width_for_mats, uint32_t* counters_host = nullptr);
+              float beam_width_for_mats, uint32_t* counters_host = nullptr,
+              bool upload_tables = true);
+// Uploads the scan table (prim_base / acc_base filled) and the material
+// table of a set of scans into workspace `ws`.
+rr_status upload_tables(rr_context* ctx, std::vector<DevScan>& scans, const rr_sensor_params* const* ps,
+                        const rr_material* mats, uint32_t n_mats, char* ws, hipStream_t st,
+                        float beam_width_for_mats);
+rr_status ensure_ws(rr_context* ctx, size_t bytes);
 
 }  // namespace rr

@@ -1,0 +1,263 @@
+// graph.cpp -- captured launch sequences (rr_graph_*) and the launch
+// parameter autotuner (rr_autotune).
+//
+// A graph holds the whole per-batch sequence: clear, ray generation, one
+// trace and one shade launch per bounce level, finalize.  The scan and
+// material tables are the only inputs that change between replays; they are
+// uploaded by a small kernel on the caller's stream right before the graph
+// is launched there, so the captured nodes never change.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "api_internal.h"
+
+using namespace rr;
+
+struct rr_graph {
+  rr_context* ctx = nullptr;
+  const rr_scene* scene = nullptr;
+  std::vector<rr_sensor_params> params;  // shapes the graph was captured for
+  std::vector<rr_material> mats;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void graph_free(rr_graph* g) {
+  if (!g) return;
+  DeviceGuard dg(g->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  if (g->ws) (void)hipFree(g->ws);
+  delete g;
+}
+
+rr_status check_descs(rr_context* ctx, const rr_scan_desc* d, uint32_t n) {
+  rr_status s;
+  for (uint32_t i = 0; i < n; ++i) {
+    if ((s = check_params(ctx, &d[i].params)) || (s = check_pose(ctx, &d[i].pose))) return s;
+    if (!d[i].image_dev) return fail(ctx, RR_EINVAL, "scan %u: image_dev is NULL", i);
+    if (d[i].params.beam_width_rad != d[0].params.beam_width_rad)
+      return fail(ctx, RR_EINVAL, "scans of a graph must share the beam width");
+  }
+  return RR_OK;
+}
+
+// Uploads the tables of `d` (n scans) into the graph's workspace on `st`.
+rr_status graph_upload(rr_graph* g, const rr_scan_desc* d, hipStream_t st) {
+  const uint32_t n = (uint32_t)g->params.size();
+  std::vector<const rr_sensor_params*> ps(n);
+  std::vector<DevScan> scans(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    ps[i] = &d[i].params;
+    make_scan(d[i].pose, d[i].params, scans[i]);
+    scans[i].image = d[i].image_dev;
+  }
+  return upload_tables(g->ctx, scans, ps.data(), g->mats.data(), (uint32_t)g->mats.size(), g->ws, st,
+                       d[0].params.beam_width_rad);
+}
+
+}  // namespace
+
+extern "C" {
+
+rr_status rr_graph_create(rr_context* ctx, const rr_scene* sc, const rr_scan_desc* descs, uint32_t n,
+                          const rr_material* mats, uint32_t n_mats, rr_graph** out) {
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  if (!out) return fail(ctx, RR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || n == 0 || n > 65535) return fail(ctx, RR_EINVAL, "need 1..65535 scans");
+  rr_status s;
+  if ((s = check_scene(ctx, sc)) || (s = check_materials(ctx, mats, n_mats, sc)) ||
+      (s = check_descs(ctx, descs, n)))
+    return s;
+  DeviceGuard dg(ctx->device);
+  rr_graph* g = new rr_graph();
+  g->ctx = ctx;
+  g->scene = sc;
+  g->mats.assign(mats, mats + n_mats);
+  std::vector<const rr_sensor_params*> ps(n);
+  std::vector<DevScan> scans(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    g->params.push_back(descs[i].params);
+    make_scan(descs[i].pose, descs[i].params, scans[i]);
+    scans[i].image = descs[i].image_dev;
+  }
+  for (uint32_t i = 0; i < n; ++i) ps[i] = &g->params[i];
+  Layout L;
+  make_layout(ps.data(), n, L);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->ws), L.total);
+  if (e != hipSuccess) {
+    graph_free(g);
+    return fail(ctx, RR_ENOMEM, "graph workspace of %zu bytes: %s", L.total, hipGetErrorString(e));
+  }
+  g->ws_bytes = L.total;
+  if ((e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+    graph_free(g);
+    return fail(ctx, RR_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+  }
+  // tables of the creating scans, so a replay without new scans is valid
+  if ((s = graph_upload(g, descs, g->cap_stream)) ||
+      ((e = hipStreamSynchronize(g->cap_stream)) != hipSuccess &&
+       (s = fail(ctx, RR_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e))))) {
+    graph_free(g);
+    return s;
+  }
+  // capture without per-launch events or counters
+  const uint32_t prof = ctx->prof_flags;
+  ctx->prof_flags = 0;
+  e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    ctx->prof_flags = prof;
+    graph_free(g);
+    return fail(ctx, RR_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  s = run(ctx, sc, scans, ps.data(), mats, n_mats, g->ws, g->ws_bytes, nullptr, g->cap_stream, nullptr,
+          descs[0].params.beam_width_rad, nullptr, /*upload_tables=*/false);
+  ctx->prof_flags = prof;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(g->cap_stream, &graph);
+  g->graph = graph;
+  if (s) {
+    graph_free(g);
+    return s;
+  }
+  if (e != hipSuccess) {
+    graph_free(g);
+    return fail(ctx, RR_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
+    graph_free(g);
+    return fail(ctx, RR_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return RR_OK;
+}
+
+rr_status rr_graph_launch(rr_graph* g, const rr_scan_desc* descs, void* stream) {
+  if (!g) return fail(nullptr, RR_EINVAL, "graph is NULL");
+  rr_context* ctx = g->ctx;
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rr_status s;
+  if (descs) {
+    const uint32_t n = (uint32_t)g->params.size();
+    if ((s = check_descs(ctx, descs, n))) return s;
+    for (uint32_t i = 0; i < n; ++i) {
+      const rr_sensor_params &a = descs[i].params, &b = g->params[i];
+      if (a.n_azimuth != b.n_azimuth || a.rays_per_beam != b.rays_per_beam || a.n_bins != b.n_bins ||
+          a.max_bounces != b.max_bounces)
+        return fail(ctx, RR_EINVAL,
+                    "scan %u: azimuths, rays per beam, bins and bounces must match the captured scans", i);
+    }
+    if ((s = graph_upload(g, descs, st))) return s;
+  }
+  HIP_TRY(ctx, hipGraphLaunch(g->exec, st));
+  return RR_OK;
+}
+
+rr_status rr_graph_destroy(rr_graph* g) {
+  graph_free(g);
+  return RR_OK;
+}
+
+// Coordinate descent over the trace launch parameters.  Each candidate is
+// timed over `reps` scans after one untimed scan; a parameter keeps its new
+// value only when it beats the incumbent by more than 1%, and the descent
+// stops after a pass without change (at most three passes).
+rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, const rr_sensor_params* params,
+                      const rr_material* mats, uint32_t n_mats, float* image_dev, uint32_t reps, rr_tuning* best,
+                      double* best_ms, void* stream) {
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  if (!image_dev) return fail(ctx, RR_EINVAL, "image_dev is NULL");
+  if (reps == 0 || reps > 1000) return fail(ctx, RR_EINVAL, "reps out of [1, 1000]");
+  rr_status s;
+  if ((s = check_scene(ctx, sc)) || (s = check_params(ctx, params)) || (s = check_pose(ctx, pose)) ||
+      (s = check_materials(ctx, mats, n_mats, sc)))
+    return s;
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ctx, RR_EDEVICE, "hipEventCreate failed");
+  }
+  const uint32_t prof = ctx->prof_flags;
+  ctx->prof_flags = 0;
+  rr_tuning cur{};
+  (void)rr_get_tuning(ctx, &cur);
+  const rr_tuning orig = cur;
+  auto measure = [&](const rr_tuning& t, double& ms) -> rr_status {
+    rr_status r = rr_set_tuning(ctx, &t);
+    if (r) return r;
+    for (uint32_t k = 0; k <= reps; ++k) {
+      if (k == 1 && hipEventRecord(e0, st) != hipSuccess) return fail(ctx, RR_EDEVICE, "hipEventRecord failed");
+      if ((r = rr_radar_scan(ctx, sc, pose, params, mats, n_mats, image_dev, nullptr, stream))) return r;
+    }
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(ctx, RR_EDEVICE, "event wait failed");
+    float f = 0.0f;
+    if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return fail(ctx, RR_EDEVICE, "hipEventElapsedTime failed");
+    ms = (double)f / reps;
+    return RR_OK;
+  };
+  static const uint32_t kRefill[] = {4, 8, 12, 16, 24, 32, 48};
+  static const uint32_t kWaves[] = {8, 12, 16, 20, 24, 32};
+  static const uint32_t kPool[] = {64, 128, 256};
+  static const uint32_t kLeaf[] = {0, 8, 16};
+  struct Axis {
+    const uint32_t* v;
+    size_t n;
+    uint32_t rr_tuning::*f;
+  } axes[] = {{kRefill, 7, &rr_tuning::refill_lanes},
+              {kWaves, 6, &rr_tuning::trace_waves_per_cu},
+              {kPool, 3, &rr_tuning::pool_rays},
+              {kLeaf, 3, &rr_tuning::leaf_batch_lanes}};
+  double inc = 0.0;
+  s = measure(cur, inc);
+  for (int pass = 0; pass < 3 && !s; ++pass) {
+    bool changed = false;
+    for (const Axis& ax : axes) {
+      for (size_t i = 0; i < ax.n && !s; ++i) {
+        if (cur.*(ax.f) == ax.v[i]) continue;
+        rr_tuning t = cur;
+        t.*(ax.f) = ax.v[i];
+        double ms = 0.0;
+        if ((s = measure(t, ms))) break;
+        if (ms < inc * 0.99) {
+          inc = ms;
+          cur = t;
+          changed = true;
+        }
+      }
+      if (s) break;
+    }
+    if (!changed) break;
+  }
+  ctx->prof_flags = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s) {
+    std::string why = ctx->err;
+    (void)rr_set_tuning(ctx, &orig);
+    ctx->err = why;
+    return s;
+  }
+  if ((s = rr_set_tuning(ctx, &cur))) return s;
+  if (best) *best = cur;
+  if (best_ms) *best_ms = inc;
+  return RR_OK;
+}
+
+}  // extern "C"

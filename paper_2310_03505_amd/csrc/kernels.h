@@ -33,6 +33,7 @@ struct LevelArgs {
   uint32_t masked;    // some scan has a primary mask: raygen compacts with atomics
   uint32_t refill;    // trace: refill a wave once this many lanes are idle
   uint32_t pool;      // trace: rays a wave claims per atomic
+  uint32_t leaf_batch;  // trace: 0 unified schedule, else phased (lanes parked before a triangle phase)
   int32_t* spill;     // trace: stack entries beyond kStack, kSpill per lane (lane-major)
   uint32_t* counters;
   unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)

@@ -106,7 +106,7 @@ __device__ __forceinline__ void normalize3(float& x, float& y, float& z) {
 // cursor (one atomic per wave) as soon as a quarter of the wave is idle, so
 // the wave does not wait for its slowest ray.  The per-lane stack lives in
 // LDS with a stride of the block size (entry s of lane t at stk[s * B]).
-template <bool kCount>
+template <bool kCount, bool kPhased>
 __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   __shared__ int32_t lds_stack[kStack * kTraceBlock];
   int32_t* stk = lds_stack + threadIdx.x;
@@ -120,6 +120,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const uint32_t spill_stride = gridDim.x * blockDim.x;
 
   bool valid = false, exhausted = false;
+  bool tri_phase = false;                 // wave-uniform (phased schedule)
   uint32_t pool_next = 0, pool_end = 0;  // wave-uniform: claimed, not yet started rays
   uint32_t ridx = 0, visits = 0, best_orig = 0;
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0;
@@ -133,7 +134,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
     // ---- refill idle lanes (wave-uniform decision) from the wave's pool of
     // claimed rays; the pool is refilled A.pool rays at a time with one atomic
     uint64_t idle = __ballot(!valid);
-    if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
+    if (!exhausted && (!kPhased || !tri_phase) && (uint32_t)__popcll(idle) >= A.refill) {
 #pragma unroll 1
       for (int pass = 0; pass < 2 && idle; ++pass) {
         if (pool_next >= pool_end) {
@@ -183,26 +184,13 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
     }
     if (__ballot(valid) == 0ull) break;  // only once the level is exhausted
 
-    // ---- one unit of work per valid lane: a node visit or a triangle test
-    if (valid) {
-      bool done = false;
-      if (tri_n == 0) {
-        if (cur == kEmpty) {
-          if (sp > 0) {
-            --sp;
-            cur = sp < kStack ? stk[sp * kTraceBlock]
-                              : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
-          } else {
-            done = true;
-          }
-        }
-        if (cur < 0) {  // a leaf: its triangles are tested one per iteration
-          tri_i = leaf_start(cur);
-          tri_n = leaf_count(cur);
-          cur = kEmpty;
-        }
-      }
-      if (tri_n > 0) {
+    // Two schedules.  Unified: every iteration each lane does one unit of work,
+    // a node visit or a triangle test.  Phased (A.leaf_batch > 0): the wave
+    // alternates node phases, in which a lane that reaches a leaf parks it,
+    // and triangle phases, entered once A.leaf_batch lanes hold a parked leaf
+    // (or no lane can visit nodes), so each phase executes only its own path.
+    if (kPhased && tri_phase) {
+      if (valid && tri_n > 0) {
         const uint32_t li = tri_i;
         ++tri_i;
         --tri_n;
@@ -222,7 +210,53 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
             }
           }
         }
-      } else if (!done) {
+        if (++visits > A.n_nodes + A.n_leaf_tris || (tri_n == 0 && cur == kEmpty && sp == 0)) {
+          A.hits[ridx] = make_uint2(__float_as_uint(best_t), (uint32_t)best);
+          valid = false;
+        }
+      }
+      if (__ballot(valid && tri_n > 0) == 0ull) tri_phase = false;
+      continue;
+    }
+    if (valid && !(kPhased && tri_n > 0)) {
+      bool done = false;
+      if (tri_n == 0) {
+        if (cur == kEmpty) {
+          if (sp > 0) {
+            --sp;
+            cur = sp < kStack ? stk[sp * kTraceBlock]
+                              : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
+          } else {
+            done = true;
+          }
+        }
+        if (cur < 0) {  // a leaf: its triangles are tested one per iteration
+          tri_i = leaf_start(cur);
+          tri_n = leaf_count(cur);
+          cur = kEmpty;
+        }
+      }
+      if (!kPhased && tri_n > 0) {
+        const uint32_t li = tri_i;
+        ++tri_i;
+        --tri_n;
+        if ((int32_t)li != excl) {
+          if (kCount) ++cnt_tris;
+          const float4 ta = tris[3 * li + 0];
+          const float4 e1 = tris[3 * li + 1];
+          const float4 e2 = tris[3 * li + 2];
+          float t;
+          if (ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
+                      best_t, t)) {
+            const uint32_t orig = __float_as_uint(ta.w);
+            if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
+              best_t = t;
+              best = (int32_t)li;
+              best_orig = orig;
+            }
+          }
+        }
+      } else if (!done && tri_n == 0) {
         const float4* np = reinterpret_cast<const float4*>(nodes + cur);
         const float4 w0 = np[0];
         const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
@@ -265,6 +299,11 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           }
         }
         cur = val[0];
+        if (kPhased && cur != kEmpty && cur < 0) {  // park the nearest leaf at once
+          tri_i = leaf_start(cur);
+          tri_n = leaf_count(cur);
+          cur = kEmpty;
+        }
       }
       // every node and leaf is entered at most once per ray; the bound only
       // guards against a malformed tree
@@ -273,6 +312,11 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         A.hits[ridx] = make_uint2(__float_as_uint(best_t), (uint32_t)best);
         valid = false;
       }
+    }
+    if (kPhased) {
+      const uint64_t parked = __ballot(valid && tri_n > 0);
+      const uint64_t walking = __ballot(valid && tri_n == 0);
+      if (parked && ((uint32_t)__popcll(parked) >= A.leaf_batch || walking == 0ull)) tri_phase = true;
     }
   }
   if (kCount) {
@@ -640,10 +684,18 @@ hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st) {
 }
 
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
-  if (a.prof)
-    hipLaunchKernelGGL(k_trace<true>, dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_trace<false>, dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
+  const dim3 g(grid ? grid : 1), b(kTraceBlock);
+  if (a.leaf_batch) {
+    if (a.prof)
+      hipLaunchKernelGGL((k_trace<true, true>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_trace<false, true>), g, b, 0, st, a);
+  } else {
+    if (a.prof)
+      hipLaunchKernelGGL((k_trace<true, false>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_trace<false, false>), g, b, 0, st, a);
+  }
   return hipGetLastError();
 }
 

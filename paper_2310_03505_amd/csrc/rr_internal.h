@@ -192,6 +192,10 @@ RR_HD void ray_box_setup(float ox, float oy, float oz, float dx, float dy, float
 // Entry distances of the four children of a quantised node; returns the mask
 // of children whose box meets [0, tmax].  Per axis the child bounds decode as
 // t = q * (2^e / d) + (origin - o) / d, one fused multiply-add per bound.
+// The near plane of an axis is its low bound when the direction component
+// is positive and its high bound otherwise; fma(q, s, b) is monotone in q,
+// so choosing the byte planes by the sign of 1/d equals taking min / max of
+// both decoded bounds.
 RR_HD uint32_t node4_boxes(const float4& w0, const uint4& w1, const uint4& w2, const int4& w3,
                            const RayBox& r, float tmax, float tn[4]) {
   uint32_t eb;
@@ -206,15 +210,19 @@ RR_HD uint32_t node4_boxes(const float4& w0, const uint4& w1, const uint4& w2, c
   const float bx = fmaf(w0.x, r.ix, -r.oix);
   const float by = fmaf(w0.y, r.iy, -r.oiy);
   const float bz = fmaf(w0.z, r.iz, -r.oiz);
+  const bool px = r.ix >= 0.0f, py = r.iy >= 0.0f, pz = r.iz >= 0.0f;
+  const uint32_t nx = px ? w1.x : w1.y, fx = px ? w1.y : w1.x;
+  const uint32_t ny = py ? w1.z : w1.w, fy = py ? w1.w : w1.z;
+  const uint32_t nz = pz ? w2.x : w2.y, fz = pz ? w2.y : w2.x;
   const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
   uint32_t mask = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const float lx = fmaf(byte_f(w1.x, j), sx, bx), hx = fmaf(byte_f(w1.y, j), sx, bx);
-    const float ly = fmaf(byte_f(w1.z, j), sy, by), hy = fmaf(byte_f(w1.w, j), sy, by);
-    const float lz = fmaf(byte_f(w2.x, j), sz, bz), hz = fmaf(byte_f(w2.y, j), sz, bz);
-    const float a = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), 0.0f));
-    const float f = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fminf(fmaxf(lz, hz), tmax));
+    const float tnx = fmaf(byte_f(nx, j), sx, bx), tfx = fmaf(byte_f(fx, j), sx, bx);
+    const float tny = fmaf(byte_f(ny, j), sy, by), tfy = fmaf(byte_f(fy, j), sy, by);
+    const float tnz = fmaf(byte_f(nz, j), sz, bz), tfz = fmaf(byte_f(fz, j), sz, bz);
+    const float a = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+    const float f = fminf(fminf(tfx, tfy), fminf(tfz, tmax));
     tn[j] = a;
     if (a <= f * kSlabSlack && ref[j] != kEmpty) mask |= 1u << j;
   }

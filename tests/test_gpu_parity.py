@@ -260,6 +260,86 @@ def test_invalid_arguments_launch_nothing(R, ctx):
         sc.release()
 
 
+# ---------------------------------------------------------------- graphs and autotuning
+def test_graph_replays_equal_eager(R, ctx):
+    """A captured batch replayed with new poses, seeds and output images gives,
+    on every replay, the images the eager batch gives for those scans; eager
+    work runs between the replays."""
+    import torch
+    s = W.tiny_room()
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+
+    def scans_at(k):
+        out = []
+        for i, (naz, ns, b) in enumerate([(120, 16, 3), (37, 5, 4), (300, 8, 2)]):
+            p = dict(s.params, n_azimuth=naz, rays_per_beam=ns, max_bounces=b,
+                     scan_id=10 * k + i, seed=1000 + k)
+            out.append((W.yaw_pose((0.3 * k - 0.2 * i, 0.1 * i, 0.0), 0.4 * k + i), p))
+        return out
+
+    g, first = R.rr_graph_create(ctx.handle, sc.handle, scans_at(0), s.materials)
+    try:
+        R.rr_graph_launch(g)
+        torch.cuda.synchronize()
+        ref0, _ = R.rr_radar_scan_batch(ctx.handle, sc.handle, scans_at(0), s.materials)
+        torch.cuda.synchronize()
+        for a, b in zip(first, ref0):
+            assert torch.equal(a, b)
+        for k in range(1, 5):
+            scans = scans_at(k)
+            imgs = [torch.full((p["n_azimuth"], p["n_bins"]), -1.0, device="cuda")
+                    for _, p in scans]
+            R.rr_graph_launch(g, scans, imgs)
+            ref, _ = R.rr_radar_scan_batch(ctx.handle, sc.handle, scans, s.materials)
+            torch.cuda.synchronize()
+            for a, b in zip(imgs, ref):
+                assert torch.equal(a, b), f"replay {k}"
+            assert float(imgs[0].sum()) > 0
+        # a replay without scans repeats the last ones into the same images
+        last = [x.clone() for x in imgs]
+        for x in imgs:
+            x.fill_(-1.0)
+        R.rr_graph_launch(g)
+        torch.cuda.synchronize()
+        for a, b in zip(imgs, last):
+            assert torch.equal(a, b)
+        bad = scans_at(9)
+        bad[1] = (bad[1][0], dict(bad[1][1], n_bins=bad[1][1]["n_bins"] + 1))
+        with pytest.raises(R.RadarError) as e:
+            R.rr_graph_launch(g, bad, imgs)
+        assert e.value.status == R.RR_EINVAL
+    finally:
+        R.rr_graph_destroy(g)
+        sc.release()
+
+
+def test_autotune_keeps_images(R, ctx):
+    """The autotuner picks launch parameters from its grid; the image is the
+    same bit for bit under the tuned and the default parameters."""
+    import torch
+    s = W.tiny_room(n_azimuth=256, rays_per_beam=32)
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    before = R.rr_get_tuning(ctx.handle)
+    try:
+        a, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        torch.cuda.synchronize()
+        t, ms = R.rr_autotune(ctx.handle, sc.handle, s.pose, s.params, s.materials, reps=2)
+        assert ms > 0
+        assert t["refill_lanes"] in (4, 8, 12, 16, 24, 32, 48)
+        assert t["trace_waves_per_cu"] in (8, 12, 16, 20, 24, 32)
+        assert t["pool_rays"] in (64, 128, 256) and t["leaf_batch_lanes"] in (0, 8, 16)
+        assert R.rr_get_tuning(ctx.handle) == t
+        b, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        log(f"autotune tiny room: {t} {ms:.3f} ms")
+    finally:
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in
+                                       ("refill_lanes", "trace_waves_per_cu", "pool_rays",
+                                        "batch_budget_mb", "leaf_batch_lanes")})
+        sc.release()
+
+
 # ---------------------------------------------------------------- serving
 def test_server_mix_equals_alone(R, ctx):
     """Requests served in overlapping batches produce the same images, bit for
