@@ -24,15 +24,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # algorithmic bytes per unit of work of the trace kernel
-NODE_BYTES = 64        # one two-child node: both child boxes + child refs
+NODE_BYTES = 64        # one four-wide node: quantised child boxes, box frame, child refs
 TRI_BYTES = 48         # v0 | e1 | e2 of a leaf triangle
 TRACE_RAY_BYTES = 52   # origin, L, direction, excluded leaf, medium/scan of a queued ray
 HIT_RECORD_BYTES = 8   # (t, leaf) written per ray
 # algorithmic float operations (fused multiply-add = 2)
-NODE_FLOPS = 42        # two slab tests: 12 FMA, 18 min/max, 2 scaled compares
+NODE_FLOPS = 76        # four slab tests: 24 FMA, 24 min/max, 4 scaled limits
 TRI_FLOPS = 46         # Moller-Trumbore (all stages)
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of one k_trace launch on the urban block, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, averaged over the
+# timed-variant dispatches), scaled by what the same counters read for a
+# plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
+# all of them).  Valid only for the kernel sources it was taken on.
+TRACE_HBM = dict(workload="urban_block_200k", fetch_kib=54229.6, write_kib=21112.2,
+                 fetch_scale=2.0, write_scale=1.0,
+                 sources_sha256="e0ec3f45f340ba3464c1a7b04a71cd97dc5db049e410d15a25081e77ed08c8b1")
+TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
+
+
+def trace_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_03505_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def trace_traffic(wname: str):
+    """Measured HBM bytes per k_trace launch, or None when the counters were
+    taken on another workload or on other kernel sources."""
+    t = TRACE_HBM
+    if wname != t["workload"] or trace_sources_sha256() != t["sources_sha256"]:
+        return None
+    return int(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
 
 
 def log(*a):
@@ -280,10 +307,10 @@ def main():
     mem_frac, alu_frac = gbs / HBM_PEAK_GBS, tfl / FP32_PEAK_TFLOPS
     if mem_frac >= alu_frac:
         roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(mem_frac, 4), traffic=None)
+                    frac=round(mem_frac, 4), traffic=trace_traffic(wname))
     else:
         roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(alu_frac, 4), traffic=None)
+                    frac=round(alu_frac, 4), traffic=trace_traffic(wname))
     roof.update(kernel="k_trace", launch_ms=round(launch_ms, 4),
                 bytes_per_launch=int(bytes_launch), flops_per_launch=int(flops_launch),
                 other_fraction=round(alu_frac if roof["bound"] == "hbm" else mem_frac, 4),
