@@ -289,9 +289,8 @@ typedef struct {
   uint32_t trace_waves_per_cu; /* persistent trace waves per compute unit (1..32) */
   uint32_t pool_rays;      /* rays a trace wave claims per atomic (64..4096) */
   uint32_t batch_budget_mb; /* workspace budget of one batch group, MiB (>= 64) */
-  uint32_t leaf_batch_lanes; /* 0: each lane visits a node or tests a triangle per
-                               step; n > 0: lanes park leaves and the wave tests
-                               triangles once n lanes hold one (1..64) */
+  uint32_t tri_batch;      /* leaves a trace wave queues before it tests their
+                             triangles in one step, one leaf per lane (1..64) */
   uint32_t reserved[3];
 } rr_tuning;
 
@@ -300,7 +299,7 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out);
 
 /* Autotuner: scans the given workload with candidate launch parameters
  * (coordinate descent over refill_lanes, trace_waves_per_cu, pool_rays and
- * leaf_batch_lanes, each candidate timed with HIP events over `reps` scans
+ * tri_batch, each candidate timed with HIP events over `reps` scans
  * on `stream`), keeps the fastest in the context and returns it in *best
  * with its time per scan.  Every candidate produces the same image. */
 rr_status rr_autotune(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
@@ -337,6 +336,14 @@ typedef struct {
   uint64_t tri_tests;          /* ray-triangle tests (RR_PROFILE_COUNT) */
   uint64_t rays;               /* rays traced by the counted launches */
   uint64_t hits;               /* rays that hit a triangle */
+  /* SIMD occupancy of the trace loop per bounce level (RR_PROFILE_COUNT):
+   * wave iterations, and lanes holding a ray summed over those iterations;
+   * the tail_ pair counts only iterations after the level's queue ran dry. */
+  uint64_t wave_iters[RR_MAX_BOUNCES];
+  uint64_t active_lanes[RR_MAX_BOUNCES];
+  uint64_t tail_wave_iters[RR_MAX_BOUNCES];
+  uint64_t tail_active_lanes[RR_MAX_BOUNCES];
+  uint64_t max_ray_iters[RR_MAX_BOUNCES]; /* most loop iterations of one ray */
 } rr_profile;
 
 /* Measurement hooks for benchmarks (not needed for scans).  Enabling with

@@ -63,7 +63,12 @@ class rr_profile(C.Structure):
     _fields_ = [("trace_launches", C.c_uint64), ("trace_ms", C.c_double),
                 ("trace_level_ms", C.c_double * RR_MAX_BOUNCES), ("shade_ms", C.c_double),
                 ("raygen_ms", C.c_double), ("node_visits", C.c_uint64),
-                ("tri_tests", C.c_uint64), ("rays", C.c_uint64), ("hits", C.c_uint64)]
+                ("tri_tests", C.c_uint64), ("rays", C.c_uint64), ("hits", C.c_uint64),
+                ("wave_iters", C.c_uint64 * RR_MAX_BOUNCES),
+                ("active_lanes", C.c_uint64 * RR_MAX_BOUNCES),
+                ("tail_wave_iters", C.c_uint64 * RR_MAX_BOUNCES),
+                ("tail_active_lanes", C.c_uint64 * RR_MAX_BOUNCES),
+                ("max_ray_iters", C.c_uint64 * RR_MAX_BOUNCES)]
 
 
 RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
@@ -72,7 +77,7 @@ RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
 class rr_tuning(C.Structure):
     _fields_ = [("refill_lanes", C.c_uint32), ("trace_waves_per_cu", C.c_uint32),
                 ("pool_rays", C.c_uint32), ("batch_budget_mb", C.c_uint32),
-                ("leaf_batch_lanes", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("tri_batch", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 class rr_server_options(C.Structure):
@@ -343,8 +348,8 @@ def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, 
 
 
 def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0, pool_rays: int = 0,
-                  batch_budget_mb: int = 0, leaf_batch_lanes: int = 0):
-    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb, leaf_batch_lanes)
+                  batch_budget_mb: int = 0, tri_batch: int = 0):
+    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb, tri_batch)
     _check(load_library().rr_set_tuning(ctx, C.byref(t)), ctx)
 
 
@@ -353,7 +358,7 @@ def rr_get_tuning(ctx) -> dict:
     _check(load_library().rr_get_tuning(ctx, C.byref(t)), ctx)
     return dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
                 pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb),
-                leaf_batch_lanes=int(t.leaf_batch_lanes))
+                tri_batch=int(t.tri_batch))
 
 
 def rr_autotune(ctx, scene, pose: dict, params: dict, materials, image=None, reps: int = 5,
@@ -373,7 +378,7 @@ def rr_autotune(ctx, scene, pose: dict, params: dict, materials, image=None, rep
                                       _stream_handle(stream)), ctx)
     return (dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
                  pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb),
-                 leaf_batch_lanes=int(t.leaf_batch_lanes)), float(ms.value))
+                 tri_batch=int(t.tri_batch)), float(ms.value))
 
 
 def rr_graph_create(ctx, scene, scans, materials, images=None):
@@ -415,7 +420,11 @@ def rr_profile_read(ctx) -> dict:
     return dict(trace_launches=int(p.trace_launches), trace_ms=float(p.trace_ms),
                 trace_level_ms=[float(x) for x in p.trace_level_ms], shade_ms=float(p.shade_ms),
                 raygen_ms=float(p.raygen_ms), node_visits=int(p.node_visits),
-                tri_tests=int(p.tri_tests), rays=int(p.rays), hits=int(p.hits))
+                tri_tests=int(p.tri_tests), rays=int(p.rays), hits=int(p.hits),
+                wave_iters=list(p.wave_iters), active_lanes=list(p.active_lanes),
+                tail_wave_iters=list(p.tail_wave_iters),
+                tail_active_lanes=list(p.tail_active_lanes),
+                max_ray_iters=list(p.max_ray_iters))
 
 
 def rr_server_create(ctx, scene, materials, n_slots: int = 0, max_batch_scans: int = 0,

@@ -271,7 +271,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   LevelArgs a{};
   a.nodes = sc->d_nodes;
   a.n_nodes = (uint32_t)sc->bvh.nodes.size();
-  a.n_leaf_tris = (uint32_t)sc->bvh.aux.size();
+  a.n_leaf_tris = (uint32_t)(sc->bvh.tris.size() / 3);
   a.tris = sc->d_tris;
   a.aux = sc->d_aux;
   a.scans = d_scans;
@@ -290,7 +290,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   trace_grid = std::min(trace_grid, kSpillLanes / (uint32_t)kTraceBlock);
   a.refill = ctx->refill_lanes;
   a.pool = ctx->pool_rays;
-  a.leaf_batch = ctx->leaf_batch;
+  a.tri_batch = ctx->tri_batch;
   a.spill = reinterpret_cast<int32_t*>(ws + L.off_spill);
   const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
   auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
@@ -716,8 +716,8 @@ rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   ctx->refill_lanes = rl;
   ctx->trace_waves_per_cu = wc;
   ctx->pool_rays = pr;
-  if (t->leaf_batch_lanes > 64) return fail(ctx, RR_EINVAL, "leaf_batch_lanes out of [0, 64]");
-  ctx->leaf_batch = t->leaf_batch_lanes;
+  if (t->tri_batch > 64) return fail(ctx, RR_EINVAL, "tri_batch out of [1, 64]");
+  ctx->tri_batch = t->tri_batch ? t->tri_batch : 32u;
   return RR_OK;
 }
 
@@ -727,7 +727,7 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
   out->refill_lanes = ctx->refill_lanes;
   out->trace_waves_per_cu = ctx->trace_waves_per_cu;
   out->pool_rays = ctx->pool_rays;
-  out->leaf_batch_lanes = ctx->leaf_batch;
+  out->tri_batch = ctx->tri_batch;
   out->batch_budget_mb = (uint32_t)(ctx->batch_budget >> 20);
   return RR_OK;
 }
@@ -737,8 +737,8 @@ rr_status rr_profile_enable(rr_context* ctx, uint32_t flags) {
   if (flags & ~(RR_PROFILE_TIME | RR_PROFILE_COUNT)) return fail(ctx, RR_EINVAL, "unknown profile flags");
   DeviceGuard g(ctx->device);
   if ((flags & RR_PROFILE_COUNT) && !ctx->d_prof) {
-    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->d_prof), 4 * sizeof(unsigned long long)));
-    HIP_TRY(ctx, hipMemset(ctx->d_prof, 0, 4 * sizeof(unsigned long long)));
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->d_prof), kProfWords * sizeof(unsigned long long)));
+    HIP_TRY(ctx, hipMemset(ctx->d_prof, 0, kProfWords * sizeof(unsigned long long)));
   }
   ctx->prof_flags = flags;
   return RR_OK;
@@ -766,7 +766,7 @@ rr_status rr_profile_read(rr_context* ctx, rr_profile* out) {
   }
   ctx->ev_used.clear();
   if (ctx->d_prof) {
-    unsigned long long h[4] = {0, 0, 0, 0};
+    unsigned long long h[kProfWords] = {};
     HIP_TRY(ctx, hipDeviceSynchronize());
     HIP_TRY(ctx, hipMemcpy(h, ctx->d_prof, sizeof h, hipMemcpyDeviceToHost));
     HIP_TRY(ctx, hipMemset(ctx->d_prof, 0, sizeof h));
@@ -774,6 +774,13 @@ rr_status rr_profile_read(rr_context* ctx, rr_profile* out) {
     out->tri_tests = h[1];
     out->rays = h[2];
     out->hits = h[3];
+    for (int d = 0; d < RR_MAX_BOUNCES; ++d) {
+      out->wave_iters[d] = h[kProfIters + d];
+      out->active_lanes[d] = h[kProfActive + d];
+      out->tail_wave_iters[d] = h[kProfTailIters + d];
+      out->tail_active_lanes[d] = h[kProfTailActive + d];
+      out->max_ray_iters[d] = h[kProfMaxVisits + d];
+    }
   }
   return RR_OK;
 }

@@ -32,7 +32,7 @@ struct rr_context {
   uint32_t refill_lanes = 16;
   uint32_t trace_waves_per_cu = 20;
   uint32_t pool_rays = 64;
-  uint32_t leaf_batch = 0;
+  uint32_t tri_batch = 32;  // queued leaves that start a triangle phase
   size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group
 };
 

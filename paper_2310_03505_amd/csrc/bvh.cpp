@@ -208,7 +208,6 @@ struct Flattener4 {
       out.tris.push_back(tri3[3 * id + 0]);
       out.tris.push_back(tri3[3 * id + 1]);
       out.tris.push_back(tri3[3 * id + 2]);
-      out.aux.push_back(aux0[id]);
     }
     out.n_leaves++;
     if (root_area > 0.0) out.sah_cost += b->box.area() / root_area * b->count;
@@ -387,6 +386,7 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
   Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area()};
   int32_t root_ref;
   out.max_stack = fl.emit(root.get(), 0, &root_ref);
+  out.aux = std::move(aux0);
   auto t1 = std::chrono::steady_clock::now();
   out.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 }
@@ -470,7 +470,7 @@ int32_t host_brute(const BuiltBvh& b, const float o[3], const float d[3], float 
   float best_t = tmax;
   int32_t best = -1;
   uint32_t best_orig = 0xffffffffu;
-  leaf_test(b, 0, (uint32_t)b.aux.size(), o, d, excl, best_t, best, best_orig);
+  leaf_test(b, 0, (uint32_t)(b.tris.size() / 3), o, d, excl, best_t, best, best_orig);
   if (t_out) *t_out = best_t;
   return best;
 }
@@ -488,7 +488,7 @@ uint64_t bvh_selfcheck(const BuiltBvh& b, uint32_t n_rays, uint64_t seed) {
   for (int a = 0; a < 3; ++a) diag += (b.hi[a] - b.lo[a]) * (b.hi[a] - b.lo[a]);
   float tmax = 2.0f * std::sqrt(diag) + 1.0f;
   uint64_t bad = 0;
-  uint32_t nl = (uint32_t)b.aux.size();
+  uint32_t nl = (uint32_t)(b.tris.size() / 3);
   for (uint32_t r = 0; r < n_rays; ++r) {
     float o[3], d[3];
     for (int a = 0; a < 3; ++a) o[a] = (float)(b.lo[a] + (b.hi[a] - b.lo[a]) * next());

@@ -18,7 +18,7 @@ struct BvhBuildOptions {
 struct BuiltBvh {
   std::vector<Node4> nodes;       // four-wide inner nodes, node 0 is the root
   std::vector<float4> tris;       // 3 per leaf triangle: (v0, orig), (e1, 0), (e2, 0)
-  std::vector<float4> aux;        // 1 per leaf triangle: (unit normal, material bits)
+  std::vector<float4> aux;        // 1 per scene triangle, original order: (unit normal, material bits)
   uint32_t n_tris = 0;            // triangles in the scene
   uint32_t n_hittable = 0;        // non-degenerate triangles in the leaves
   uint32_t n_leaves = 0;

@@ -215,7 +215,7 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   static const uint32_t kRefill[] = {4, 8, 12, 16, 24, 32, 48};
   static const uint32_t kWaves[] = {8, 12, 16, 20, 24, 32};
   static const uint32_t kPool[] = {64, 128, 256};
-  static const uint32_t kLeaf[] = {0, 8, 16};
+  static const uint32_t kTriBatch[] = {16, 32, 48, 64};
   struct Axis {
     const uint32_t* v;
     size_t n;
@@ -223,7 +223,7 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   } axes[] = {{kRefill, 7, &rr_tuning::refill_lanes},
               {kWaves, 6, &rr_tuning::trace_waves_per_cu},
               {kPool, 3, &rr_tuning::pool_rays},
-              {kLeaf, 3, &rr_tuning::leaf_batch_lanes}};
+              {kTriBatch, 4, &rr_tuning::tri_batch}};
   double inc = 0.0;
   s = measure(cur, inc);
   for (int pass = 0; pass < 3 && !s; ++pass) {

@@ -28,12 +28,12 @@ struct LevelArgs {
   const DevMaterial* mats;
   unsigned long long* acc;
   QueueView in, out;  // rays of this level / children appended for the next
-  uint2* hits;        // per ray of this level: (t bits, leaf index or -1)
+  uint2* hits;        // per ray of this level: (t bits, original triangle id or -1)
   uint32_t n_first;   // primaries of every scan (raygen work items)
   uint32_t masked;    // some scan has a primary mask: raygen compacts with atomics
   uint32_t refill;    // trace: refill a wave once this many lanes are idle
   uint32_t pool;      // trace: rays a wave claims per atomic
-  uint32_t leaf_batch;  // trace: 0 unified schedule, else phased (lanes parked before a triangle phase)
+  uint32_t tri_batch;   // trace: queued leaves that start a triangle phase (1..64)
   int32_t* spill;     // trace: stack entries beyond kStack, kSpill per lane (lane-major)
   uint32_t* counters;
   unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)
@@ -53,7 +53,18 @@ hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_finalize(const DevScan* scans, uint32_t n_scans, const unsigned long long* acc,
                            uint32_t max_cells, hipStream_t st);
 
+// profile counter block (u64): [0] node visits, [1] triangle tests, [2] rays,
+// [3] hits, then per bounce level: wave iterations, active lanes, and the
+// same two after the level's queue ran dry, and the most loop iterations
+// any one ray took
+constexpr int kProfIters = 4;
+constexpr int kProfActive = kProfIters + 8;
+constexpr int kProfTailIters = kProfActive + 8;
+constexpr int kProfTailActive = kProfTailIters + 8;
+constexpr int kProfMaxVisits = kProfTailActive + 8;
+constexpr int kProfWords = kProfMaxVisits + 8;
 constexpr int kBlock = 256;
+constexpr uint32_t kLeafRing = 512;  // trace: leaf entries per wave in LDS (power of two)
 constexpr int kTraceBlock = 128;  // trace workgroup (LDS stack of kStack words per lane)
 
 }  // namespace rr

@@ -101,16 +101,32 @@ __device__ __forceinline__ void normalize3(float& x, float& y, float& z) {
 
 // Closest-hit traversal, persistent and replenishing (after Aila & Laine,
 // "Understanding the efficiency of ray traversal on GPUs", HPG 2009): every
-// lane owns one ray at a time and advances it one inner node per loop
-// iteration; lanes whose ray has finished take new rays from the level's
-// cursor (one atomic per wave) as soon as a quarter of the wave is idle, so
-// the wave does not wait for its slowest ray.  The per-lane stack lives in
-// LDS with a stride of the block size (entry s of lane t at stk[s * B]).
-template <bool kCount, bool kPhased>
+// lane owns one ray at a time; lanes whose ray has finished take new rays
+// from the level's cursor (one atomic per wave) as soon as A.refill lanes are
+// idle.
+//
+// Each loop iteration is either a node step or a triangle phase, decided for
+// the whole wave.  In a node step every tracing lane visits one inner node:
+// inner children hit by the ray go nearest-first onto its stack (LDS, entry s
+// of lane t at stk[s * B], entries beyond kStack in the workspace), hit leaf
+// children are appended to the wave's leaf ring in LDS.  A triangle phase
+// takes up to 64 ring entries, one per lane, and tests the leaf's triangles
+// for the ray of the lane that appended it; hits meet in a per-lane LDS word
+// holding min over (t, original triangle id), updated with a 64-bit LDS
+// atomic min.  The closest hit is that minimum whatever the order of the
+// tests, and a box is culled only beyond the current minimum, so batching
+// leaves changes speed, never the result.  A lane finishes its ray once its
+// stack is empty and the ring has passed its last entry.
+template <bool kCount>
 __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   __shared__ int32_t lds_stack[kStack * kTraceBlock];
+  __shared__ uint32_t lds_leaf[kTraceBlock / 64][kLeafRing];     // leaf reference
+  __shared__ uint8_t lds_own[kTraceBlock / 64][kLeafRing];       // lane that appended it
+  __shared__ unsigned long long lds_best[kTraceBlock];           // (t bits << 32) | original id
   int32_t* stk = lds_stack + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = threadIdx.x >> 6;
+  const uint32_t wave_base = threadIdx.x - lane;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
   const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
   uint32_t* cursor = A.counters + kCtrWork + A.depth;
@@ -118,23 +134,26 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const float4* __restrict__ tris = A.tris;
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t spill_stride = gridDim.x * blockDim.x;
+  const uint32_t tri_batch = min(max(A.tri_batch, 1u), 64u);
 
   bool valid = false, exhausted = false;
-  bool tri_phase = false;                 // wave-uniform (phased schedule)
   uint32_t pool_next = 0, pool_end = 0;  // wave-uniform: claimed, not yet started rays
-  uint32_t ridx = 0, visits = 0, best_orig = 0;
+  uint32_t ring_head = 0, ring_tail = 0;  // wave-uniform: appended / tested ring entries
+  uint32_t ridx = 0, visits = 0, excl = 0xffffffffu, last_pos = 0;
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0;
   RayBox rb{};
-  int32_t best = -1, excl = -1, cur = 0;
+  int32_t cur = 0;
   int sp = 0;
-  uint32_t tri_i = 0, tri_n = 0;
+  bool trav_done = false;  // stack empty (or visit bound reached)
   uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0;
+  uint64_t cnt_iters = 0, cnt_active = 0, cnt_tail_iters = 0, cnt_tail_active = 0;  // wave-uniform
+  uint32_t cnt_max_visits = 0;
 
   for (;;) {
     // ---- refill idle lanes (wave-uniform decision) from the wave's pool of
     // claimed rays; the pool is refilled A.pool rays at a time with one atomic
     uint64_t idle = __ballot(!valid);
-    if (!exhausted && (!kPhased || !tri_phase) && (uint32_t)__popcll(idle) >= A.refill) {
+    if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
 #pragma unroll 1
       for (int pass = 0; pass < 2 && idle; ++pass) {
         if (pool_next >= pool_end) {
@@ -156,10 +175,11 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           const float4 a = A.in.a[my];
           const float4 b = A.in.b[my];
           const uint32_t m = A.in.m[my];
-          excl = (int32_t)A.in.c[my].w;
+          excl = A.in.c[my].w;
           const uint32_t medium = (m >> 8) & 0xffu;
           const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
           best_t = (A.scans[m >> 16].r_max - a.w) / n_cur;
+          lds_best[threadIdx.x] = ((unsigned long long)__float_as_uint(best_t) << 32) | 0xffffffffull;
           ox = a.x;
           oy = a.y;
           oz = a.z;
@@ -168,12 +188,11 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           dz = b.z;
           ray_box_setup(ox, oy, oz, dx, dy, dz, rb);
           ridx = my;
-          best = -1;
-          best_orig = 0xffffffffu;
           cur = 0;
           sp = 0;
-          tri_n = 0;
           visits = 0;
+          last_pos = ring_head;
+          trav_done = false;
           valid = true;
           if (kCount) ++cnt_rays;
         }
@@ -182,147 +201,173 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         if (pool_next >= pool_end && pool_end >= n_in) exhausted = true;
       }
     }
-    if (__ballot(valid) == 0ull) break;  // only once the level is exhausted
+    const uint64_t live = __ballot(valid);
+    if (live == 0ull) break;  // only once the level is exhausted
+    if (kCount) {
+      ++cnt_iters;
+      cnt_active += (uint64_t)__popcll(live);
+      if (exhausted) {
+        ++cnt_tail_iters;
+        cnt_tail_active += (uint64_t)__popcll(live);
+      }
+    }
 
-    // Two schedules.  Unified: every iteration each lane does one unit of work,
-    // a node visit or a triangle test.  Phased (A.leaf_batch > 0): the wave
-    // alternates node phases, in which a lane that reaches a leaf parks it,
-    // and triangle phases, entered once A.leaf_batch lanes hold a parked leaf
-    // (or no lane can visit nodes), so each phase executes only its own path.
-    if (kPhased && tri_phase) {
-      if (valid && tri_n > 0) {
-        const uint32_t li = tri_i;
-        ++tri_i;
-        --tri_n;
-        if ((int32_t)li != excl) {
-          if (kCount) ++cnt_tris;
+    // ---- node step or triangle phase.  A node step may append up to four
+    // leaves per lane, so it runs only while the ring has room for that.
+    const uint64_t walking = __ballot(valid && !trav_done);
+    const uint32_t queued = ring_head - ring_tail;
+    const bool tri_phase = queued >= tri_batch ||
+                           (queued > 0 && (walking == 0ull || queued + 4u * (uint32_t)__popcll(walking) > kLeafRing));
+    if (tri_phase) {
+      const uint32_t n = min(queued, 64u);
+      const bool take = lane < n;
+      const uint32_t pos = (ring_tail + lane) & (kLeafRing - 1u);
+      const uint32_t ref = take ? lds_leaf[wib][pos] : 0u;
+      const int own = take ? (int)lds_own[wib][pos] : (int)lane;
+      const float rox = __shfl(ox, own), roy = __shfl(oy, own), roz = __shfl(oz, own);
+      const float rdx = __shfl(dx, own), rdy = __shfl(dy, own), rdz = __shfl(dz, own);
+      const uint32_t rexcl = __shfl(excl, own);
+      if (take) {
+        unsigned long long cb = lds_best[wave_base + own];
+        float tmax = __uint_as_float((uint32_t)(cb >> 32));
+        const uint32_t start = leaf_start((int32_t)ref), count = leaf_count((int32_t)ref);
+#pragma unroll 1
+        for (uint32_t k = 0; k < count; ++k) {
+          const uint32_t li = start + k;
           const float4 ta = tris[3 * li + 0];
+          const uint32_t orig = __float_as_uint(ta.w);
+          if (orig == rexcl) continue;
+          if (kCount) ++cnt_tris;
           const float4 e1 = tris[3 * li + 1];
           const float4 e2 = tris[3 * li + 2];
           float t;
-          if (ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
-                      best_t, t)) {
-            const uint32_t orig = __float_as_uint(ta.w);
-            if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
-              best_t = t;
-              best = (int32_t)li;
-              best_orig = orig;
+          if (ray_tri(rox, roy, roz, rdx, rdy, rdz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
+                      tmax, t)) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(t) << 32) | orig;
+            if (key < cb) {
+              atomicMin(&lds_best[wave_base + own], key);
+              cb = key;
+              tmax = t;
             }
           }
         }
-        if (++visits > A.n_nodes + A.n_leaf_tris || (tri_n == 0 && cur == kEmpty && sp == 0)) {
-          A.hits[ridx] = make_uint2(__float_as_uint(best_t), (uint32_t)best);
-          valid = false;
-        }
       }
-      if (__ballot(valid && tri_n > 0) == 0ull) tri_phase = false;
-      continue;
-    }
-    if (valid && !(kPhased && tri_n > 0)) {
-      bool done = false;
-      if (tri_n == 0) {
+      ring_tail += n;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) best_t = __uint_as_float((uint32_t)(lds_best[threadIdx.x] >> 32));
+    } else {
+      uint32_t leaves = 0;  // hit leaf children of this lane's node
+      int32_t lref[4] = {0, 0, 0, 0};
+      if (valid && !trav_done) {
+        // top of the LDS stack, read ahead of the decision to pop so the pop
+        // stays an LDS access (entries beyond kStack come from the workspace)
+        const int32_t top = stk[min(max(sp - 1, 0), kStack - 1) * kTraceBlock];
         if (cur == kEmpty) {
           if (sp > 0) {
             --sp;
-            cur = sp < kStack ? stk[sp * kTraceBlock]
-                              : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
+            cur = sp < kStack ? top : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
           } else {
-            done = true;
+            trav_done = true;
           }
         }
-        if (cur < 0) {  // a leaf: its triangles are tested one per iteration
-          tri_i = leaf_start(cur);
-          tri_n = leaf_count(cur);
-          cur = kEmpty;
-        }
-      }
-      if (!kPhased && tri_n > 0) {
-        const uint32_t li = tri_i;
-        ++tri_i;
-        --tri_n;
-        if ((int32_t)li != excl) {
-          if (kCount) ++cnt_tris;
-          const float4 ta = tris[3 * li + 0];
-          const float4 e1 = tris[3 * li + 1];
-          const float4 e2 = tris[3 * li + 2];
-          float t;
-          if (ray_tri(ox, oy, oz, dx, dy, dz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
-                      best_t, t)) {
-            const uint32_t orig = __float_as_uint(ta.w);
-            if (best < 0 || t < best_t || (t == best_t && orig < best_orig)) {
-              best_t = t;
-              best = (int32_t)li;
-              best_orig = orig;
+        if (!trav_done) {
+          const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+          const float4 w0 = np[0];
+          const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
+          const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
+          const int4 w3 = reinterpret_cast<const int4*>(np)[3];
+          if (kCount) ++cnt_nodes;
+          float tn[4];
+          const uint32_t mask = node4_boxes(w0, w1, w2, w3, rb, best_t, tn);
+          const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
+          // hit inner children far to near, everything else last: 5 compare-exchanges
+          float key[4];
+          int32_t val[4];
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const bool h = (mask >> j) & 1u;
+            const bool inner = h && ref[j] >= 0;
+            if (h && ref[j] < 0) leaves |= 1u << j;
+            lref[j] = ref[j];
+            key[j] = inner ? tn[j] : -INFINITY;
+            val[j] = inner ? ref[j] : kEmpty;
+          }
+  #define RR_CX(i, j)                     \
+    if (key[j] > key[i]) {                \
+      const float tk = key[i];            \
+      key[i] = key[j];                    \
+      key[j] = tk;                        \
+      const int32_t tv = val[i];          \
+      val[i] = val[j];                    \
+      val[j] = tv;                        \
+    }
+          RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
+  #undef RR_CX
+          // the nearest hit inner child is visited next; the h - 1 others are
+          // pushed farthest first.  Where three slots are free in LDS all three
+          // are written unconditionally (slots at or above the new top are
+          // unused); otherwise entry by entry, deeper ones into the workspace.
+          // The builder bounds the worst-case depth by kStack + kSpill.
+          const int h = __popc(mask & ~leaves);
+          if (sp + 3 <= kStack) {
+            stk[(sp + 0) * kTraceBlock] = val[0];
+            stk[(sp + 1) * kTraceBlock] = val[1];
+            stk[(sp + 2) * kTraceBlock] = val[2];
+            sp += h > 1 ? h - 1 : 0;
+          } else {
+  #pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              if (j < h - 1 && sp < kStack + kSpill) {
+                if (sp < kStack)
+                  stk[sp * kTraceBlock] = val[j];
+                else
+                  A.spill[(size_t)(sp - kStack) * spill_stride + gtid] = val[j];
+                ++sp;
+              }
             }
           }
-        }
-      } else if (!done && tri_n == 0) {
-        const float4* np = reinterpret_cast<const float4*>(nodes + cur);
-        const float4 w0 = np[0];
-        const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
-        const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
-        const int4 w3 = reinterpret_cast<const int4*>(np)[3];
-        if (kCount) ++cnt_nodes;
-        float tn[4];
-        const uint32_t mask = node4_boxes(w0, w1, w2, w3, rb, best_t, tn);
-        const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
-        float key[4];
-        int32_t val[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool h = (mask >> j) & 1u;
-          key[j] = h ? tn[j] : INFINITY;
-          val[j] = h ? ref[j] : kEmpty;
-        }
-        // hit children (leaves and inner nodes) near to far: 5 compare-exchanges
-#define RR_CX(i, j)                     \
-  if (key[j] < key[i]) {                \
-    const float tk = key[i];            \
-    key[i] = key[j];                    \
-    key[j] = tk;                        \
-    const int32_t tv = val[i];          \
-    val[i] = val[j];                    \
-    val[j] = tv;                        \
-  }
-        RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
-#undef RR_CX
-        // push the farther ones, nearest of them last; the builder bounds the
-        // worst-case depth by kStack + kSpill
-#pragma unroll
-        for (int j = 3; j >= 1; --j) {
-          if (val[j] != kEmpty && sp < kStack + kSpill) {
-            if (sp < kStack)
-              stk[sp * kTraceBlock] = val[j];
-            else
-              A.spill[(size_t)(sp - kStack) * spill_stride + gtid] = val[j];
-            ++sp;
-          }
-        }
-        cur = val[0];
-        if (kPhased && cur != kEmpty && cur < 0) {  // park the nearest leaf at once
-          tri_i = leaf_start(cur);
-          tri_n = leaf_count(cur);
-          cur = kEmpty;
+          cur = h == 0 ? kEmpty : h == 1 ? val[0] : h == 2 ? val[1] : h == 3 ? val[2] : val[3];
+          // every node is entered at most once per ray; the bound only guards
+          // against a malformed tree
+          if (++visits > A.n_nodes) trav_done = true;
         }
       }
-      // every node and leaf is entered at most once per ray; the bound only
-      // guards against a malformed tree
-      if (++visits > A.n_nodes + A.n_leaf_tris) done = true;
-      if (done) {
-        A.hits[ridx] = make_uint2(__float_as_uint(best_t), (uint32_t)best);
-        valid = false;
+      // hit leaves into the ring, child slot by child slot (all lanes take
+      // part, so the ring head stays the same in every lane)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool want = (leaves >> j) & 1u;
+        const uint64_t m = __ballot(want);
+        if (want) {
+          const uint32_t p = ring_head + (uint32_t)__popcll(m & lanes_below);
+          lds_leaf[wib][p & (kLeafRing - 1u)] = (uint32_t)lref[j];
+          lds_own[wib][p & (kLeafRing - 1u)] = (uint8_t)lane;
+          last_pos = p + 1u;
+        }
+        ring_head += (uint32_t)__popcll(m);
       }
     }
-    if (kPhased) {
-      const uint64_t parked = __ballot(valid && tri_n > 0);
-      const uint64_t walking = __ballot(valid && tri_n == 0);
-      if (parked && ((uint32_t)__popcll(parked) >= A.leaf_batch || walking == 0ull)) tri_phase = true;
+    __builtin_amdgcn_wave_barrier();
+
+    // ---- rays whose traversal and leaf tests are complete
+    if (valid && trav_done && (int32_t)(ring_tail - last_pos) >= 0) {
+      if (kCount) cnt_max_visits = max(cnt_max_visits, visits);
+      const unsigned long long b = lds_best[threadIdx.x];
+      A.hits[ridx] = make_uint2((uint32_t)(b >> 32), (uint32_t)b);
+      valid = false;
     }
   }
   if (kCount) {
     atomicAdd(A.prof + 0, (unsigned long long)cnt_nodes);
     atomicAdd(A.prof + 1, (unsigned long long)cnt_tris);
     atomicAdd(A.prof + 2, (unsigned long long)cnt_rays);
+    atomicMax(A.prof + kProfMaxVisits + A.depth, (unsigned long long)cnt_max_visits);
+    if (lane == 0) {
+      atomicAdd(A.prof + kProfIters + A.depth, (unsigned long long)cnt_iters);
+      atomicAdd(A.prof + kProfActive + A.depth, (unsigned long long)cnt_active);
+      atomicAdd(A.prof + kProfTailIters + A.depth, (unsigned long long)cnt_tail_iters);
+      atomicAdd(A.prof + kProfTailActive + A.depth, (unsigned long long)cnt_tail_active);
+    }
   }
 }
 
@@ -449,8 +494,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
       const DevScan* S = A.scans + scan;
       if (S->records) {
         const size_t nheap = (1u << S->max_b) - 1u;
-        S->records[(size_t)pid * nheap + heap - 1] =
-            hit >= 0 ? (int32_t)__float_as_uint(A.tris[3 * (uint32_t)hit].w) : -1;
+        S->records[(size_t)pid * nheap + heap - 1] = hit >= 0 ? hit : -1;
       }
       if (hit >= 0) {
         if (kCount) ++cnt_hits;
@@ -462,7 +506,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
         const float dx = b.x, dy = b.y, dz = b.z;
         g = b.w;
         const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
-        const float4 ax = A.aux[hit];
+        const float4 ax = A.aux[hit];  // per original triangle
         const uint32_t mat = __float_as_uint(ax.w);
         const DevMaterial M = A.mats[mat];
         const float dn = dot3(dx, dy, dz, ax.x, ax.y, ax.z);
@@ -685,17 +729,10 @@ hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st) {
 
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
   const dim3 g(grid ? grid : 1), b(kTraceBlock);
-  if (a.leaf_batch) {
-    if (a.prof)
-      hipLaunchKernelGGL((k_trace<true, true>), g, b, 0, st, a);
-    else
-      hipLaunchKernelGGL((k_trace<false, true>), g, b, 0, st, a);
-  } else {
-    if (a.prof)
-      hipLaunchKernelGGL((k_trace<true, false>), g, b, 0, st, a);
-    else
-      hipLaunchKernelGGL((k_trace<false, false>), g, b, 0, st, a);
-  }
+  if (a.prof)
+    hipLaunchKernelGGL(k_trace<true>, g, b, 0, st, a);
+  else
+    hipLaunchKernelGGL(k_trace<false>, g, b, 0, st, a);
   return hipGetLastError();
 }
 

@@ -39,8 +39,8 @@ struct alignas(64) Node {
 static_assert(sizeof(Node) == 64, "node layout");
 
 constexpr int kMaxDepth = 32;  // two-wide build: inner-node depth bound
-constexpr int kStack = 32;     // traversal stack entries per lane held in LDS
-constexpr int kSpill = 64;     // further entries per lane in workspace memory
+constexpr int kStack = 20;     // traversal stack entries per lane held in LDS
+constexpr int kSpill = 76;     // further entries per lane in workspace memory
 
 // Four-wide node with quantised child boxes, 64 bytes (four 16-byte loads):
 //   w0 = (origin.x, origin.y, origin.z, exponent bytes ex | ey << 8 | ez << 16)

@@ -327,7 +327,7 @@ def test_autotune_keeps_images(R, ctx):
         assert ms > 0
         assert t["refill_lanes"] in (4, 8, 12, 16, 24, 32, 48)
         assert t["trace_waves_per_cu"] in (8, 12, 16, 20, 24, 32)
-        assert t["pool_rays"] in (64, 128, 256) and t["leaf_batch_lanes"] in (0, 8, 16)
+        assert t["pool_rays"] in (64, 128, 256) and t["tri_batch"] in (16, 32, 48, 64)
         assert R.rr_get_tuning(ctx.handle) == t
         b, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
         torch.cuda.synchronize()
@@ -336,7 +336,7 @@ def test_autotune_keeps_images(R, ctx):
     finally:
         R.rr_set_tuning(ctx.handle, **{k: before[k] for k in
                                        ("refill_lanes", "trace_waves_per_cu", "pool_rays",
-                                        "batch_budget_mb", "leaf_batch_lanes")})
+                                        "batch_budget_mb", "tri_batch")})
         sc.release()
 
 
