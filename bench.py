@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # timed-variant dispatches), scaled by what the same counters read for a
 # plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
 # all of them).  Valid only for the kernel sources it was taken on.
-TRACE_HBM = dict(workload="urban_block_200k", fetch_kib=54229.6, write_kib=21112.2,
+TRACE_HBM = dict(workload="urban_block_200k", fetch_kib=55481.3, write_kib=20666.5,
                  fetch_scale=2.0, write_scale=1.0,
-                 sources_sha256="e0ec3f45f340ba3464c1a7b04a71cd97dc5db049e410d15a25081e77ed08c8b1")
+                 sources_sha256="e11bb16dafc2989039078d6fa64a29fe9152e428a537b975bfe4bdfde3836311")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
@@ -94,8 +94,10 @@ def cpu_baseline(scene, threads: int, n_cols: int):
 
 def bench_trajectory(args):
     """64 poses along a spline through the 2M-triangle scene, each with its
-    own azimuth count and rays per beam (B = 5): one batched call against the
-    same 64 scans issued one rr_radar_scan at a time."""
+    own azimuth count and rays per beam (B = 5).  The launch parameters are
+    autotuned on the first pose; the scans are then run as batched launches
+    (groups bounded by the workspace budget), as HIP graphs of those groups
+    replayed with the same tables, and one rr_radar_scan at a time."""
     import torch
     import paper_2310_03505_amd as R
     import workloads as W
@@ -108,28 +110,52 @@ def bench_trajectory(args):
     imgs = [torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
             for _, p in scans]
     singles = [torch.empty_like(x) for x in imgs]
+    graphed = [torch.empty_like(x) for x in imgs]
+    tuned, tuned_ms = R.rr_autotune(c, s, scans[0][0], scans[0][1], scene.materials, reps=2)
+    log(f"autotuned on pose 0: {tuned} ({tuned_ms:.3f} ms)")
     _, st = R.rr_radar_scan_batch(c, s, scans, scene.materials, images=imgs, stats=True)
     segs = st["segments"]
     steps = max(1, min(args.steps, 3))
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        R.rr_radar_scan_batch(c, s, scans, scene.materials, images=imgs)
-    e1.record()
-    torch.cuda.synchronize()
-    batch_ms = e0.elapsed_time(e1) / steps
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    batch_ms = timed(lambda: R.rr_radar_scan_batch(c, s, scans, scene.materials, images=imgs))
+    # graphs: consecutive groups within the context's workspace budget
+    budget = tuned["batch_budget_mb"] << 20
+    groups, i = [], 0
+    while i < len(scans):
+        j = i + 1
+        while j < len(scans) and R.rr_batch_workspace_query(scans[i:j + 1]) <= budget:
+            j += 1
+        groups.append((i, j))
+        i = j
+    graphs = [R.rr_graph_create(c, s, scans[a:b], scene.materials, images=graphed[a:b])[0]
+              for a, b in groups]
+
+    def replay():
+        for g in graphs:
+            R.rr_graph_launch(g)
+    replay()
+    graph_ms = timed(replay)
+    for g in graphs:
+        R.rr_graph_destroy(g)
     for (pose, p), im in zip(scans, singles):           # warm the single-scan workspace
         R.rr_radar_scan(c, s, pose, p, scene.materials, image=im)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(steps):
+
+    def one_by_one():
         for (pose, p), im in zip(scans, singles):
             R.rr_radar_scan(c, s, pose, p, scene.materials, image=im)
-    e1.record()
-    torch.cuda.synchronize()
-    single_ms = e0.elapsed_time(e1) / steps
+    single_ms = timed(one_by_one)
     same = all(torch.equal(a, b) for a, b in zip(imgs, singles))
+    same_graph = all(torch.equal(a, b) for a, b in zip(imgs, graphed))
     out = {
         "metric": "Mray-segments/s", "value": round(segs / (batch_ms / 1e3) / 1e6, 2),
         "unit": "Mray-segments/s", "n_gpus": 1, "steps": steps, "warmup": 1,
@@ -139,10 +165,13 @@ def bench_trajectory(args):
                    "n_scans": len(scans), "primaries": sum(p["n_azimuth"] * p["rays_per_beam"]
                                                             for _, p in scans),
                    "segments_per_step": segs, "scans_per_s": round(len(scans) / (batch_ms / 1e3), 2),
+                   "tuning": tuned, "groups": len(groups),
+                   "graph_ms_per_step": round(graph_ms, 3),
+                   "graph_mseg_per_s": round(segs / (graph_ms / 1e3) / 1e6, 2),
                    "single_scan_ms_per_step": round(single_ms, 3),
                    "single_scan_mseg_per_s": round(segs / (single_ms / 1e3) / 1e6, 2),
                    "batch_speedup": round(single_ms / batch_ms, 3),
-                   "batch_images_equal_single": same},
+                   "batch_images_equal_single": same, "graph_images_equal_batch": same_graph},
     }
     sc.release()
     ctx.close()
