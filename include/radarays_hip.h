@@ -110,7 +110,8 @@ typedef struct {
   uint32_t max_leaf_size; /* triangles per leaf, 1..16, default 4 */
   uint32_t sah_bins;      /* SAH bins per axis, 4..64, default 16 */
   uint32_t n_threads;     /* host build threads, 0 = all cores */
-  uint32_t reserved;
+  uint32_t split_pct;     /* early split clipping: extra triangle references, in
+                             percent of the triangle count, 0..200 (0 = none) */
 } rr_bvh_options;
 
 typedef struct {
@@ -183,9 +184,13 @@ rr_status rr_bvh_selfcheck(const rr_scene* scene, uint32_t n_rays, uint64_t seed
 rr_status rr_scene_release(rr_context* ctx, rr_scene* scene);
 
 /* ---------------------------------------------------------------- scans */
-/* Exact device bytes one scan with these parameters needs as workspace:
- * two ray queues of N_p * 2^(B-1) rays, the fixed-point accumulator and the
- * counters.  EINVAL if the parameters are out of range. */
+/* Exact device bytes one scan with these parameters needs as workspace in
+ * the default launch mode: two ray queues of N_p * 2^(B-1) rays, the hit
+ * buffer, the fixed-point accumulator, the counters and the traversal-stack
+ * spill area.  With rr_tuning.fused = 1 a context also reserves a child pool
+ * and hit ring per trace wave (about 1.2 GB) in its own workspace; a
+ * caller-provided workspace of this size is then too small (EINVAL).
+ * EINVAL if the parameters are out of range. */
 rr_status rr_workspace_query(const rr_sensor_params* params, size_t* bytes);
 
 /* One polar image (Sec. III-A, III-B).  image_dev receives n_azimuth x n_bins
@@ -291,15 +296,21 @@ typedef struct {
   uint32_t batch_budget_mb; /* workspace budget of one batch group, MiB (>= 64) */
   uint32_t tri_batch;      /* leaves a trace wave queues before it tests their
                              triangles in one step, one leaf per lane (1..64) */
-  uint32_t reserved[3];
+  uint32_t fused;          /* 0: default (2); 1: every bounce level in one
+                             persistent launch, each wave tracing and shading
+                             its own rays' children; 2: one trace and one shade
+                             launch per bounce level */
+  uint32_t shade_batch;    /* fused: finished rays a wave queues before it
+                             shades them in one step (1..64) */
+  uint32_t reserved[1];
 } rr_tuning;
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t);
 rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out);
 
 /* Autotuner: scans the given workload with candidate launch parameters
- * (coordinate descent over refill_lanes, trace_waves_per_cu, pool_rays and
- * tri_batch, each candidate timed with HIP events over `reps` scans
+ * (coordinate descent over refill_lanes, trace_waves_per_cu, pool_rays,
+ * tri_batch, fused and shade_batch, each candidate timed with HIP events over `reps` scans
  * on `stream`), keeps the fastest in the context and returns it in *best
  * with its time per scan.  Every candidate produces the same image. */
 rr_status rr_autotune(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,

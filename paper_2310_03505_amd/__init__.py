@@ -45,7 +45,7 @@ class rr_material(C.Structure):
 
 class rr_bvh_options(C.Structure):
     _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32),
-                ("n_threads", C.c_uint32), ("reserved", C.c_uint32)]
+                ("n_threads", C.c_uint32), ("split_pct", C.c_uint32)]
 
 
 class rr_bvh_info(C.Structure):
@@ -77,7 +77,8 @@ RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
 class rr_tuning(C.Structure):
     _fields_ = [("refill_lanes", C.c_uint32), ("trace_waves_per_cu", C.c_uint32),
                 ("pool_rays", C.c_uint32), ("batch_budget_mb", C.c_uint32),
-                ("tri_batch", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("tri_batch", C.c_uint32), ("fused", C.c_uint32), ("shade_batch", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class rr_server_options(C.Structure):
@@ -231,8 +232,9 @@ def rr_scene_upload(ctx, vertices, indices, tri_material):
     return h
 
 
-def rr_bvh_build(ctx, scene, max_leaf_size: int = 0, sah_bins: int = 0, n_threads: int = 0):
-    opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, 0)
+def rr_bvh_build(ctx, scene, max_leaf_size: int = 0, sah_bins: int = 0, n_threads: int = 0,
+                 split_pct: int = 0):
+    opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, split_pct)
     _check(load_library().rr_bvh_build(ctx, scene, C.byref(opt)), ctx)
 
 
@@ -347,18 +349,26 @@ def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, 
     return images, (_stats_dict(st) if st is not None else None)
 
 
+TUNING_KEYS = ("refill_lanes", "trace_waves_per_cu", "pool_rays", "batch_budget_mb", "tri_batch",
+               "fused", "shade_batch")
+
+
+def _tuning_dict(t) -> dict:
+    return {k: int(getattr(t, k)) for k in TUNING_KEYS}
+
+
 def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0, pool_rays: int = 0,
-                  batch_budget_mb: int = 0, tri_batch: int = 0):
-    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb, tri_batch)
+                  batch_budget_mb: int = 0, tri_batch: int = 0, fused: int = 0,
+                  shade_batch: int = 0):
+    t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb, tri_batch, fused,
+                  shade_batch)
     _check(load_library().rr_set_tuning(ctx, C.byref(t)), ctx)
 
 
 def rr_get_tuning(ctx) -> dict:
     t = rr_tuning()
     _check(load_library().rr_get_tuning(ctx, C.byref(t)), ctx)
-    return dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
-                pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb),
-                tri_batch=int(t.tri_batch))
+    return _tuning_dict(t)
 
 
 def rr_autotune(ctx, scene, pose: dict, params: dict, materials, image=None, reps: int = 5,
@@ -376,9 +386,7 @@ def rr_autotune(ctx, scene, pose: dict, params: dict, materials, image=None, rep
                                       C.byref(make_params(params)), mats, len(materials),
                                       _ptr(image), reps, C.byref(t), C.byref(ms),
                                       _stream_handle(stream)), ctx)
-    return (dict(refill_lanes=int(t.refill_lanes), trace_waves_per_cu=int(t.trace_waves_per_cu),
-                 pool_rays=int(t.pool_rays), batch_budget_mb=int(t.batch_budget_mb),
-                 tri_batch=int(t.tri_batch)), float(ms.value))
+    return _tuning_dict(t), float(ms.value)
 
 
 def rr_graph_create(ctx, scene, scans, materials, images=None):

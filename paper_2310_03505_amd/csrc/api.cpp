@@ -180,11 +180,15 @@ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // lanes whose traversal stack may spill into the workspace: 256 compute
 // units x 32 waves x 64 lanes
 constexpr uint32_t kSpillLanes = 256u * 32u * 64u;
+// fused scan: per-wave child pool and hit ring, for every wave a trace grid
+// can have (kSpillLanes / 64)
+constexpr uint32_t kWqPool = 2048u, kWqHits = 256u;
+constexpr size_t kWqBytes = (size_t)(kSpillLanes / 64u) * (kWqPool + kWqHits) * 64u;
 
 // Levels alternate between two queues; level d of a scan has at most
 // N_p * 2^d rays, and only scans with B > d have a level d.  The hit buffer
 // holds one (t, leaf) pair per ray of the current level.
-void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L) {
+void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool fused) {
   uint64_t level[RR_MAX_BOUNCES] = {};
   L = Layout();
   for (uint32_t i = 0; i < n; ++i) {
@@ -211,6 +215,8 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L) {
   o += align256(8 * cap);
   L.off_spill = o;
   o += align256(sizeof(int32_t) * (size_t)kSpill * kSpillLanes);
+  L.off_wq = o;
+  if (fused) o += align256(kWqBytes);
   for (int q = 0; q < 2; ++q) {
     L.off_q[q][0] = o;
     o += align256(16 * cap);
@@ -243,7 +249,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
               float beam_width_for_mats, uint32_t* counters_host, bool upload) {
   Layout L;
-  make_layout(ps, (uint32_t)scans.size(), L);
+  make_layout(ps, (uint32_t)scans.size(), L, ctx->fused != 0);
   if (ws_bytes < L.total)
     return fail(ctx, RR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
   if (L.cap >= (1ull << 31) || L.n_first >= (1ull << 31))
@@ -292,6 +298,10 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   a.pool = ctx->pool_rays;
   a.tri_batch = ctx->tri_batch;
   a.spill = reinterpret_cast<int32_t*>(ws + L.off_spill);
+  a.wq = reinterpret_cast<float4*>(ws + L.off_wq);
+  a.wq_pool = kWqPool;
+  a.wq_hits = kWqHits;
+  a.shade_batch = ctx->shade_batch;
   const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
   auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
     rr_context::EvPair ev{};
@@ -325,7 +335,15 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     if ((rs = timed_launch(0, 0, [&] { return launch_raygen(a, grid, st); }))) return rs;
   }
   uint64_t level_bound = L.n_first;
-  for (uint32_t d = 0; d < L.max_b; ++d) {
+  if (ctx->fused) {
+    // every level in one persistent launch; each wave keeps its rays' children
+    a.depth = 0;
+    a.in = queue_at(ws, L, 0);
+    uint64_t tblocks = (L.n_first + kTraceBlock - 1) / kTraceBlock;
+    uint32_t tgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
+    if ((rs = timed_launch(1, 0, [&] { return launch_scan(a, tgrid, st); }))) return rs;
+  }
+  for (uint32_t d = 0; d < (ctx->fused ? 0u : L.max_b); ++d) {
     a.depth = d;
     a.in = queue_at(ws, L, d & 1);
     a.out = queue_at(ws, L, (d + 1) & 1);
@@ -491,7 +509,9 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
     if (opt->max_leaf_size) o.max_leaf = opt->max_leaf_size;
     if (opt->sah_bins) o.bins = opt->sah_bins;
     o.threads = opt->n_threads;
+    o.split_pct = opt->split_pct;
   }
+  if (o.split_pct > 200) return fail(ctx, RR_EINVAL, "split_pct out of [0, 200]");
   if (o.max_leaf < 1 || o.max_leaf > 16) return fail(ctx, RR_EINVAL, "max_leaf_size out of [1, 16]");
   if (o.bins < 4 || o.bins > 64) return fail(ctx, RR_EINVAL, "sah_bins out of [4, 64]");
   try {
@@ -602,7 +622,7 @@ static rr_status scan_common(rr_context* ctx, const rr_scene* sc, const rr_pose*
   if (!image) return fail(ctx, RR_EINVAL, "image_dev is NULL");
   DeviceGuard g(ctx->device);
   Layout L;
-  make_layout(&params, 1, L);
+  make_layout(&params, 1, L, ctx->fused != 0);
   if (!ws) {
     if ((s = ensure_ws(ctx, L.total))) return s;
     ws = ctx->ws;
@@ -663,7 +683,7 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
     while (j < n) {
       ps.push_back(&descs[j].params);
       Layout L;
-      make_layout(ps.data(), (uint32_t)ps.size(), L);
+      make_layout(ps.data(), (uint32_t)ps.size(), L, ctx->fused != 0);
       if (L.total > ctx->batch_budget) break;
       ++j;
     }
@@ -675,7 +695,7 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
     std::vector<const rr_sensor_params*> ps;
     for (uint32_t i = gr.first; i < gr.second; ++i) ps.push_back(&descs[i].params);
     Layout L;
-    make_layout(ps.data(), (uint32_t)ps.size(), L);
+    make_layout(ps.data(), (uint32_t)ps.size(), L, ctx->fused != 0);
     need = std::max(need, L.total);
   }
   if ((s = ensure_ws(ctx, need))) return s;
@@ -717,6 +737,10 @@ rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   ctx->trace_waves_per_cu = wc;
   ctx->pool_rays = pr;
   if (t->tri_batch > 64) return fail(ctx, RR_EINVAL, "tri_batch out of [1, 64]");
+  if (t->fused > 2) return fail(ctx, RR_EINVAL, "fused out of [0, 2]");
+  if (t->shade_batch > 64) return fail(ctx, RR_EINVAL, "shade_batch out of [1, 64]");
+  ctx->fused = t->fused == 1 ? 1u : 0u;
+  ctx->shade_batch = t->shade_batch ? t->shade_batch : 64u;
   ctx->tri_batch = t->tri_batch ? t->tri_batch : 32u;
   return RR_OK;
 }
@@ -728,6 +752,8 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
   out->trace_waves_per_cu = ctx->trace_waves_per_cu;
   out->pool_rays = ctx->pool_rays;
   out->tri_batch = ctx->tri_batch;
+  out->fused = ctx->fused ? 1u : 2u;
+  out->shade_batch = ctx->shade_batch;
   out->batch_budget_mb = (uint32_t)(ctx->batch_budget >> 20);
   return RR_OK;
 }

@@ -33,6 +33,8 @@ struct rr_context {
   uint32_t trace_waves_per_cu = 20;
   uint32_t pool_rays = 64;
   uint32_t tri_batch = 32;  // queued leaves that start a triangle phase
+  uint32_t fused = 0;       // 1: all bounce levels in one persistent launch
+  uint32_t shade_batch = 64;  // fused: finished rays that start a shade phase
   size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group
 };
 
@@ -64,7 +66,7 @@ namespace rr {
 
 // Workspace layout of a set of scans (see api.cpp).
 struct Layout {
-  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0;
+  size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0, off_wq = 0;
   size_t off_q[2][4] = {};
   size_t total = 0;
   uint64_t cap = 0;       // rays per queue
@@ -84,7 +86,8 @@ struct DeviceGuard {
   }
 };
 
-void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L);
+// fused: add the per-wave child pools and hit rings of the one-launch mode
+void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool fused = false);
 void make_scan(const rr_pose& pose, const rr_sensor_params& p, DevScan& s);
 rr_status check_params(rr_context* ctx, const rr_sensor_params* p);
 rr_status check_pose(rr_context* ctx, const rr_pose* q);

@@ -8,6 +8,15 @@
 // kMaxDepth - 1 by switching to object-median splits when the remaining
 // depth budget gets tight.  The tree is then collapsed into four-wide nodes
 // with 8-bit child boxes quantised outward in the node's frame.
+//
+// Optionally, before the build, the references with the largest boxes are
+// split (early split clipping, Ernst & Greiner, "Early split clipping for
+// bounding volume hierarchies", RT 2007): a reference is cut at the middle of
+// its box's longest axis and each half is bounded by the part of the
+// triangle inside it, so long diagonal triangles (walls, ground) get several
+// tight boxes instead of one loose one.  A triangle may then sit in several
+// leaves; the closest hit is the same, since every test of it gives the same
+// (t, original id).
 #include "bvh.h"
 
 #include <algorithm>
@@ -16,6 +25,7 @@
 #include <cstring>
 #include <future>
 #include <memory>
+#include <queue>
 #include <thread>
 
 namespace rr {
@@ -49,6 +59,52 @@ struct Ref {
   float c[3];
   uint32_t id;
 };
+
+// Bounds of the part of triangle (p0, p1, p2) inside box r, rounded outward
+// to float; false if that part is empty.  Sutherland-Hodgman in float64.
+bool clipped_bounds(const double p[3][3], const double rlo[3], const double rhi[3], Box& out) {
+  double poly[16][3], tmp[16][3];
+  int n = 3;
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) poly[i][a] = p[i][a];
+  for (int a = 0; a < 3 && n > 0; ++a) {
+    for (int side = 0; side < 2 && n > 0; ++side) {
+      const double c = side ? rhi[a] : rlo[a];
+      auto inside = [&](const double* v) { return side ? v[a] <= c : v[a] >= c; };
+      int m = 0;
+      for (int i = 0; i < n; ++i) {
+        const double* u = poly[i];
+        const double* v = poly[(i + 1) % n];
+        const bool iu = inside(u), iv = inside(v);
+        if (iu && m < 16) {
+          for (int q = 0; q < 3; ++q) tmp[m][q] = u[q];
+          ++m;
+        }
+        if (iu != iv && m < 16) {
+          const double s = (c - u[a]) / (v[a] - u[a]);
+          for (int q = 0; q < 3; ++q) tmp[m][q] = u[q] + s * (v[q] - u[q]);
+          tmp[m][a] = c;
+          ++m;
+        }
+      }
+      n = m;
+      for (int i = 0; i < n; ++i)
+        for (int q = 0; q < 3; ++q) poly[i][q] = tmp[i][q];
+    }
+  }
+  if (n == 0) return false;
+  out = Box();
+  for (int i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) {
+      float lo = (float)poly[i][a], hi = lo;
+      if ((double)lo > poly[i][a]) lo = std::nextafter(lo, -INFINITY);
+      if ((double)hi < poly[i][a]) hi = std::nextafter(hi, INFINITY);
+      out.lo[a] = std::min(out.lo[a], lo);
+      out.hi[a] = std::max(out.hi[a], hi);
+    }
+  }
+  return true;
+}
 
 struct BNode {
   Box box;
@@ -203,16 +259,21 @@ struct Flattener4 {
       return 0;
     }
     uint32_t start = (uint32_t)(out.tris.size() / 3);
+    uint32_t kept = 0;
     for (uint32_t i = 0; i < b->count; ++i) {
       uint32_t id = refs[b->begin + i].id;
+      bool dup = false;  // split references of one triangle in the same leaf
+      for (uint32_t k = 0; k < i; ++k) dup = dup || refs[b->begin + k].id == id;
+      if (dup) continue;
+      ++kept;
       out.tris.push_back(tri3[3 * id + 0]);
       out.tris.push_back(tri3[3 * id + 1]);
       out.tris.push_back(tri3[3 * id + 2]);
     }
     out.n_leaves++;
-    if (root_area > 0.0) out.sah_cost += b->box.area() / root_area * b->count;
-    *ref = leaf_ref_encode(start, b->count);
-    *count = b->count;
+    if (root_area > 0.0) out.sah_cost += b->box.area() / root_area * kept;
+    *ref = leaf_ref_encode(start, kept);
+    *count = kept;
     return 0;
   }
 
@@ -356,6 +417,76 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
     refs.push_back(r);
   }
   out.n_hittable = (uint32_t)refs.size();
+  if (opt.split_pct > 0 && !refs.empty()) {
+    // largest boxes first; a reference is split while the budget lasts and
+    // its box is larger than the mean triangle box
+    double mean = 0.0;
+    for (const Ref& r : refs) mean += r.box.area();
+    mean /= (double)refs.size();
+    const size_t budget = refs.size() + (size_t)((uint64_t)refs.size() * std::min(opt.split_pct, 200u) / 100u);
+    struct Cell {
+      double lo[3], hi[3];
+    };
+    std::vector<Cell> region(refs.size());  // the cell each reference is clipped to
+    for (size_t i = 0; i < refs.size(); ++i)
+      for (int a = 0; a < 3; ++a) {
+        region[i].lo[a] = refs[i].box.lo[a];
+        region[i].hi[a] = refs[i].box.hi[a];
+      }
+    auto cmp = [&](uint32_t x, uint32_t y) {
+      const double ax = refs[x].box.area(), ay = refs[y].box.area();
+      return ax < ay || (ax == ay && x > y);
+    };
+    std::priority_queue<uint32_t, std::vector<uint32_t>, decltype(cmp)> heap(cmp);
+    for (uint32_t i = 0; i < (uint32_t)refs.size(); ++i) heap.push(i);
+    while (refs.size() < budget && !heap.empty()) {
+      const uint32_t i = heap.top();
+      if (!(refs[i].box.area() > mean)) break;
+      heap.pop();
+      const uint32_t id = refs[i].id;
+      double p[3][3];
+      for (int v = 0; v < 3; ++v) {
+        const float* q = V + 3 * (size_t)F[3 * (size_t)id + v];
+        for (int a = 0; a < 3; ++a) p[v][a] = q[a];
+      }
+      const Box tb = refs[i].box;
+      int ax = 0;
+      for (int a = 1; a < 3; ++a)
+        if (tb.hi[a] - tb.lo[a] > tb.hi[ax] - tb.lo[ax]) ax = a;
+      const double c = 0.5 * ((double)tb.lo[ax] + (double)tb.hi[ax]);
+      Cell lc, rc;
+      for (int a = 0; a < 3; ++a) {
+        lc.lo[a] = rc.lo[a] = std::max(region[i].lo[a], (double)tb.lo[a]);
+        lc.hi[a] = rc.hi[a] = std::min(region[i].hi[a], (double)tb.hi[a]);
+      }
+      lc.hi[ax] = c;
+      rc.lo[ax] = c;
+      Box lb, rb;
+      const bool hl = clipped_bounds(p, lc.lo, lc.hi, lb), hr = clipped_bounds(p, rc.lo, rc.hi, rb);
+      if (!hl || !hr) continue;  // degenerate cut: keep the reference as it is
+      for (int a = 0; a < 3; ++a) {  // never wider than the reference itself
+        lb.lo[a] = std::max(lb.lo[a], tb.lo[a]);
+        lb.hi[a] = std::min(lb.hi[a], tb.hi[a]);
+        rb.lo[a] = std::max(rb.lo[a], tb.lo[a]);
+        rb.hi[a] = std::min(rb.hi[a], tb.hi[a]);
+      }
+      // the two cells share the cut exactly (float64), so together they keep
+      // every point of the triangle the parent cell held
+      Ref r2 = refs[i];
+      refs[i].box = lb;
+      r2.box = rb;
+      for (int a = 0; a < 3; ++a) {
+        refs[i].c[a] = 0.5f * (lb.lo[a] + lb.hi[a]);
+        r2.c[a] = 0.5f * (rb.lo[a] + rb.hi[a]);
+      }
+      region[i] = lc;
+      refs.push_back(r2);
+      region.push_back(rc);
+      heap.push(i);
+      heap.push((uint32_t)refs.size() - 1);
+    }
+  }
+  out.n_refs = (uint32_t)refs.size();
   out.pad = mag * (1.0f / 262144.0f);  // 2^-18 of the largest coordinate
   for (int a = 0; a < 3; ++a) {
     out.lo[a] = scene.empty() ? 0.0f : scene.lo[a];
@@ -398,8 +529,8 @@ inline void leaf_test(const BuiltBvh& b, uint32_t start, uint32_t count, const f
                       uint32_t& best_orig) {
   for (uint32_t k = 0; k < count; ++k) {
     uint32_t li = start + k;
-    if ((int32_t)li == excl) continue;
     const float4& a = b.tris[3 * (size_t)li + 0];
+    if ((int32_t)fbits(a.w) == excl) continue;
     const float4& e1 = b.tris[3 * (size_t)li + 1];
     const float4& e2 = b.tris[3 * (size_t)li + 2];
     float t;
@@ -503,7 +634,7 @@ uint64_t bvh_selfcheck(const BuiltBvh& b, uint32_t n_rays, uint64_t seed) {
     d[0] = (float)(x / q);
     d[1] = (float)(y / q);
     d[2] = (float)(z / q);
-    int32_t excl = (nl && (r & 3) == 0) ? (int32_t)(next() * nl) : -1;
+    int32_t excl = (nl && (r & 3) == 0) ? (int32_t)fbits(b.tris[3 * (size_t)(next() * nl)].w) : -1;
     float ta, tb;
     int32_t ha = host_traverse(b, o, d, tmax, excl, &ta);
     int32_t hb = host_brute(b, o, d, tmax, excl, &tb);

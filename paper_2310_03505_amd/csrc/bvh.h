@@ -13,6 +13,7 @@ struct BvhBuildOptions {
   uint32_t max_leaf = 4;
   uint32_t bins = 16;
   uint32_t threads = 0;
+  uint32_t split_pct = 0;  // early split clipping budget, percent of the triangles
 };
 
 struct BuiltBvh {
@@ -21,6 +22,7 @@ struct BuiltBvh {
   std::vector<float4> aux;        // 1 per scene triangle, original order: (unit normal, material bits)
   uint32_t n_tris = 0;            // triangles in the scene
   uint32_t n_hittable = 0;        // non-degenerate triangles in the leaves
+  uint32_t n_refs = 0;            // triangle references in the leaves (>= n_hittable)
   uint32_t n_leaves = 0;
   uint32_t max_depth = 0;         // deepest four-wide inner node (root = 0)
   uint32_t max_depth2 = 0;        // deepest node of the two-wide build tree
@@ -35,8 +37,9 @@ struct BuiltBvh {
 void build_bvh(const float* vertices, const uint32_t* indices, uint32_t nt,
                const uint16_t* tri_material, const BvhBuildOptions& opt, BuiltBvh& out);
 
-// Closest hit through the hierarchy on the host (the same traversal order
-// and box test the GPU kernel uses).  Returns the leaf index or -1.
+// Closest hit through the hierarchy on the host (the same box test the GPU
+// kernel uses).  Returns the leaf index or -1; excl is an original triangle
+// id that is never hit.
 int32_t host_traverse(const BuiltBvh& b, const float o[3], const float d[3], float tmax,
                       int32_t excl_leaf, float* t_out);
 

@@ -95,7 +95,7 @@ rr_status rr_graph_create(rr_context* ctx, const rr_scene* sc, const rr_scan_des
   }
   for (uint32_t i = 0; i < n; ++i) ps[i] = &g->params[i];
   Layout L;
-  make_layout(ps.data(), n, L);
+  make_layout(ps.data(), n, L, ctx->fused != 0);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->ws), L.total);
   if (e != hipSuccess) {
     graph_free(g);
@@ -216,6 +216,8 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   static const uint32_t kWaves[] = {8, 12, 16, 20, 24, 32};
   static const uint32_t kPool[] = {64, 128, 256};
   static const uint32_t kTriBatch[] = {16, 32, 48, 64};
+  static const uint32_t kFused[] = {1, 2};  // one launch per scan, one per level
+  static const uint32_t kShadeBatch[] = {16, 32, 64};
   struct Axis {
     const uint32_t* v;
     size_t n;
@@ -223,7 +225,9 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   } axes[] = {{kRefill, 7, &rr_tuning::refill_lanes},
               {kWaves, 6, &rr_tuning::trace_waves_per_cu},
               {kPool, 3, &rr_tuning::pool_rays},
-              {kTriBatch, 4, &rr_tuning::tri_batch}};
+              {kTriBatch, 4, &rr_tuning::tri_batch},
+              {kFused, 2, &rr_tuning::fused},
+              {kShadeBatch, 3, &rr_tuning::shade_batch}};
   double inc = 0.0;
   s = measure(cur, inc);
   for (int pass = 0; pass < 3 && !s; ++pass) {

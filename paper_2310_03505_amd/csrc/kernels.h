@@ -35,6 +35,10 @@ struct LevelArgs {
   uint32_t pool;      // trace: rays a wave claims per atomic
   uint32_t tri_batch;   // trace: queued leaves that start a triangle phase (1..64)
   int32_t* spill;     // trace: stack entries beyond kStack, kSpill per lane (lane-major)
+  float4* wq;         // fused scan: per-wave child pool and hit ring (4 float4 per entry)
+  uint32_t wq_pool;   // fused scan: child-pool entries per wave
+  uint32_t wq_hits;   // fused scan: hit-ring entries per wave (power of two, >= 128)
+  uint32_t shade_batch;  // fused scan: finished rays that start a shade phase (1..64)
   uint32_t* counters;
   unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)
 };
@@ -50,6 +54,8 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st);
+// All bounce levels in one persistent launch (primaries from queue `in`).
+hipError_t launch_scan(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_finalize(const DevScan* scans, uint32_t n_scans, const unsigned long long* acc,
                            uint32_t max_cells, hipStream_t st);
 
@@ -62,8 +68,10 @@ constexpr int kProfActive = kProfIters + 8;
 constexpr int kProfTailIters = kProfActive + 8;
 constexpr int kProfTailActive = kProfTailIters + 8;
 constexpr int kProfMaxVisits = kProfTailActive + 8;
-constexpr int kProfWords = kProfMaxVisits + 8;
+constexpr int kProfPoolMax = kProfMaxVisits + 8;  // fused scan: largest child pool of a wave
+constexpr int kProfWords = kProfPoolMax + 1;
 constexpr int kBlock = 256;
+constexpr uint32_t kMaxLevels = 8;   // bounce levels (interactions per path) at most
 constexpr uint32_t kLeafRing = 512;  // trace: leaf entries per wave in LDS (power of two)
 constexpr int kTraceBlock = 128;  // trace workgroup (LDS stack of kStack words per lane)
 

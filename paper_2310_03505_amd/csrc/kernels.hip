@@ -443,6 +443,143 @@ __global__ void __launch_bounds__(kBlock) k_raygen(LevelArgs A) {
   }
 }
 
+// ---------------------------------------------------------------- interaction
+// What the interaction at one hit produces (Sec. III-A): the return to bin
+// and up to two children.
+struct Shaded {
+  bool has_q = false, has_r = false, has_t = false;
+  uint32_t cell = 0;              // accumulator cell of the return
+  unsigned long long qv = 0;      // its fixed-point energy
+  float range = 0.0f, g = 1.0f;   // one-way optical path at the hit; receive gain
+  float rox = 0, roy = 0, roz = 0, rdx = 0, rdy = 0, rdz = 0;  // reflected child
+  float tox = 0, toy = 0, toz = 0, tdx = 0, tdy = 0, tdz = 0;  // refracted child
+  double e_refl = 0.0, e_refr = 0.0;
+  uint32_t pid = 0, r_meta = 0, t_meta = 0;
+  int32_t hit = -1;
+};
+
+// Interaction of ray (a, b, c, m) with its closest hit (t bits, original
+// triangle id, -1 for a miss): the record, the Snell/Fresnel split (float64
+// energies), the standard-BRDF return over the beam window (Eq. 3-5), the
+// range bin (Sec. III-B) and the two children with offset origins.  The
+// bounce depth is that of the ray's heap id.
+__device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, const float4 b, const uint4 c,
+                                          uint32_t m, uint32_t t_bits, int32_t hit, Shaded& o) {
+  const uint32_t heap = m & 0xffu;
+  const uint32_t medium = (m >> 8) & 0xffu;
+  const uint32_t scan = m >> 16;
+  const uint32_t depth = 31u - (uint32_t)__clz(heap);
+  o.pid = c.z;
+  o.hit = hit;
+  const DevScan* S = A.scans + scan;
+  if (S->records) {
+    const size_t nheap = (1u << S->max_b) - 1u;
+    S->records[(size_t)o.pid * nheap + heap - 1] = hit >= 0 ? hit : -1;
+  }
+  if (hit < 0) return;
+  const float t = __uint_as_float(t_bits);
+  const double E = __hiloint2double((int)c.y, (int)c.x);
+  const float ox = a.x, oy = a.y, oz = a.z, L = a.w;
+  const float dx = b.x, dy = b.y, dz = b.z;
+  o.g = b.w;
+  const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
+  const float4 ax = A.aux[hit];  // per original triangle
+  const uint32_t mat = __float_as_uint(ax.w);
+  const DevMaterial M = A.mats[mat];
+  const float dn = dot3(dx, dy, dz, ax.x, ax.y, ax.z);
+  const bool entering = dn < 0.0f;
+  const float nfx = entering ? ax.x : -ax.x;
+  const float nfy = entering ? ax.y : -ax.y;
+  const float nfz = entering ? ax.z : -ax.z;
+  const float dnf = dot3(dx, dy, dz, nfx, nfy, nfz);
+  const float cosi = -dnf;
+  const float k2 = 2.0f * dnf;
+  o.rdx = dx - k2 * nfx;
+  o.rdy = dy - k2 * nfy;
+  o.rdz = dz - k2 * nfz;
+  normalize3(o.rdx, o.rdy, o.rdz);
+  double R, T;
+  const double ci = (double)cosi;
+  bool refract = false;
+  uint32_t t_medium = kAir;
+  if (M.kind == 0u) {
+    const float n1 = n_cur, n2 = entering ? M.n : 1.0f;
+    const float eta = n1 / n2;
+    const float kappa = 1.0f - (eta * eta) * (1.0f - cosi * cosi);
+    if (kappa < 0.0f) {
+      R = 1.0;
+      T = 0.0;
+    } else {
+      const float cost = sqrtf(kappa);
+      const float aa = eta * cosi - cost;
+      const float ex = eta * dx, ey = eta * dy, ez = eta * dz;
+      o.tdx = ex + aa * nfx;
+      o.tdy = ey + aa * nfy;
+      o.tdz = ez + aa * nfz;
+      normalize3(o.tdx, o.tdy, o.tdz);
+      refract = true;
+      t_medium = entering ? mat : kAir;
+      const double N1 = n1, N2 = n2;
+      const double e = N1 / N2;
+      const double k64 = 1.0 - e * e * (1.0 - ci * ci);
+      const double ct = sqrt(k64 > 0.0 ? k64 : 0.0);
+      const double dsum = N1 * ci + N2 * ct, psum = N2 * ci + N1 * ct;
+      if (dsum == 0.0 || psum == 0.0) {
+        R = 1.0;
+      } else {
+        const double rs = (N1 * ci - N2 * ct) / dsum;
+        const double rp = (N2 * ci - N1 * ct) / psum;
+        R = 0.5 * (rs * rs + rp * rp);
+      }
+      T = 1.0 - R;
+    }
+  } else {
+    R = (double)M.refl;
+    T = 0.0;
+  }
+  double w;
+  if (S->flags & 8u) {
+    w = 1.0;
+  } else {
+    double cw = 2.0 * ci * ci - 1.0;
+    if (cw < 0.0) cw = 0.0;
+    w = M.a + M.beta * cw + M.s * pow(cw, (double)M.C);
+    w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+  }
+  const double e_ret = E * R * w;
+  o.range = L + n_cur * t;
+  const float q = o.range / S->bin_size;
+  if (q < (float)S->n_bins) {
+    const uint32_t bin = (uint32_t)q;
+    o.qv = __double2ull_rn(e_ret * (double)o.g * kFixedScale);
+    if (o.qv) {
+      const uint32_t k = o.pid / S->n_s;
+      o.cell = (uint32_t)(S->acc_base + (uint64_t)k * S->n_bins + bin);
+      o.has_q = true;
+    }
+  }
+  if (depth + 1 < S->max_b) {
+    const double ecut = (double)S->e_cut;
+    o.e_refl = E * R - e_ret;
+    o.e_refr = refract ? E * T : 0.0;
+    const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
+    if (o.e_refl > ecut) {
+      o.has_r = true;
+      o.rox = offset1(px, nfx);
+      o.roy = offset1(py, nfy);
+      o.roz = offset1(pz, nfz);
+    }
+    if (refract && o.e_refr > ecut) {
+      o.has_t = true;
+      o.tox = offset1(px, -nfx);
+      o.toy = offset1(py, -nfy);
+      o.toz = offset1(pz, -nfz);
+    }
+  }
+  o.r_meta = (scan << 16) | (medium << 8) | (2u * heap);
+  o.t_meta = (scan << 16) | (t_medium << 8) | (2u * heap + 1u);
+}
+
 // Interaction at the hit of every ray of the level (Sec. III-A): Snell and
 // Fresnel split, the retrace return through the beam window of the standard
 // BRDF, range binning (Sec. III-B) and the two children.
@@ -472,134 +609,18 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
   for (uint32_t base = begin; base < end; base += kBlock) {
     const uint32_t idx = base + threadIdx.x;
     const bool active = idx < end;
-    bool has_r = false, has_t = false;
-    float rdx = 0, rdy = 0, rdz = 0, tdx = 0, tdy = 0, tdz = 0;
-    float rox = 0, roy = 0, roz = 0, tox = 0, toy = 0, toz = 0;
-    double e_refl = 0.0, e_refr = 0.0;
-    float range = 0.0f, g = 1.0f;
-    uint32_t pid = 0, heap = 1, medium = kAir, scan = 0, t_medium = kAir;
-    int32_t hit = -1;
-    bool has_q = false;            // a return to bin
-    unsigned long long qv = 0;     // its fixed-point energy
-    uint32_t cell = 0;             // its accumulator cell
+    Shaded o;
     if (active) {
       const uint2 h = A.hits[idx];
-      const uint32_t m = A.in.m[idx];
-      heap = m & 0xffu;
-      medium = (m >> 8) & 0xffu;
-      scan = m >> 16;
-      const uint4 c = A.in.c[idx];
-      pid = c.z;
-      hit = (int32_t)h.y;
-      const DevScan* S = A.scans + scan;
-      if (S->records) {
-        const size_t nheap = (1u << S->max_b) - 1u;
-        S->records[(size_t)pid * nheap + heap - 1] = hit >= 0 ? hit : -1;
-      }
-      if (hit >= 0) {
-        if (kCount) ++cnt_hits;
-        const float t = __uint_as_float(h.x);
-        const float4 a = A.in.a[idx];
-        const float4 b = A.in.b[idx];
-        const double E = __hiloint2double((int)c.y, (int)c.x);
-        const float ox = a.x, oy = a.y, oz = a.z, L = a.w;
-        const float dx = b.x, dy = b.y, dz = b.z;
-        g = b.w;
-        const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
-        const float4 ax = A.aux[hit];  // per original triangle
-        const uint32_t mat = __float_as_uint(ax.w);
-        const DevMaterial M = A.mats[mat];
-        const float dn = dot3(dx, dy, dz, ax.x, ax.y, ax.z);
-        const bool entering = dn < 0.0f;
-        const float nfx = entering ? ax.x : -ax.x;
-        const float nfy = entering ? ax.y : -ax.y;
-        const float nfz = entering ? ax.z : -ax.z;
-        const float dnf = dot3(dx, dy, dz, nfx, nfy, nfz);
-        const float cosi = -dnf;
-        const float k2 = 2.0f * dnf;
-        rdx = dx - k2 * nfx;
-        rdy = dy - k2 * nfy;
-        rdz = dz - k2 * nfz;
-        normalize3(rdx, rdy, rdz);
-        double R, T;
-        const double ci = (double)cosi;
-        bool refract = false;
-        if (M.kind == 0u) {
-          const float n1 = n_cur, n2 = entering ? M.n : 1.0f;
-          const float eta = n1 / n2;
-          const float kappa = 1.0f - (eta * eta) * (1.0f - cosi * cosi);
-          if (kappa < 0.0f) {
-            R = 1.0;
-            T = 0.0;
-          } else {
-            const float cost = sqrtf(kappa);
-            const float aa = eta * cosi - cost;
-            const float ex = eta * dx, ey = eta * dy, ez = eta * dz;
-            tdx = ex + aa * nfx;
-            tdy = ey + aa * nfy;
-            tdz = ez + aa * nfz;
-            normalize3(tdx, tdy, tdz);
-            refract = true;
-            t_medium = entering ? mat : kAir;
-            const double N1 = n1, N2 = n2;
-            const double e = N1 / N2;
-            const double k64 = 1.0 - e * e * (1.0 - ci * ci);
-            const double ct = sqrt(k64 > 0.0 ? k64 : 0.0);
-            const double dsum = N1 * ci + N2 * ct, psum = N2 * ci + N1 * ct;
-            if (dsum == 0.0 || psum == 0.0) {
-              R = 1.0;
-            } else {
-              const double rs = (N1 * ci - N2 * ct) / dsum;
-              const double rp = (N2 * ci - N1 * ct) / psum;
-              R = 0.5 * (rs * rs + rp * rp);
-            }
-            T = 1.0 - R;
-          }
-        } else {
-          R = (double)M.refl;
-          T = 0.0;
-        }
-        double w;
-        if (S->flags & 8u) {
-          w = 1.0;
-        } else {
-          double cw = 2.0 * ci * ci - 1.0;
-          if (cw < 0.0) cw = 0.0;
-          w = M.a + M.beta * cw + M.s * pow(cw, (double)M.C);
-          w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
-        }
-        const double e_ret = E * R * w;
-        range = L + n_cur * t;
-        const float q = range / S->bin_size;
-        if (q < (float)S->n_bins) {
-          const uint32_t bin = (uint32_t)q;
-          qv = __double2ull_rn(e_ret * (double)g * kFixedScale);
-          if (qv) {
-            const uint32_t k = pid / S->n_s;
-            cell = (uint32_t)(S->acc_base + (uint64_t)k * S->n_bins + bin);
-            has_q = true;
-          }
-        }
-        if (A.depth + 1 < S->max_b) {
-          const double ecut = (double)S->e_cut;
-          e_refl = E * R - e_ret;
-          e_refr = refract ? E * T : 0.0;
-          const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
-          if (e_refl > ecut) {
-            has_r = true;
-            rox = offset1(px, nfx);
-            roy = offset1(py, nfy);
-            roz = offset1(pz, nfz);
-          }
-          if (refract && e_refr > ecut) {
-            has_t = true;
-            tox = offset1(px, -nfx);
-            toy = offset1(py, -nfy);
-            toz = offset1(pz, -nfz);
-          }
-        }
-      }
+      const int32_t hit = (int32_t)h.y;
+      const float4 a = hit >= 0 ? A.in.a[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      const float4 b = hit >= 0 ? A.in.b[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      shade_hit(A, a, b, A.in.c[idx], A.in.m[idx], h.x, hit, o);
+      if (kCount && hit >= 0) ++cnt_hits;
     }
+    const bool has_q = o.has_q, has_r = o.has_r, has_t = o.has_t;
+    const uint32_t cell = o.cell;
+    const unsigned long long qv = o.qv;
     // ---- return into the block's table (global atomic if its probe fails)
     if (has_q) {
       uint32_t h = (cell * 2654435761u) >> (32 - kHashBits);
@@ -638,16 +659,16 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
     if (has_r) {
       const uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
       if (slot < A.cap)
-        put_ray(A.out, slot, rox, roy, roz, range, rdx, rdy, rdz, g, e_refl, pid, (uint32_t)hit,
-                (scan << 16) | (medium << 8) | (2u * heap));
+        put_ray(A.out, slot, o.rox, o.roy, o.roz, o.range, o.rdx, o.rdy, o.rdz, o.g, o.e_refl, o.pid,
+                (uint32_t)o.hit, o.r_meta);
       else
         atomicOr(A.counters + kCtrOverflow, 1u);
     }
     if (has_t) {
       const uint32_t slot = ob + nr + (uint32_t)__popcll(mt & lanes_below);
       if (slot < A.cap)
-        put_ray(A.out, slot, tox, toy, toz, range, tdx, tdy, tdz, g, e_refr, pid, (uint32_t)hit,
-                (scan << 16) | (t_medium << 8) | (2u * heap + 1u));
+        put_ray(A.out, slot, o.tox, o.toy, o.toz, o.range, o.tdx, o.tdy, o.tdz, o.g, o.e_refr, o.pid,
+                (uint32_t)o.hit, o.t_meta);
       else
         atomicOr(A.counters + kCtrOverflow, 1u);
     }
@@ -657,6 +678,339 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
   for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock)
     if (h_key[i] != kHashEmpty) atomicAdd(A.acc + h_key[i], h_val[i]);
   if (kCount) atomicAdd(A.prof + 3, (unsigned long long)cnt_hits);
+}
+
+// ---------------------------------------------------------------- fused scan
+// All bounce levels in one persistent launch.  Each wave runs its own
+// wavefront loop over three kinds of step, chosen for the whole wave:
+//   node step      every tracing lane visits one inner node (as k_trace);
+//   triangle phase up to 64 queued leaves, one per lane (as k_trace);
+//   shade phase    up to 64 finished rays from the wave's hit ring, one per
+//                  lane: the interaction, the return added into the image
+//                  accumulator with a 64-bit atomic, the children pushed on
+//                  the wave's child pool.
+// Idle lanes take children from the pool (last in, first out) and only when
+// it is empty new primaries from the level-0 queue, so lanes stay busy across
+// levels and the only tail is the end of the scan.  The hit ring and child
+// pool are private to the wave (workspace memory, written and read by the
+// same wave, ordered with workgroup-scope fences), so waves never wait on
+// each other.  Every ray is traced and shaded exactly as in the
+// level-by-level kernels, so the images are identical.
+template <bool kCount>
+__global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
+  __shared__ int32_t lds_stack[kStack * kTraceBlock];
+  __shared__ uint32_t lds_leaf[kTraceBlock / 64][kLeafRing];
+  __shared__ uint8_t lds_own[kTraceBlock / 64][kLeafRing];
+  __shared__ unsigned long long lds_best[kTraceBlock];
+  int32_t* stk = lds_stack + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = threadIdx.x >> 6;
+  const uint32_t wave_base = threadIdx.x - lane;
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+  const uint32_t n_in = min(A.counters[kCtrCount], A.cap);
+  uint32_t* cursor = A.counters + kCtrWork;
+  const Node4* __restrict__ nodes = A.nodes;
+  const float4* __restrict__ tris = A.tris;
+  const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t spill_stride = gridDim.x * blockDim.x;
+  const uint32_t tri_batch = min(max(A.tri_batch, 1u), 64u);
+  const uint32_t shade_batch = min(max(A.shade_batch, 1u), 64u);
+  const uint32_t wave_id = blockIdx.x * (kTraceBlock / 64) + wib;
+  // wave-private child pool (wq_pool entries) and hit ring (wq_hits, a power
+  // of two), four float4 per entry: (o, L), (d, g), (E lo, E hi, pid, excl),
+  // (meta, t bits, hit, 0)
+  float4* const pool = A.wq + (size_t)wave_id * (A.wq_pool + A.wq_hits) * 4u;
+  float4* const hring = pool + (size_t)A.wq_pool * 4u;
+
+  bool valid = false, exhausted = false;
+  uint32_t pool_next = 0, pool_end = 0;     // wave-uniform: claimed primaries
+  uint32_t ring_head = 0, ring_tail = 0;    // wave-uniform: leaf ring
+  uint32_t hit_head = 0, hit_tail = 0;      // wave-uniform: hit ring
+  uint32_t pool_n = 0;                      // wave-uniform: children in the pool
+  uint32_t n_depth[kMaxLevels] = {};    // wave-uniform: children created per depth
+  uint32_t visits = 0, excl = 0xffffffffu, last_pos = 0;
+  float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0, ray_L = 0, ray_g = 0;
+  uint4 ray_c = make_uint4(0u, 0u, 0u, 0u);
+  uint32_t ray_m = 0;
+  RayBox rb{};
+  int32_t cur = 0;
+  int sp = 0;
+  bool trav_done = false;
+  uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0, cnt_hits = 0, cnt_pool_max = 0;
+
+  auto start_ray = [&](const float4 a, const float4 b, const uint4 c, uint32_t m) {
+    excl = c.w;
+    const uint32_t medium = (m >> 8) & 0xffu;
+    const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
+    best_t = (A.scans[m >> 16].r_max - a.w) / n_cur;
+    lds_best[threadIdx.x] = ((unsigned long long)__float_as_uint(best_t) << 32) | 0xffffffffull;
+    ox = a.x;
+    oy = a.y;
+    oz = a.z;
+    dx = b.x;
+    dy = b.y;
+    dz = b.z;
+    ray_L = a.w;
+    ray_g = b.w;
+    ray_c = c;
+    ray_m = m;
+    ray_box_setup(ox, oy, oz, dx, dy, dz, rb);
+    cur = 0;
+    sp = 0;
+    visits = 0;
+    last_pos = ring_head;
+    trav_done = false;
+    valid = true;
+    if (kCount) ++cnt_rays;
+  };
+
+  for (;;) {
+    // ---- refill idle lanes: children of this wave first, then primaries
+    uint64_t idle = __ballot(!valid);
+    if (pool_n > 0 && idle) {
+      const uint32_t take = min((uint32_t)__popcll(idle), pool_n);
+      const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      if (!valid && rank < take) {
+        const float4* e = pool + (size_t)(pool_n - 1u - rank) * 4u;
+        const float4 a = e[0], b = e[1];
+        const uint4 c = reinterpret_cast<const uint4*>(e)[2];
+        const uint32_t m = reinterpret_cast<const uint4*>(e)[3].x;
+        start_ray(a, b, c, m);
+      }
+      pool_n -= take;
+      idle = __ballot(!valid);
+    }
+    if (!exhausted && pool_n == 0 && (uint32_t)__popcll(idle) >= A.refill) {
+#pragma unroll 1
+      for (int pass = 0; pass < 2 && idle; ++pass) {
+        if (pool_next >= pool_end) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(cursor, A.pool);
+          base = __shfl(base, 0);
+          pool_next = base;
+          pool_end = min(base + A.pool, n_in);
+          if (base >= n_in) {
+            exhausted = true;
+            break;
+          }
+        }
+        const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
+        const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+        if (!valid && rank < take) {
+          const uint32_t my = pool_next + rank;
+          start_ray(A.in.a[my], A.in.b[my], A.in.c[my], A.in.m[my]);
+        }
+        pool_next += take;
+        idle = __ballot(!valid);
+        if (pool_next >= pool_end && pool_end >= n_in) exhausted = true;
+      }
+    }
+    const uint64_t live = __ballot(valid);
+    const uint32_t hits_q = hit_head - hit_tail;
+    if (live == 0ull && hits_q == 0u && pool_n == 0u && exhausted) break;
+
+    const uint64_t walking = __ballot(valid && !trav_done);
+    const uint32_t queued = ring_head - ring_tail;
+    const bool shade_phase = hits_q >= shade_batch || hits_q + 64u > A.wq_hits ||
+                             (hits_q > 0u && live == 0ull);
+    const bool tri_phase = !shade_phase &&
+                           (queued >= tri_batch ||
+                            (queued > 0 && (walking == 0ull || queued + 4u * (uint32_t)__popcll(walking) > kLeafRing)));
+    if (shade_phase) {
+      // ---- interactions of up to 64 finished rays, one per lane
+      const uint32_t n = min(hits_q, 64u);
+      const bool take = lane < n;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      Shaded o;
+      uint32_t child_depth = 0;
+      if (take) {
+        const float4* e = hring + (size_t)((hit_tail + lane) & (A.wq_hits - 1u)) * 4u;
+        const float4 a = e[0], b = e[1];
+        const uint4 c = reinterpret_cast<const uint4*>(e)[2];
+        const uint4 d = reinterpret_cast<const uint4*>(e)[3];
+        shade_hit(A, a, b, c, d.x, d.y, (int32_t)d.z, o);
+        if (o.has_q) atomicAdd(A.acc + o.cell, o.qv);
+        child_depth = 32u - (uint32_t)__clz(d.x & 0xffu);  // depth of the ray + 1
+        if (kCount && o.hit >= 0) ++cnt_hits;
+      }
+      hit_tail += n;
+      const uint64_t mr = __ballot(take && o.has_r);
+      const uint64_t mt = __ballot(take && o.has_t);
+      const uint32_t nr = (uint32_t)__popcll(mr), nt = (uint32_t)__popcll(mt);
+      if (pool_n + nr + nt <= A.wq_pool) {
+        if (take && o.has_r) {
+          float4* e = pool + (size_t)(pool_n + (uint32_t)__popcll(mr & lanes_below)) * 4u;
+          e[0] = make_float4(o.rox, o.roy, o.roz, o.range);
+          e[1] = make_float4(o.rdx, o.rdy, o.rdz, o.g);
+          reinterpret_cast<uint4*>(e)[2] = make_uint4((uint32_t)__double2loint(o.e_refl),
+                                                      (uint32_t)__double2hiint(o.e_refl), o.pid, (uint32_t)o.hit);
+          reinterpret_cast<uint4*>(e)[3] = make_uint4(o.r_meta, 0u, 0u, 0u);
+        }
+        if (take && o.has_t) {
+          float4* e = pool + (size_t)(pool_n + nr + (uint32_t)__popcll(mt & lanes_below)) * 4u;
+          e[0] = make_float4(o.tox, o.toy, o.toz, o.range);
+          e[1] = make_float4(o.tdx, o.tdy, o.tdz, o.g);
+          reinterpret_cast<uint4*>(e)[2] = make_uint4((uint32_t)__double2loint(o.e_refr),
+                                                      (uint32_t)__double2hiint(o.e_refr), o.pid, (uint32_t)o.hit);
+          reinterpret_cast<uint4*>(e)[3] = make_uint4(o.t_meta, 0u, 0u, 0u);
+        }
+        pool_n += nr + nt;
+#pragma unroll
+        for (uint32_t d = 1; d < kMaxLevels; ++d)
+          n_depth[d] += (uint32_t)__popcll((mr | mt) & __ballot(take && child_depth == d)) +
+                        (uint32_t)__popcll(mr & mt & __ballot(take && child_depth == d));
+        if (kCount) cnt_pool_max = max(cnt_pool_max, pool_n);
+      } else if (nr + nt > 0u && lane == 0) {
+        atomicOr(A.counters + kCtrOverflow, 1u);  // pool full: children dropped, scan reports it
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    } else if (tri_phase) {
+      const uint32_t n = min(queued, 64u);
+      const bool take = lane < n;
+      const uint32_t pos = (ring_tail + lane) & (kLeafRing - 1u);
+      const uint32_t ref = take ? lds_leaf[wib][pos] : 0u;
+      const int own = take ? (int)lds_own[wib][pos] : (int)lane;
+      const float rox = __shfl(ox, own), roy = __shfl(oy, own), roz = __shfl(oz, own);
+      const float rdx = __shfl(dx, own), rdy = __shfl(dy, own), rdz = __shfl(dz, own);
+      const uint32_t rexcl = __shfl(excl, own);
+      if (take) {
+        unsigned long long cb = lds_best[wave_base + own];
+        float tmax = __uint_as_float((uint32_t)(cb >> 32));
+        const uint32_t start = leaf_start((int32_t)ref), count = leaf_count((int32_t)ref);
+#pragma unroll 1
+        for (uint32_t k = 0; k < count; ++k) {
+          const uint32_t li = start + k;
+          const float4 ta = tris[3 * li + 0];
+          const uint32_t orig = __float_as_uint(ta.w);
+          if (orig == rexcl) continue;
+          if (kCount) ++cnt_tris;
+          const float4 e1 = tris[3 * li + 1];
+          const float4 e2 = tris[3 * li + 2];
+          float t;
+          if (ray_tri(rox, roy, roz, rdx, rdy, rdz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
+                      tmax, t)) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(t) << 32) | orig;
+            if (key < cb) {
+              atomicMin(&lds_best[wave_base + own], key);
+              cb = key;
+              tmax = t;
+            }
+          }
+        }
+      }
+      ring_tail += n;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) best_t = __uint_as_float((uint32_t)(lds_best[threadIdx.x] >> 32));
+    } else {
+      uint32_t leaves = 0;
+      int32_t lref[4] = {0, 0, 0, 0};
+      if (valid && !trav_done) {
+        const int32_t top = stk[min(max(sp - 1, 0), kStack - 1) * kTraceBlock];
+        if (cur == kEmpty) {
+          if (sp > 0) {
+            --sp;
+            cur = sp < kStack ? top : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
+          } else {
+            trav_done = true;
+          }
+        }
+        if (!trav_done) {
+          const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+          const float4 w0 = np[0];
+          const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
+          const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
+          const int4 w3 = reinterpret_cast<const int4*>(np)[3];
+          if (kCount) ++cnt_nodes;
+          float tn[4];
+          const uint32_t mask = node4_boxes(w0, w1, w2, w3, rb, best_t, tn);
+          const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
+          float key[4];
+          int32_t val[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const bool h = (mask >> j) & 1u;
+            const bool inner = h && ref[j] >= 0;
+            if (h && ref[j] < 0) leaves |= 1u << j;
+            lref[j] = ref[j];
+            key[j] = inner ? tn[j] : -INFINITY;
+            val[j] = inner ? ref[j] : kEmpty;
+          }
+#define RR_CX(i, j)                     \
+  if (key[j] > key[i]) {                \
+    const float tk = key[i];            \
+    key[i] = key[j];                    \
+    key[j] = tk;                        \
+    const int32_t tv = val[i];          \
+    val[i] = val[j];                    \
+    val[j] = tv;                        \
+  }
+          RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
+#undef RR_CX
+          const int h = __popc(mask & ~leaves);
+          if (sp + 3 <= kStack) {
+            stk[(sp + 0) * kTraceBlock] = val[0];
+            stk[(sp + 1) * kTraceBlock] = val[1];
+            stk[(sp + 2) * kTraceBlock] = val[2];
+            sp += h > 1 ? h - 1 : 0;
+          } else {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              if (j < h - 1 && sp < kStack + kSpill) {
+                if (sp < kStack)
+                  stk[sp * kTraceBlock] = val[j];
+                else
+                  A.spill[(size_t)(sp - kStack) * spill_stride + gtid] = val[j];
+                ++sp;
+              }
+            }
+          }
+          cur = h == 0 ? kEmpty : h == 1 ? val[0] : h == 2 ? val[1] : h == 3 ? val[2] : val[3];
+          if (++visits > A.n_nodes) trav_done = true;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool want = (leaves >> j) & 1u;
+        const uint64_t m = __ballot(want);
+        if (want) {
+          const uint32_t p = ring_head + (uint32_t)__popcll(m & lanes_below);
+          lds_leaf[wib][p & (kLeafRing - 1u)] = (uint32_t)lref[j];
+          lds_own[wib][p & (kLeafRing - 1u)] = (uint8_t)lane;
+          last_pos = p + 1u;
+        }
+        ring_head += (uint32_t)__popcll(m);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // ---- finished rays into the hit ring (room for 64 is kept free)
+    const bool fin = valid && trav_done && (int32_t)(ring_tail - last_pos) >= 0;
+    const uint64_t fm = __ballot(fin);
+    if (fin) {
+      const unsigned long long bst = lds_best[threadIdx.x];
+      float4* e = hring + (size_t)((hit_head + (uint32_t)__popcll(fm & lanes_below)) & (A.wq_hits - 1u)) * 4u;
+      e[0] = make_float4(ox, oy, oz, ray_L);
+      e[1] = make_float4(dx, dy, dz, ray_g);
+      reinterpret_cast<uint4*>(e)[2] = ray_c;
+      reinterpret_cast<uint4*>(e)[3] = make_uint4(ray_m, (uint32_t)(bst >> 32), (uint32_t)bst, 0u);
+      valid = false;
+    }
+    hit_head += (uint32_t)__popcll(fm);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (uint32_t d = 1; d < kMaxLevels; ++d)
+      if (n_depth[d]) atomicAdd(A.counters + kCtrCount + d, n_depth[d]);
+  }
+  if (kCount) {
+    atomicAdd(A.prof + 0, (unsigned long long)cnt_nodes);
+    atomicAdd(A.prof + 1, (unsigned long long)cnt_tris);
+    atomicAdd(A.prof + 2, (unsigned long long)cnt_rays);
+    atomicAdd(A.prof + 3, (unsigned long long)cnt_hits);
+    if (lane == 0) atomicMax(A.prof + kProfPoolMax, (unsigned long long)cnt_pool_max);
+  }
 }
 
 // ---------------------------------------------------------------- helpers
@@ -733,6 +1087,15 @@ hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
     hipLaunchKernelGGL(k_trace<true>, g, b, 0, st, a);
   else
     hipLaunchKernelGGL(k_trace<false>, g, b, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const LevelArgs& a, uint32_t grid, hipStream_t st) {
+  const dim3 g(grid ? grid : 1), b(kTraceBlock);
+  if (a.prof)
+    hipLaunchKernelGGL(k_scan<true>, g, b, 0, st, a);
+  else
+    hipLaunchKernelGGL(k_scan<false>, g, b, 0, st, a);
   return hipGetLastError();
 }
 

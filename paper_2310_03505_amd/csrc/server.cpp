@@ -76,9 +76,9 @@ struct rr_server {
 
 namespace {
 
-size_t layout_bytes(const std::vector<const rr_sensor_params*>& ps) {
+size_t layout_bytes(const std::vector<const rr_sensor_params*>& ps, bool fused) {
   Layout L;
-  make_layout(ps.data(), (uint32_t)ps.size(), L);
+  make_layout(ps.data(), (uint32_t)ps.size(), L, fused);
   return L.total;
 }
 
@@ -125,7 +125,7 @@ void dispatcher(rr_server* s) {
       const Req& cand = s->pending.front();
       if (cand.params.beam_width_rad != bw) break;
       ps.push_back(&cand.params);
-      if (!sl.batch.empty() && layout_bytes(ps) > s->slot_budget) {
+      if (!sl.batch.empty() && layout_bytes(ps, s->ctx->fused != 0) > s->slot_budget) {
         ps.pop_back();
         break;
       }
@@ -143,7 +143,7 @@ void dispatcher(rr_server* s) {
       scans[i].image = sl.batch[i].image;
     }
     rr_status st = RR_OK;
-    size_t need = layout_bytes(bp);
+    size_t need = layout_bytes(bp, s->ctx->fused != 0);
     if (sl.ws_bytes < need) {
       if (sl.ws) (void)hipFree(sl.ws);  // the slot's stream is idle
       sl.ws = nullptr;
@@ -241,7 +241,7 @@ rr_status rr_server_submit(rr_server* s, const rr_pose* pose, const rr_sensor_pa
   std::vector<const rr_sensor_params*> ps{params};
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return fail(nullptr, RR_ESTATE, "server is stopping");
-  if (layout_bytes(ps) > s->slot_budget) {
+  if (layout_bytes(ps, s->ctx->fused != 0) > s->slot_budget) {
     s->rejected++;
     return fail(nullptr, RR_ENOMEM, "request needs more workspace than a slot's budget");
   }

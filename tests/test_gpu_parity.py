@@ -222,6 +222,58 @@ def test_batch_equals_single_scans(R, ctx):
         sc.release()
 
 
+def test_fused_launch_equals_levels(R, ctx):
+    """One persistent launch for all bounce levels gives the same records,
+    accumulator, image and per-level ray counts, bit for bit, as one trace
+    and one shade launch per level (single scans and a mixed batch)."""
+    import torch
+    before = R.rr_get_tuning(ctx.handle)
+    s = W.tiny_room()
+    cases = [(s, s.params, s.pose),
+             (s, dict(s.params, max_bounces=8, n_azimuth=64, rays_per_beam=16), s.pose),
+             (s, dict(s.params, flags=s.params["flags"] | 4, n_azimuth=50), W.yaw_pose((1.0, -0.5, 0.2), 0.7))]
+    u = W.urban_block()
+    cases.append((u, dict(u.params, n_azimuth=40), u.pose))
+    try:
+        for scene, p, pose in cases:
+            sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+            try:
+                outs = []
+                for fused in (2, 1):
+                    R.rr_set_tuning(ctx.handle, fused=fused)
+                    o = R.rr_radar_scan_records(ctx.handle, sc.handle, pose, p, scene.materials)
+                    torch.cuda.synchronize()
+                    outs.append(o)
+                a, b = outs
+                assert torch.equal(a["image"], b["image"])
+                assert torch.equal(a["records"], b["records"])
+                assert torch.equal(a["accum"], b["accum"])
+                assert a["stats"]["rays_per_depth"] == b["stats"]["rays_per_depth"]
+                assert b["stats"]["overflow"] == 0
+            finally:
+                sc.release()
+        # a mixed batch
+        scans = []
+        for i, (naz, ns, bb) in enumerate([(100, 16, 2), (400, 64, 3), (37, 5, 4), (800, 8, 1)]):
+            scans.append((W.yaw_pose((0.2 * i, -0.1 * i, 0.0), 0.3 * i),
+                          dict(s.params, n_azimuth=naz, rays_per_beam=ns, max_bounces=bb, scan_id=i)))
+        sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+        try:
+            res = []
+            for fused in (2, 1):
+                R.rr_set_tuning(ctx.handle, fused=fused)
+                imgs, st = R.rr_radar_scan_batch(ctx.handle, sc.handle, scans, s.materials, stats=True)
+                torch.cuda.synchronize()
+                res.append((imgs, st))
+            for x, y in zip(res[0][0], res[1][0]):
+                assert torch.equal(x, y)
+            assert res[0][1]["rays_per_depth"] == res[1][1]["rays_per_depth"]
+        finally:
+            sc.release()
+    finally:
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
+
+
 def test_workspace_variant_matches(R, ctx):
     import torch
     s = W.tiny_room(n_azimuth=100, rays_per_beam=32)
@@ -328,15 +380,14 @@ def test_autotune_keeps_images(R, ctx):
         assert t["refill_lanes"] in (4, 8, 12, 16, 24, 32, 48)
         assert t["trace_waves_per_cu"] in (8, 12, 16, 20, 24, 32)
         assert t["pool_rays"] in (64, 128, 256) and t["tri_batch"] in (16, 32, 48, 64)
+        assert t["fused"] in (1, 2) and t["shade_batch"] in (16, 32, 64)
         assert R.rr_get_tuning(ctx.handle) == t
         b, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
         log(f"autotune tiny room: {t} {ms:.3f} ms")
     finally:
-        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in
-                                       ("refill_lanes", "trace_waves_per_cu", "pool_rays",
-                                        "batch_budget_mb", "tri_batch")})
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
         sc.release()
 
 
