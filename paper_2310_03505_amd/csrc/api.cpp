@@ -277,7 +277,6 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   LevelArgs a{};
   a.nodes = sc->d_nodes;
   a.n_nodes = (uint32_t)sc->bvh.nodes.size();
-  a.n_leaf_tris = (uint32_t)(sc->bvh.tris.size() / 3);
   a.tris = sc->d_tris;
   a.aux = sc->d_aux;
   a.scans = d_scans;

@@ -17,8 +17,7 @@ struct QueueView {
 // Arguments shared by the per-level kernels.
 struct LevelArgs {
   const Node4* nodes;
-  uint32_t n_nodes;  // inner nodes (with n_leaf_tris, bounds the traversal loop)
-  uint32_t n_leaf_tris;
+  uint32_t n_nodes;  // inner nodes (bounds the node visits of one ray)
   uint32_t depth;
   const float4* tris;
   const float4* aux;

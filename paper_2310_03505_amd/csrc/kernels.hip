@@ -1,14 +1,17 @@
 // kernels.hip -- the radar-scan hot path on CDNA4 (gfx950).
 //
-// Wavefront organisation, three kernels per bounce level:
+// Wavefront organisation:
 //   k_raygen  primaries of every scan from the counter-based generator
 //             (Sec. III-A, Eq. 2), appended to ray queue 0;
-//   k_trace   closest hit of every queued ray through the BVH: persistent
-//             lanes that take a new ray as soon as theirs is done;
-//   k_shade   the interaction at each hit (Snell, Fresnel, standard BRDF
-//             return, Sec. III-A), the return binned into the polar image with
-//             a 64-bit fixed-point atomic (Sec. III-B), and up to two
-//             children appended to the next queue with one atomic per wave.
+//   k_trace   (per bounce level) closest hit of every queued ray through the
+//             BVH: persistent lanes that take a new ray as soon as theirs is
+//             done, leaf tests batched wave-wide;
+//   k_shade   (per bounce level) the interaction at each hit (Snell,
+//             Fresnel, standard BRDF return, Sec. III-A), the return binned
+//             into the polar image with a 64-bit fixed-point atomic
+//             (Sec. III-B), and up to two children appended to the next queue;
+//   k_scan    the optional one-launch form of k_trace + k_shade over every
+//             level, each wave keeping its own rays' children.
 //
 // Floating-point rules: no contraction except where fmaf is written; the
 // closest-hit, bin and total-internal-reflection decisions and the child
