@@ -112,12 +112,15 @@ typedef struct {
   uint32_t n_threads;     /* host build threads, 0 = all cores */
   uint32_t split_pct;     /* early split clipping: extra triangle references, in
                              percent of the triangle count, 0..200 (0 = none) */
+  uint32_t width;         /* children per node: 4 (default) or 8 (compressed
+                             eight-wide nodes, leaves of at most 4 triangles) */
+  uint32_t reserved[3];
 } rr_bvh_options;
 
 typedef struct {
   uint32_t n_tris;        /* triangles in the scene */
   uint32_t n_hittable;    /* non-degenerate triangles placed in the BVH */
-  uint32_t n_nodes;       /* four-wide inner nodes */
+  uint32_t n_nodes;       /* wide inner nodes */
   uint32_t n_leaves;
   uint32_t max_depth;     /* deepest inner node (root = 0) */
   uint32_t max_stack;     /* worst-case traversal stack entries */

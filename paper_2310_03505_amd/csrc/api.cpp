@@ -275,8 +275,14 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
       HIP_TRY(ctx, launch_fill_i32(scans[i].records,
                                    (size_t)scans[i].n_prim * ((1u << scans[i].max_b) - 1u), -2, st));
   LevelArgs a{};
-  a.nodes = sc->d_nodes;
-  a.n_nodes = (uint32_t)sc->bvh.nodes.size();
+  if (sc->bvh.width == 8) {
+    if (ctx->fused) return fail(ctx, RR_EINVAL, "the one-launch mode needs a four-wide BVH");
+    a.nodes8 = static_cast<const Node8*>(sc->d_nodes);
+    a.n_nodes = (uint32_t)sc->bvh.nodes8.size();
+  } else {
+    a.nodes = static_cast<const Node4*>(sc->d_nodes);
+    a.n_nodes = (uint32_t)sc->bvh.nodes.size();
+  }
   a.tris = sc->d_tris;
   a.aux = sc->d_aux;
   a.scans = d_scans;
@@ -509,7 +515,10 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
     if (opt->sah_bins) o.bins = opt->sah_bins;
     o.threads = opt->n_threads;
     o.split_pct = opt->split_pct;
+    o.width = opt->width ? opt->width : 4u;
   }
+  if (o.width != 4 && o.width != 8) return fail(ctx, RR_EINVAL, "width must be 4 or 8");
+  if (o.width == 8 && o.max_leaf > 4) return fail(ctx, RR_EINVAL, "an eight-wide BVH takes leaves of at most 4 triangles");
   if (o.split_pct > 200) return fail(ctx, RR_EINVAL, "split_pct out of [0, 200]");
   if (o.max_leaf < 1 || o.max_leaf > 16) return fail(ctx, RR_EINVAL, "max_leaf_size out of [1, 16]");
   if (o.bins < 4 || o.bins > 64) return fail(ctx, RR_EINVAL, "sah_bins out of [4, 64]");
@@ -520,9 +529,11 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
   }
   if (sc->bvh.n_hittable >= kMaxLeafTris)
     return fail(ctx, RR_EINVAL, "scene has %u triangles, more than 2^27", sc->bvh.n_hittable);
-  if (sc->bvh.max_stack > (uint32_t)(kStack + kSpill))
-    return fail(ctx, RR_EOVERFLOW, "BVH needs %u stack entries, more than %d", sc->bvh.max_stack,
-                kStack + kSpill);
+  const uint32_t stack_cap = sc->bvh.width == 8 ? (uint32_t)(kStack8 + kSpill / 2) : (uint32_t)(kStack + kSpill);
+  if (sc->bvh.max_stack > stack_cap)
+    return fail(ctx, RR_EOVERFLOW, "BVH needs %u stack entries, more than %u", sc->bvh.max_stack, stack_cap);
+  if (sc->bvh.width == 8 && sc->bvh.tris.size() / 3 >= kMaxTris8)
+    return fail(ctx, RR_EINVAL, "an eight-wide BVH addresses fewer than 2^24 triangle references");
   sc->built = true;
   if (!ctx) return RR_OK;
   DeviceGuard g(ctx->device);
@@ -532,13 +543,16 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
   sc->d_nodes = nullptr;
   sc->d_tris = nullptr;
   sc->d_aux = nullptr;
-  size_t bn = sizeof(Node4) * sc->bvh.nodes.size();
+  size_t bn = sc->bvh.width == 8 ? sizeof(Node8) * sc->bvh.nodes8.size() : sizeof(Node4) * sc->bvh.nodes.size();
   size_t bt = sizeof(float4) * std::max<size_t>(sc->bvh.tris.size(), 3);
   size_t ba = sizeof(float4) * std::max<size_t>(sc->bvh.aux.size(), 1);
   HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&sc->d_nodes), bn));
   HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&sc->d_tris), bt));
   HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&sc->d_aux), ba));
-  HIP_TRY(ctx, hipMemcpy(sc->d_nodes, sc->bvh.nodes.data(), bn, hipMemcpyHostToDevice));
+  if (sc->bvh.width == 8)
+    HIP_TRY(ctx, hipMemcpy(sc->d_nodes, sc->bvh.nodes8.data(), bn, hipMemcpyHostToDevice));
+  else
+    HIP_TRY(ctx, hipMemcpy(sc->d_nodes, sc->bvh.nodes.data(), bn, hipMemcpyHostToDevice));
   if (!sc->bvh.tris.empty())
     HIP_TRY(ctx, hipMemcpy(sc->d_tris, sc->bvh.tris.data(), sizeof(float4) * sc->bvh.tris.size(),
                            hipMemcpyHostToDevice));
@@ -555,7 +569,7 @@ rr_status rr_bvh_get_info(const rr_scene* sc, rr_bvh_info* out) {
   std::memset(out, 0, sizeof *out);
   out->n_tris = sc->bvh.n_tris;
   out->n_hittable = sc->bvh.n_hittable;
-  out->n_nodes = (uint32_t)sc->bvh.nodes.size();
+  out->n_nodes = (uint32_t)(sc->bvh.width == 8 ? sc->bvh.nodes8.size() : sc->bvh.nodes.size());
   out->n_leaves = sc->bvh.n_leaves;
   out->max_depth = sc->bvh.max_depth;
   out->max_stack = sc->bvh.max_stack;

@@ -47,7 +47,7 @@ struct rr_scene {
   uint32_t max_mat = 0;
   bool built = false;
   rr::BuiltBvh bvh;
-  rr::Node4* d_nodes = nullptr;
+  void* d_nodes = nullptr;  // rr::Node4 or rr::Node8 array, as bvh.width says
   float4* d_tris = nullptr;
   float4* d_aux = nullptr;
   uint64_t dev_bytes = 0;

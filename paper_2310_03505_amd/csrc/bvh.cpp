@@ -110,6 +110,7 @@ struct BNode {
   Box box;
   std::unique_ptr<BNode> l, r;
   uint32_t begin = 0, count = 0;  // leaf range in the ref array
+  uint32_t span = 0;              // references below an inner node (from begin)
   bool leaf() const { return !l; }
 };
 
@@ -214,6 +215,8 @@ struct Builder {
     }
     auto nd = std::make_unique<BNode>();
     nd->box = box;
+    nd->begin = b;  // an inner node's references are [b, e) too
+    nd->span = n;
     if (depth < par_depth && n > 4096) {
       auto fut = std::async(std::launch::async, [&, b, mid, depth] { return build(b, mid, depth + 1); });
       nd->r = build(mid, e, depth + 1);
@@ -353,6 +356,161 @@ struct Flattener4 {
     // every hit child but the nearest is pushed (leaves too); the deepest
     // inner child adds its own need on top
     return (n_kids ? n_kids - 1 : 0) + need_max;
+  }
+};
+
+// Collapses the two-wide build tree into eight-wide quantised nodes.  Each
+// output node opens its largest-area inner children until it has eight; the
+// children are placed in slots by the corner of the node box they lie toward
+// (greedy on the score sum_a sign_a(slot) * (child centre - node centre)_a),
+// inner children get consecutive node indices and leaf children consecutive
+// triangles.
+struct Flattener8 {
+  const std::vector<Ref>& refs;
+  const std::vector<float4>& tri3;
+  BuiltBvh& out;
+  float pad;
+  double root_area;
+  uint32_t leaf_max;  // a subtree with at most this many references becomes one leaf
+
+  static uint32_t refs_of(const BNode* k) { return k->leaf() ? k->count : k->span; }
+  bool is_leaf(const BNode* k) const { return k->leaf() || k->span <= leaf_max; }
+
+  // returns the stack need (groups) of the subtree below node `idx`
+  uint32_t fill(const BNode* b, uint32_t idx, uint32_t depth) {
+    std::vector<const BNode*> kids{b->l.get(), b->r.get()};
+    while (kids.size() < 8) {
+      // open the largest child that has children: first those too big for a
+      // leaf, then leaf-sized ones, which splits them into smaller leaves
+      int best = -1;
+      double ba = -1.0;
+      bool big = false;
+      for (size_t i = 0; i < kids.size(); ++i) {
+        if (kids[i]->leaf()) continue;
+        const bool kb = !is_leaf(kids[i]);
+        if ((kb && !big) || ((kb == big) && kids[i]->box.area() > ba)) {
+          ba = kids[i]->box.area();
+          best = (int)i;
+          big = kb;
+        }
+      }
+      if (best < 0) break;
+      const BNode* o = kids[(size_t)best];
+      kids[(size_t)best] = o->l.get();
+      kids.insert(kids.begin() + best + 1, o->r.get());
+    }
+    kids.erase(std::remove_if(kids.begin(), kids.end(), [](const BNode* k) { return refs_of(k) == 0; }),
+               kids.end());
+    out.max_depth = std::max(out.max_depth, depth);
+    if (root_area > 0.0) out.sah_cost += b->box.area() / root_area;
+    // slots by octant
+    const BNode* slot[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    {
+      double c[3];
+      for (int a = 0; a < 3; ++a) c[a] = 0.5 * ((double)b->box.lo[a] + (double)b->box.hi[a]);
+      std::vector<bool> used(kids.size(), false);
+      for (size_t round = 0; round < kids.size(); ++round) {
+        double best = -INFINITY;
+        int bk = -1, bs = -1;
+        for (size_t j = 0; j < kids.size(); ++j) {
+          if (used[j]) continue;
+          double kc[3];
+          for (int a = 0; a < 3; ++a) kc[a] = 0.5 * ((double)kids[j]->box.lo[a] + (double)kids[j]->box.hi[a]) - c[a];
+          for (int s = 0; s < 8; ++s) {
+            if (slot[s]) continue;
+            double sc = 0.0;
+            for (int a = 0; a < 3; ++a) sc += ((s >> a) & 1) ? kc[a] : -kc[a];
+            if (sc > best) {
+              best = sc;
+              bk = (int)j;
+              bs = s;
+            }
+          }
+        }
+        used[(size_t)bk] = true;
+        slot[bs] = kids[(size_t)bk];
+      }
+    }
+    // padded child boxes and the node frame
+    float clo[8][3], chi[8][3];
+    float nlo[3] = {INFINITY, INFINITY, INFINITY}, nhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int s = 0; s < 8; ++s) {
+      if (!slot[s]) continue;
+      const Box& cb = slot[s]->box;
+      for (int a = 0; a < 3; ++a) {
+        clo[s][a] = cb.empty() ? 0.0f : cb.lo[a] - pad;
+        chi[s][a] = cb.empty() ? 0.0f : cb.hi[a] + pad;
+        if (!cb.empty()) {
+          nlo[a] = std::min(nlo[a], clo[s][a]);
+          nhi[a] = std::max(nhi[a], chi[s][a]);
+        }
+      }
+    }
+    for (int a = 0; a < 3; ++a)
+      if (!(nlo[a] <= nhi[a])) nlo[a] = nhi[a] = 0.0f;
+    float origin[3];
+    uint32_t eb[3];
+    for (int a = 0; a < 3; ++a) Flattener4::quantise_axis(nlo[a], nhi[a], origin[a], eb[a]);
+    uint32_t qlo[3][2] = {}, qhi[3][2] = {};
+    for (int s = 0; s < 8; ++s) {
+      if (!slot[s]) continue;
+      for (int a = 0; a < 3; ++a) {
+        double sc = std::ldexp(1.0, (int)eb[a] - 127);
+        double lo = std::floor(((double)clo[s][a] - (double)origin[a]) / sc);
+        double hi = std::ceil(((double)chi[s][a] - (double)origin[a]) / sc);
+        uint32_t ql = (uint32_t)std::min(255.0, std::max(0.0, lo));
+        uint32_t qh = (uint32_t)std::min(255.0, std::max(0.0, hi));
+        qlo[a][s >> 2] |= ql << (8 * (s & 3));
+        qhi[a][s >> 2] |= qh << (8 * (s & 3));
+      }
+    }
+    // inner children: consecutive nodes in slot order
+    uint32_t imask = 0, n_inner = 0;
+    for (int s = 0; s < 8; ++s)
+      if (slot[s] && !is_leaf(slot[s])) {
+        imask |= 1u << s;
+        ++n_inner;
+      }
+    const uint32_t first = (uint32_t)out.nodes8.size();
+    out.nodes8.resize(first + n_inner);
+    // leaf children: consecutive triangles in slot order
+    const uint32_t first_tri = (uint32_t)(out.tris.size() / 3);
+    uint32_t leafmask = 0, meta[2] = {0, 0};
+    for (int s = 0; s < 8; ++s) {
+      if (!slot[s] || !is_leaf(slot[s])) continue;
+      const BNode* k = slot[s];
+      const uint32_t offset = (uint32_t)(out.tris.size() / 3) - first_tri;
+      uint32_t kept = 0;
+      for (uint32_t i = 0; i < refs_of(k); ++i) {
+        uint32_t id = refs[k->begin + i].id;
+        bool dup = false;  // split references of one triangle in the same leaf
+        for (uint32_t q = 0; q < i; ++q) dup = dup || refs[k->begin + q].id == id;
+        if (dup) continue;
+        ++kept;
+        out.tris.push_back(tri3[3 * id + 0]);
+        out.tris.push_back(tri3[3 * id + 1]);
+        out.tris.push_back(tri3[3 * id + 2]);
+      }
+      out.n_leaves++;
+      if (root_area > 0.0) out.sah_cost += k->box.area() / root_area * kept;
+      leafmask |= 1u << s;
+      meta[s >> 2] |= (((kept - 1u) << 5) | offset) << (8 * (s & 3));
+    }
+    Node8 nd{};
+    uint32_t ebits = eb[0] | (eb[1] << 8) | (eb[2] << 16) | (imask << 24);
+    float ebf;
+    std::memcpy(&ebf, &ebits, 4);
+    nd.w0 = float4{origin[0], origin[1], origin[2], ebf};
+    nd.w1 = uint4{first, first_tri | (leafmask << 24), meta[0], meta[1]};
+    nd.w2 = uint4{qlo[0][0], qlo[0][1], qhi[0][0], qhi[0][1]};
+    nd.w3 = uint4{qlo[1][0], qlo[1][1], qhi[1][0], qhi[1][1]};
+    nd.w4 = uint4{qlo[2][0], qlo[2][1], qhi[2][0], qhi[2][1]};
+    out.nodes8[idx] = nd;
+    uint32_t need = 0, rank = 0;
+    for (int s = 0; s < 8; ++s)
+      if ((imask >> s) & 1u) need = std::max(need, fill(slot[s], first + rank++, depth + 1));
+    // descending into a child pushes at most this node's remaining group
+    return need + (n_inner > 1 ? 1u : 0u);
   }
 };
 
@@ -496,7 +654,10 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
   unsigned th = opt.threads ? opt.threads : (hw ? hw : 1);
   int par_depth = 0;
   while ((1u << par_depth) < th && par_depth < 8) ++par_depth;
-  Builder bld{refs, std::max(1u, opt.max_leaf), std::max(4u, opt.bins), par_depth};
+  // the eight-wide collapse forms its own leaves (subtrees of at most
+  // max_leaf references), so its binary tree goes down to single triangles
+  const uint32_t leaf2 = opt.width == 8 ? 1u : std::max(1u, opt.max_leaf);
+  Builder bld{refs, leaf2, std::max(4u, opt.bins), par_depth};
   std::unique_ptr<BNode> root;
   uint32_t n = (uint32_t)refs.size();
   if (n >= 2) {
@@ -514,9 +675,16 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
     root = std::move(r);
   }
   out.max_depth2 = depth_of(root.get()) - 1;
-  Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area()};
-  int32_t root_ref;
-  out.max_stack = fl.emit(root.get(), 0, &root_ref);
+  out.width = opt.width == 8 ? 8u : 4u;
+  if (out.width == 8) {
+    Flattener8 fl{refs, tri3, out, out.pad, root->box.empty() ? 0.0 : root->box.area(), opt.max_leaf};
+    out.nodes8.resize(1);
+    out.max_stack = fl.fill(root.get(), 0, 0);
+  } else {
+    Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area()};
+    int32_t root_ref;
+    out.max_stack = fl.emit(root.get(), 0, &root_ref);
+  }
   out.aux = std::move(aux0);
   auto t1 = std::chrono::steady_clock::now();
   out.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -596,6 +764,59 @@ int32_t host_traverse(const BuiltBvh& b, const float o[3], const float d[3], flo
   return best;
 }
 
+// Eight-wide traversal on the host: the same node-group stack (first inner
+// child, hit slots in octant order, inner-slot mask) the GPU kernel keeps.
+int32_t host_traverse8(const BuiltBvh& b, const float o[3], const float d[3], float tmax,
+                       int32_t excl, float* t_out) {
+  RayBox rb;
+  ray_box_setup(o[0], o[1], o[2], d[0], d[1], d[2], rb);
+  const uint32_t oct = ray_octant(rb);
+  float best_t = tmax;
+  int32_t best = -1;
+  uint32_t best_orig = 0xffffffffu;
+  uint32_t gs_base[kMaxDepth + 2], gs_mask[kMaxDepth + 2];
+  int sp = 0;
+  uint32_t g_base = 0, g_mask = 0;  // current group: (first child, order bits | imask << 8)
+  int32_t cur = 0;
+  for (;;) {
+    if (cur < 0) {
+      if ((g_mask & 0xffu) == 0) {
+        if (sp == 0) break;
+        --sp;
+        g_base = gs_base[sp];
+        g_mask = gs_mask[sp];
+      }
+      const uint32_t i = (uint32_t)__builtin_ctz(g_mask & 0xffu);
+      g_mask &= ~(1u << i);
+      const uint32_t s = i ^ oct, im = g_mask >> 8;
+      cur = (int32_t)(g_base + (uint32_t)__builtin_popcount(im & ((1u << s) - 1u)));
+    }
+    const Node8& nd = b.nodes8[(size_t)cur];
+    const uint32_t hits = node8_boxes(nd, rb, best_t);
+    const uint32_t im = fbits(nd.w0.w) >> 24, lm = nd.w1.y >> 24;
+    for (int s = 0; s < 8; ++s) {
+      if (!((hits & lm) >> s & 1u)) continue;
+      const uint32_t meta = ((s < 4 ? nd.w1.z : nd.w1.w) >> (8 * (s & 3))) & 0xffu;
+      leaf_test(b, (nd.w1.y & 0xffffffu) + (meta & 31u), (meta >> 5) + 1u, o, d, excl, best_t, best,
+                best_orig);
+    }
+    const uint32_t inner = hits & im;
+    if (inner) {
+      if (g_mask & 0xffu) {
+        if (sp >= kMaxDepth + 2) return -2;
+        gs_base[sp] = g_base;
+        gs_mask[sp] = g_mask;
+        ++sp;
+      }
+      g_base = nd.w1.x;
+      g_mask = octant_order(inner, oct) | (im << 8);
+    }
+    cur = -1;
+  }
+  if (t_out) *t_out = best_t;
+  return best;
+}
+
 int32_t host_brute(const BuiltBvh& b, const float o[3], const float d[3], float tmax,
                    int32_t excl, float* t_out) {
   float best_t = tmax;
@@ -636,7 +857,7 @@ uint64_t bvh_selfcheck(const BuiltBvh& b, uint32_t n_rays, uint64_t seed) {
     d[2] = (float)(z / q);
     int32_t excl = (nl && (r & 3) == 0) ? (int32_t)fbits(b.tris[3 * (size_t)(next() * nl)].w) : -1;
     float ta, tb;
-    int32_t ha = host_traverse(b, o, d, tmax, excl, &ta);
+    int32_t ha = b.width == 8 ? host_traverse8(b, o, d, tmax, excl, &ta) : host_traverse(b, o, d, tmax, excl, &ta);
     int32_t hb = host_brute(b, o, d, tmax, excl, &tb);
     uint32_t oa = ha >= 0 ? fbits(b.tris[3 * (size_t)ha].w) : 0xffffffffu;
     uint32_t ob = hb >= 0 ? fbits(b.tris[3 * (size_t)hb].w) : 0xffffffffu;

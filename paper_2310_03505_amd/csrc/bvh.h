@@ -14,17 +14,20 @@ struct BvhBuildOptions {
   uint32_t bins = 16;
   uint32_t threads = 0;
   uint32_t split_pct = 0;  // early split clipping budget, percent of the triangles
+  uint32_t width = 4;      // 4: Node4 tree; 8: Node8 tree
 };
 
 struct BuiltBvh {
+  uint32_t width = 4;             // which of the two node arrays is built
   std::vector<Node4> nodes;       // four-wide inner nodes, node 0 is the root
+  std::vector<Node8> nodes8;      // eight-wide inner nodes, node 0 is the root
   std::vector<float4> tris;       // 3 per leaf triangle: (v0, orig), (e1, 0), (e2, 0)
   std::vector<float4> aux;        // 1 per scene triangle, original order: (unit normal, material bits)
   uint32_t n_tris = 0;            // triangles in the scene
   uint32_t n_hittable = 0;        // non-degenerate triangles in the leaves
   uint32_t n_refs = 0;            // triangle references in the leaves (>= n_hittable)
   uint32_t n_leaves = 0;
-  uint32_t max_depth = 0;         // deepest four-wide inner node (root = 0)
+  uint32_t max_depth = 0;         // deepest wide inner node (root = 0)
   uint32_t max_depth2 = 0;        // deepest node of the two-wide build tree
   uint32_t max_stack = 0;         // worst-case traversal stack entries
   float pad = 0.0f;               // absolute box padding

@@ -16,7 +16,8 @@ struct QueueView {
 
 // Arguments shared by the per-level kernels.
 struct LevelArgs {
-  const Node4* nodes;
+  const Node4* nodes;   // four-wide tree, or
+  const Node8* nodes8;  // eight-wide tree (exactly one is set)
   uint32_t n_nodes;  // inner nodes (bounds the node visits of one ray)
   uint32_t depth;
   const float4* tris;
@@ -71,7 +72,9 @@ constexpr int kProfPoolMax = kProfMaxVisits + 8;  // fused scan: largest child p
 constexpr int kProfWords = kProfPoolMax + 1;
 constexpr int kBlock = 256;
 constexpr uint32_t kMaxLevels = 8;   // bounce levels (interactions per path) at most
-constexpr uint32_t kLeafRing = 512;  // trace: leaf entries per wave in LDS (power of two)
+constexpr uint32_t kLeafRing = 512;
+constexpr uint32_t kLeafRing8 = 1024;  // eight-wide trace: leaf entries per wave (power of two)
+constexpr int kStack8 = 6;              // eight-wide trace: node groups per lane in LDS  // trace: leaf entries per wave in LDS (power of two)
 constexpr int kTraceBlock = 128;  // trace workgroup (LDS stack of kStack words per lane)
 
 }  // namespace rr

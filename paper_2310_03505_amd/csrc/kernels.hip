@@ -374,6 +374,249 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   }
 }
 
+// Closest-hit traversal of the eight-wide tree (after Ylitie, Karras and
+// Laine, "Efficient incoherent ray traversal on GPUs through compressed wide
+// BVHs", HPG 2017): instead of sorting hit children, a node's hit inner
+// children form a group (first child, hit slots in the ray's octant order,
+// inner-slot mask) and the traversal takes them lowest order bit first; a
+// visit pushes at most the rest of the current group.  Hit leaves go to the
+// wave's leaf ring (one 32-bit entry: lane << 26 | (count - 1) << 24 | first
+// triangle) and are tested in triangle phases exactly as in k_trace; the
+// refill, the per-lane (t, original id) minimum and the completion rule are
+// those of k_trace.
+template <bool kCount>
+__global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
+  __shared__ uint2 lds_gstack[kStack8 * kTraceBlock];           // node groups
+  __shared__ uint32_t lds_leaf[kTraceBlock / 64][kLeafRing8];
+  __shared__ unsigned long long lds_best[kTraceBlock];
+  uint2* gstk = lds_gstack + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wib = threadIdx.x >> 6;
+  const uint32_t wave_base = threadIdx.x - lane;
+  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+  const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
+  uint32_t* cursor = A.counters + kCtrWork + A.depth;
+  const Node8* __restrict__ nodes = A.nodes8;
+  const float4* __restrict__ tris = A.tris;
+  const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t spill_stride = gridDim.x * blockDim.x;
+  uint2* const spill = reinterpret_cast<uint2*>(A.spill);
+  const uint32_t tri_batch = min(max(A.tri_batch, 1u), 64u);
+
+  bool valid = false, exhausted = false;
+  uint32_t pool_next = 0, pool_end = 0;
+  uint32_t ring_head = 0, ring_tail = 0;
+  uint32_t ridx = 0, visits = 0, excl = 0xffffffffu, last_pos = 0, oct = 0;
+  float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0;
+  RayBox rb{};
+  int32_t cur = 0;                     // node to visit (-1: take one from the group)
+  uint32_t g_base = 0, g_mask = 0;     // current group
+  int sp = 0;
+  bool trav_done = false;
+  uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0;
+  uint64_t cnt_iters = 0, cnt_active = 0, cnt_tail_iters = 0, cnt_tail_active = 0;
+  uint32_t cnt_max_visits = 0;
+
+  for (;;) {
+    uint64_t idle = __ballot(!valid);
+    if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
+#pragma unroll 1
+      for (int pass = 0; pass < 2 && idle; ++pass) {
+        if (pool_next >= pool_end) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(cursor, A.pool);
+          base = __shfl(base, 0);
+          pool_next = base;
+          pool_end = min(base + A.pool, n_in);
+          if (base >= n_in) {
+            exhausted = true;
+            break;
+          }
+        }
+        const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
+        const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+        if (!valid && rank < take) {
+          const uint32_t my = pool_next + rank;
+          const float4 a = A.in.a[my];
+          const float4 b = A.in.b[my];
+          const uint32_t m = A.in.m[my];
+          excl = A.in.c[my].w;
+          const uint32_t medium = (m >> 8) & 0xffu;
+          const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
+          best_t = (A.scans[m >> 16].r_max - a.w) / n_cur;
+          lds_best[threadIdx.x] = ((unsigned long long)__float_as_uint(best_t) << 32) | 0xffffffffull;
+          ox = a.x;
+          oy = a.y;
+          oz = a.z;
+          dx = b.x;
+          dy = b.y;
+          dz = b.z;
+          ray_box_setup(ox, oy, oz, dx, dy, dz, rb);
+          oct = ray_octant(rb);
+          ridx = my;
+          cur = 0;
+          g_mask = 0;
+          sp = 0;
+          visits = 0;
+          last_pos = ring_head;
+          trav_done = false;
+          valid = true;
+          if (kCount) ++cnt_rays;
+        }
+        pool_next += take;
+        idle = __ballot(!valid);
+        if (pool_next >= pool_end && pool_end >= n_in) exhausted = true;
+      }
+    }
+    const uint64_t live = __ballot(valid);
+    if (live == 0ull) break;
+    if (kCount) {
+      ++cnt_iters;
+      cnt_active += (uint64_t)__popcll(live);
+      if (exhausted) {
+        ++cnt_tail_iters;
+        cnt_tail_active += (uint64_t)__popcll(live);
+      }
+    }
+
+    const uint64_t walking = __ballot(valid && !trav_done);
+    const uint32_t queued = ring_head - ring_tail;
+    const bool tri_phase = queued >= tri_batch ||
+                           (queued > 0 && (walking == 0ull || queued + 8u * (uint32_t)__popcll(walking) > kLeafRing8));
+    if (tri_phase) {
+      const uint32_t n = min(queued, 64u);
+      const bool take = lane < n;
+      const uint32_t e = take ? lds_leaf[wib][(ring_tail + lane) & (kLeafRing8 - 1u)] : (lane << 26);
+      const int own = (int)(e >> 26);
+      const float rox = __shfl(ox, own), roy = __shfl(oy, own), roz = __shfl(oz, own);
+      const float rdx = __shfl(dx, own), rdy = __shfl(dy, own), rdz = __shfl(dz, own);
+      const uint32_t rexcl = __shfl(excl, own);
+      if (take) {
+        unsigned long long cb = lds_best[wave_base + own];
+        float tmax = __uint_as_float((uint32_t)(cb >> 32));
+        const uint32_t start = e & 0xffffffu, count = ((e >> 24) & 3u) + 1u;
+#pragma unroll 1
+        for (uint32_t k = 0; k < count; ++k) {
+          const uint32_t li = start + k;
+          const float4 ta = tris[3 * li + 0];
+          const uint32_t orig = __float_as_uint(ta.w);
+          if (orig == rexcl) continue;
+          if (kCount) ++cnt_tris;
+          const float4 e1 = tris[3 * li + 1];
+          const float4 e2 = tris[3 * li + 2];
+          float t;
+          if (ray_tri(rox, roy, roz, rdx, rdy, rdz, ta.x, ta.y, ta.z, e1.x, e1.y, e1.z, e2.x, e2.y, e2.z,
+                      tmax, t)) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(t) << 32) | orig;
+            if (key < cb) {
+              atomicMin(&lds_best[wave_base + own], key);
+              cb = key;
+              tmax = t;
+            }
+          }
+        }
+      }
+      ring_tail += n;
+      __builtin_amdgcn_wave_barrier();
+      if (valid) best_t = __uint_as_float((uint32_t)(lds_best[threadIdx.x] >> 32));
+    } else {
+      uint32_t leaves = 0, l_first = 0, l_meta0 = 0, l_meta1 = 0;  // hit leaf slots of this visit
+      if (valid && !trav_done) {
+        if (cur < 0) {
+          if ((g_mask & 0xffu) == 0u) {
+            if (sp > 0) {
+              --sp;
+              const uint2 ge = sp < kStack8 ? gstk[sp * kTraceBlock]
+                                            : spill[(size_t)(sp - kStack8) * spill_stride + gtid];
+              g_base = ge.x;
+              g_mask = ge.y;
+            } else {
+              trav_done = true;
+            }
+          }
+          if (!trav_done) {
+            const uint32_t i = (uint32_t)__builtin_ctz(g_mask & 0xffu);
+            g_mask &= ~(1u << i);
+            const uint32_t s = i ^ oct;
+            cur = (int32_t)(g_base + (uint32_t)__popc((g_mask >> 8) & ((1u << s) - 1u)));
+          }
+        }
+        if (!trav_done) {
+          const float4* np = reinterpret_cast<const float4*>(nodes + cur);
+          Node8 nd;
+          nd.w0 = np[0];
+          nd.w1 = reinterpret_cast<const uint4*>(np)[1];
+          nd.w2 = reinterpret_cast<const uint4*>(np)[2];
+          nd.w3 = reinterpret_cast<const uint4*>(np)[3];
+          nd.w4 = reinterpret_cast<const uint4*>(np)[4];
+          if (kCount) ++cnt_nodes;
+          const uint32_t hits = node8_boxes(nd, rb, best_t);
+          const uint32_t im = __float_as_uint(nd.w0.w) >> 24;
+          leaves = hits & (nd.w1.y >> 24);
+          l_first = nd.w1.y & 0xffffffu;
+          l_meta0 = nd.w1.z;
+          l_meta1 = nd.w1.w;
+          const uint32_t inner = hits & im;
+          if (inner) {
+            if ((g_mask & 0xffu) && sp < kStack8 + kSpill / 2) {
+              if (sp < kStack8)
+                gstk[sp * kTraceBlock] = make_uint2(g_base, g_mask);
+              else
+                spill[(size_t)(sp - kStack8) * spill_stride + gtid] = make_uint2(g_base, g_mask);
+              ++sp;
+            }
+            g_base = nd.w1.x;
+            g_mask = octant_order(inner, oct) | (im << 8);
+          }
+          cur = -1;
+          // every node is entered at most once per ray; the bound only guards
+          // against a malformed tree
+          if (++visits > A.n_nodes) trav_done = true;
+        }
+      }
+      // hit leaves into the ring: exclusive prefix of the per-lane counts
+      // from one ballot per count bit (all lanes take part)
+      const uint32_t cnt = (uint32_t)__popc(leaves);
+      uint32_t prefix = 0, total = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const uint64_t m = __ballot((cnt >> b) & 1u);
+        prefix += (uint32_t)__popcll(m & lanes_below) << b;
+        total += (uint32_t)__popcll(m) << b;
+      }
+      uint32_t p = ring_head + prefix;
+      while (leaves) {
+        const uint32_t s = (uint32_t)__builtin_ctz(leaves);
+        leaves &= leaves - 1u;
+        const uint32_t meta = ((s < 4 ? l_meta0 : l_meta1) >> (8 * (s & 3u))) & 0xffu;
+        lds_leaf[wib][p & (kLeafRing8 - 1u)] = (lane << 26) | ((meta >> 5) << 24) | (l_first + (meta & 31u));
+        last_pos = ++p;
+      }
+      ring_head += total;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    if (valid && trav_done && (int32_t)(ring_tail - last_pos) >= 0) {
+      if (kCount) cnt_max_visits = max(cnt_max_visits, visits);
+      const unsigned long long b = lds_best[threadIdx.x];
+      A.hits[ridx] = make_uint2((uint32_t)(b >> 32), (uint32_t)b);
+      valid = false;
+    }
+  }
+  if (kCount) {
+    atomicAdd(A.prof + 0, (unsigned long long)cnt_nodes);
+    atomicAdd(A.prof + 1, (unsigned long long)cnt_tris);
+    atomicAdd(A.prof + 2, (unsigned long long)cnt_rays);
+    atomicMax(A.prof + kProfMaxVisits + A.depth, (unsigned long long)cnt_max_visits);
+    if (lane == 0) {
+      atomicAdd(A.prof + kProfIters + A.depth, (unsigned long long)cnt_iters);
+      atomicAdd(A.prof + kProfActive + A.depth, (unsigned long long)cnt_active);
+      atomicAdd(A.prof + kProfTailIters + A.depth, (unsigned long long)cnt_tail_iters);
+      atomicAdd(A.prof + kProfTailActive + A.depth, (unsigned long long)cnt_tail_active);
+    }
+  }
+}
+
 // Wave-aggregated append of up to one ray per lane into a queue: one atomic
 // per wave.  Returns the slot of this lane (valid only if `want`).
 __device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter, uint32_t lane,
@@ -1086,6 +1329,13 @@ hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st) {
 
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
   const dim3 g(grid ? grid : 1), b(kTraceBlock);
+  if (a.nodes8) {
+    if (a.prof)
+      hipLaunchKernelGGL(k_trace8<true>, g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL(k_trace8<false>, g, b, 0, st, a);
+    return hipGetLastError();
+  }
   if (a.prof)
     hipLaunchKernelGGL(k_trace<true>, g, b, 0, st, a);
   else

@@ -24,20 +24,6 @@ struct alignas(16) uint4 {
 
 namespace rr {
 
-// BVH2 node, 64 bytes: the boxes of both children are stored in the parent
-// so one 64-byte fetch decides both (Aila & Laine 2009 layout).
-//   n0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
-//   n1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
-//   n2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
-//   n3 = (child0, child1, count0, count1)
-// child >= 0: inner node index; child < 0: leaf whose triangles start at
-// ~child in the leaf-ordered triangle array, count in n3.z / n3.w.
-struct alignas(64) Node {
-  float4 n0, n1, n2;
-  int4 n3;
-};
-static_assert(sizeof(Node) == 64, "node layout");
-
 constexpr int kMaxDepth = 32;  // two-wide build: inner-node depth bound
 constexpr int kStack = 20;     // traversal stack entries per lane held in LDS
 constexpr int kSpill = 76;     // further entries per lane in workspace memory
@@ -229,20 +215,78 @@ RR_HD uint32_t node4_boxes(const float4& w0, const uint4& w1, const uint4& w2, c
   return mask;
 }
 
-RR_HD void node_boxes(const float4& n0, const float4& n1, const float4& n2, const RayBox& r,
-                      float tmax, bool& hit0, bool& hit1, float& tn0, float& tn1) {
-  float l0x = fmaf(n0.x, r.ix, -r.oix), h0x = fmaf(n0.y, r.ix, -r.oix);
-  float l0y = fmaf(n0.z, r.iy, -r.oiy), h0y = fmaf(n0.w, r.iy, -r.oiy);
-  float l0z = fmaf(n2.x, r.iz, -r.oiz), h0z = fmaf(n2.y, r.iz, -r.oiz);
-  float l1x = fmaf(n1.x, r.ix, -r.oix), h1x = fmaf(n1.y, r.ix, -r.oix);
-  float l1y = fmaf(n1.z, r.iy, -r.oiy), h1y = fmaf(n1.w, r.iy, -r.oiy);
-  float l1z = fmaf(n2.z, r.iz, -r.oiz), h1z = fmaf(n2.w, r.iz, -r.oiz);
-  tn0 = fmaxf(fmaxf(fminf(l0x, h0x), fminf(l0y, h0y)), fmaxf(fminf(l0z, h0z), 0.0f));
-  float tf0 = fminf(fminf(fmaxf(l0x, h0x), fmaxf(l0y, h0y)), fminf(fmaxf(l0z, h0z), tmax));
-  tn1 = fmaxf(fmaxf(fminf(l1x, h1x), fminf(l1y, h1y)), fmaxf(fminf(l1z, h1z), 0.0f));
-  float tf1 = fminf(fminf(fmaxf(l1x, h1x), fmaxf(l1y, h1y)), fminf(fmaxf(l1z, h1z), tmax));
-  hit0 = tn0 <= tf0 * kSlabSlack;
-  hit1 = tn1 <= tf1 * kSlabSlack;
+// Eight-wide node, 80 bytes (five 16-byte loads):
+//   w0 = (origin.x, origin.y, origin.z, ex | ey << 8 | ez << 16 | imask << 24)
+//   w1 = (first inner child, first triangle | leafmask << 24, meta[0..3], meta[4..7])
+//   w2 = (qlo.x[0..3], qlo.x[4..7], qhi.x[0..3], qhi.x[4..7])   one byte per slot
+//   w3 = (qlo.y[0..3], qlo.y[4..7], qhi.y[0..3], qhi.y[4..7])
+//   w4 = (qlo.z[0..3], qlo.z[4..7], qhi.z[0..3], qhi.z[4..7])
+// Slot s holds an inner child (imask bit s: node first + number of inner
+// slots below s, so the inner children of a node are consecutive), a leaf
+// (leafmask bit s: meta[s] = (count - 1) << 5 | offset, its triangles at
+// first triangle + offset ...), or nothing.  The builder puts the child that
+// lies toward the box corner with sign bits s (bit a set: high side of axis
+// a) into slot s, so a ray whose direction has sign bits o (bit a set:
+// negative) meets the children roughly in the order of slot i ^ o, i = 0..7.
+struct alignas(16) Node8 {
+  float4 w0;
+  uint4 w1, w2, w3, w4;
+};
+static_assert(sizeof(Node8) == 80, "node layout");
+constexpr uint32_t kMaxTris8 = 1u << 24;  // triangle references an eight-wide tree addresses
+
+// Hit mask of the eight children of a quantised node (bit s: slot s's box
+// meets [0, tmax]); tn[s] receives the entry distances.  Same decode and
+// conservative rounding as node4_boxes.
+RR_HD uint32_t node8_boxes(const Node8& n, const RayBox& r, float tmax) {
+  uint32_t eb;
+#if defined(__HIP_DEVICE_COMPILE__)
+  eb = __float_as_uint(n.w0.w);
+#else
+  __builtin_memcpy(&eb, &n.w0.w, 4);
+#endif
+  const float sx = pow2_from_byte(eb & 0xffu) * r.ix;
+  const float sy = pow2_from_byte((eb >> 8) & 0xffu) * r.iy;
+  const float sz = pow2_from_byte((eb >> 16) & 0xffu) * r.iz;
+  const float bx = fmaf(n.w0.x, r.ix, -r.oix);
+  const float by = fmaf(n.w0.y, r.iy, -r.oiy);
+  const float bz = fmaf(n.w0.z, r.iz, -r.oiz);
+  const bool px = r.ix >= 0.0f, py = r.iy >= 0.0f, pz = r.iz >= 0.0f;
+  // near / far planes: (lo, hi) bytes for a positive direction, else swapped
+  const uint32_t nx0 = px ? n.w2.x : n.w2.z, nx1 = px ? n.w2.y : n.w2.w;
+  const uint32_t fx0 = px ? n.w2.z : n.w2.x, fx1 = px ? n.w2.w : n.w2.y;
+  const uint32_t ny0 = py ? n.w3.x : n.w3.z, ny1 = py ? n.w3.y : n.w3.w;
+  const uint32_t fy0 = py ? n.w3.z : n.w3.x, fy1 = py ? n.w3.w : n.w3.y;
+  const uint32_t nz0 = pz ? n.w4.x : n.w4.z, nz1 = pz ? n.w4.y : n.w4.w;
+  const uint32_t fz0 = pz ? n.w4.z : n.w4.x, fz1 = pz ? n.w4.w : n.w4.y;
+  const uint32_t present = (eb >> 24) | (n.w1.y >> 24);
+  uint32_t mask = 0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int j = s & 3;
+    const uint32_t nx = s < 4 ? nx0 : nx1, fx = s < 4 ? fx0 : fx1;
+    const uint32_t ny = s < 4 ? ny0 : ny1, fy = s < 4 ? fy0 : fy1;
+    const uint32_t nz = s < 4 ? nz0 : nz1, fz = s < 4 ? fz0 : fz1;
+    const float tnx = fmaf(byte_f(nx, j), sx, bx), tfx = fmaf(byte_f(fx, j), sx, bx);
+    const float tny = fmaf(byte_f(ny, j), sy, by), tfy = fmaf(byte_f(fy, j), sy, by);
+    const float tnz = fmaf(byte_f(nz, j), sz, bz), tfz = fmaf(byte_f(fz, j), sz, bz);
+    const float a = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+    const float f = fminf(fminf(tfx, tfy), fminf(tfz, tmax));
+    if (a <= f * kSlabSlack) mask |= 1u << s;
+  }
+  return mask & present;
+}
+
+// Octant code of a ray (bit a set: negative direction on axis a) and the
+// hit mask reordered so that bit i stands for slot i ^ octant.
+RR_HD uint32_t ray_octant(const RayBox& r) {
+  return (r.ix < 0.0f ? 1u : 0u) | (r.iy < 0.0f ? 2u : 0u) | (r.iz < 0.0f ? 4u : 0u);
+}
+RR_HD uint32_t octant_order(uint32_t m, uint32_t oct) {
+  if (oct & 1u) m = ((m & 0x55u) << 1) | ((m >> 1) & 0x55u);
+  if (oct & 2u) m = ((m & 0x33u) << 2) | ((m >> 2) & 0x33u);
+  if (oct & 4u) m = ((m & 0x0fu) << 4) | ((m >> 4) & 0x0fu);
+  return m;
 }
 
 }  // namespace rr

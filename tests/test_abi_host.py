@@ -113,6 +113,27 @@ def test_host_bvh_options(R, leaf, bins):
     sc.release()
 
 
+@pytest.mark.parametrize("width,leaf,split", [(8, 4, 0), (8, 2, 0), (8, 1, 0), (4, 4, 50), (8, 3, 100)])
+def test_host_bvh_wide_and_split(R, width, leaf, split):
+    """Eight-wide trees (octant-ordered groups, merged leaves) and early split
+    clipping (a triangle in several leaves) find the brute-force closest hit."""
+    for s, n in ((W.tiny_room(), 4000), (W.urban_block(), 1000)):
+        sc = R.Scene(None, s.vertices, s.indices, s.tri_material, width=width, max_leaf_size=leaf,
+                     split_pct=split)
+        info = sc.info()
+        assert info["n_tris"] == s.n_tris and info["n_nodes"] > 0
+        assert sc.selfcheck(n, 13) == 0
+        sc.release()
+
+
+def test_bvh_option_validation(R):
+    s = W.tiny_room()
+    for bad in (dict(width=6), dict(width=8, max_leaf_size=5), dict(split_pct=201)):
+        with pytest.raises(R.RadarError) as e:
+            R.Scene(None, s.vertices, s.indices, s.tri_material, **bad)
+        assert e.value.status == R.RR_EINVAL
+
+
 def test_deep_median_fallback_bounds_depth(R):
     """A pathological mesh (triangles in a geometric progression along x)
     would give a very deep SAH tree; the builder caps inner depth below the
@@ -127,7 +148,8 @@ def test_deep_median_fallback_bounds_depth(R):
     V[2::3, 0] = xs
     V[2::3, 2] = 0.5
     F = np.arange(3 * n, dtype=np.uint32).reshape(n, 3)
-    sc = R.Scene(None, V, F, np.zeros(n, np.uint16), max_leaf_size=1)
-    assert sc.info()["max_stack"] <= 96
-    assert sc.selfcheck(3000, 11) == 0
-    sc.release()
+    for width in (4, 8):
+        sc = R.Scene(None, V, F, np.zeros(n, np.uint16), max_leaf_size=1, width=width)
+        assert sc.info()["max_stack"] <= (96 if width == 4 else 44)
+        assert sc.selfcheck(3000, 11) == 0
+        sc.release()

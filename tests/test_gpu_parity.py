@@ -274,6 +274,31 @@ def test_fused_launch_equals_levels(R, ctx):
         R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
 
 
+def test_eight_wide_equals_four_wide(R, ctx):
+    """The eight-wide tree (octant-ordered node groups) finds the same closest
+    hits as the four-wide one: records, accumulator and image bit for bit."""
+    import torch
+    s, u = W.tiny_room(), W.urban_block()
+    cases = [(s, s.params, s.pose),
+             (s, dict(s.params, max_bounces=8, n_azimuth=64, rays_per_beam=16), W.yaw_pose((0.5, 0.3, 0.4), 1.1)),
+             (u, dict(u.params, n_azimuth=40), u.pose)]
+    for scene, p, pose in cases:
+        outs = []
+        for width in (4, 8):
+            sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material, width=width)
+            try:
+                o = R.rr_radar_scan_records(ctx.handle, sc.handle, pose, p, scene.materials)
+                torch.cuda.synchronize()
+                outs.append(o)
+            finally:
+                sc.release()
+        a, b = outs
+        assert torch.equal(a["records"], b["records"])
+        assert torch.equal(a["accum"], b["accum"])
+        assert torch.equal(a["image"], b["image"])
+        assert a["stats"]["rays_per_depth"] == b["stats"]["rays_per_depth"]
+
+
 def test_workspace_variant_matches(R, ctx):
     import torch
     s = W.tiny_room(n_azimuth=100, rays_per_beam=32)
