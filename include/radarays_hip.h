@@ -107,14 +107,19 @@ typedef struct {
 
 /* BVH build options (all zero = defaults). */
 typedef struct {
-  uint32_t max_leaf_size; /* triangles per leaf, 1..16, default 4 */
+  uint32_t max_leaf_size; /* triangles per leaf, 1..16 (1..4 for width 8), default 2 */
   uint32_t sah_bins;      /* SAH bins per axis, 4..64, default 16 */
   uint32_t n_threads;     /* host build threads, 0 = all cores */
   uint32_t split_pct;     /* early split clipping: extra triangle references, in
                              percent of the triangle count, 0..200 (0 = none) */
   uint32_t width;         /* children per node: 4 (default) or 8 (compressed
                              eight-wide nodes, leaves of at most 4 triangles) */
-  uint32_t reserved[3];
+  uint32_t merge_leaves;  /* 0: default (1); 1: the binary build goes down to
+                             single triangles and the wide collapse forms
+                             leaves of at most max_leaf_size references
+                             (always so for width 8); 2: leaves are those of
+                             the binary SAH build */
+  uint32_t reserved[2];
 } rr_bvh_options;
 
 typedef struct {

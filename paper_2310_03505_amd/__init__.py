@@ -46,7 +46,7 @@ class rr_material(C.Structure):
 class rr_bvh_options(C.Structure):
     _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32),
                 ("n_threads", C.c_uint32), ("split_pct", C.c_uint32), ("width", C.c_uint32),
-                ("reserved", C.c_uint32 * 3)]
+                ("merge_leaves", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 class rr_bvh_info(C.Structure):
@@ -234,8 +234,8 @@ def rr_scene_upload(ctx, vertices, indices, tri_material):
 
 
 def rr_bvh_build(ctx, scene, max_leaf_size: int = 0, sah_bins: int = 0, n_threads: int = 0,
-                 split_pct: int = 0, width: int = 0):
-    opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, split_pct, width)
+                 split_pct: int = 0, width: int = 0, merge_leaves: int = 0):
+    opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, split_pct, width, merge_leaves)
     _check(load_library().rr_bvh_build(ctx, scene, C.byref(opt)), ctx)
 
 

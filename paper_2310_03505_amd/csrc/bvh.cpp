@@ -240,6 +240,10 @@ struct Flattener4 {
   BuiltBvh& out;
   float pad;
   double root_area;
+  uint32_t leaf_max = 0;  // > 0: a subtree with at most this many references becomes one leaf
+
+  static uint32_t refs_of(const BNode* k) { return k->leaf() ? k->count : k->span; }
+  bool is_leaf(const BNode* k) const { return k->leaf() || (leaf_max && k->span <= leaf_max); }
 
   static void quantise_axis(float lo, float hi, float& origin, uint32_t& ebyte) {
     origin = lo;
@@ -256,14 +260,14 @@ struct Flattener4 {
   }
 
   uint32_t leaf_ref(const BNode* b, int32_t* ref, uint32_t* count) {
-    if (b->count == 0) {
+    if (refs_of(b) == 0) {
       *ref = kEmpty;
       *count = 0;
       return 0;
     }
     uint32_t start = (uint32_t)(out.tris.size() / 3);
     uint32_t kept = 0;
-    for (uint32_t i = 0; i < b->count; ++i) {
+    for (uint32_t i = 0; i < refs_of(b); ++i) {
       uint32_t id = refs[b->begin + i].id;
       bool dup = false;  // split references of one triangle in the same leaf
       for (uint32_t k = 0; k < i; ++k) dup = dup || refs[b->begin + k].id == id;
@@ -284,13 +288,19 @@ struct Flattener4 {
   uint32_t emit(const BNode* b, uint32_t depth, int32_t* ref_out) {
     std::vector<const BNode*> kids{b->l.get(), b->r.get()};
     while (kids.size() < 4) {
+      // open the largest child that has children, those too big for a leaf first
       int best = -1;
       double ba = -1.0;
-      for (size_t i = 0; i < kids.size(); ++i)
-        if (!kids[i]->leaf() && kids[i]->box.area() > ba) {
+      bool big = false;
+      for (size_t i = 0; i < kids.size(); ++i) {
+        if (kids[i]->leaf()) continue;
+        const bool kb = !is_leaf(kids[i]);
+        if ((kb && !big) || ((kb == big) && kids[i]->box.area() > ba)) {
           ba = kids[i]->box.area();
           best = (int)i;
+          big = kb;
         }
+      }
       if (best < 0) break;
       const BNode* o = kids[(size_t)best];
       kids[(size_t)best] = o->l.get();
@@ -333,7 +343,7 @@ struct Flattener4 {
         qlo[a] |= ql << (8 * j);
         qhi[a] |= qh << (8 * j);
       }
-      if (k->leaf()) {
+      if (is_leaf(k)) {
         uint32_t cnt;
         leaf_ref(k, &ref[j], &cnt);
         if (cnt) ++n_kids;
@@ -656,7 +666,8 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
   while ((1u << par_depth) < th && par_depth < 8) ++par_depth;
   // the eight-wide collapse forms its own leaves (subtrees of at most
   // max_leaf references), so its binary tree goes down to single triangles
-  const uint32_t leaf2 = opt.width == 8 ? 1u : std::max(1u, opt.max_leaf);
+  const bool merge = opt.width == 8 || opt.merge_leaves;
+  const uint32_t leaf2 = merge ? 1u : std::max(1u, opt.max_leaf);
   Builder bld{refs, leaf2, std::max(4u, opt.bins), par_depth};
   std::unique_ptr<BNode> root;
   uint32_t n = (uint32_t)refs.size();
@@ -681,7 +692,8 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
     out.nodes8.resize(1);
     out.max_stack = fl.fill(root.get(), 0, 0);
   } else {
-    Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area()};
+    Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area(),
+                  merge ? std::max(1u, opt.max_leaf) : 0u};
     int32_t root_ref;
     out.max_stack = fl.emit(root.get(), 0, &root_ref);
   }

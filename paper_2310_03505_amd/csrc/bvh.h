@@ -10,11 +10,12 @@
 namespace rr {
 
 struct BvhBuildOptions {
-  uint32_t max_leaf = 4;
+  uint32_t max_leaf = 2;
   uint32_t bins = 16;
   uint32_t threads = 0;
   uint32_t split_pct = 0;  // early split clipping budget, percent of the triangles
   uint32_t width = 4;      // 4: Node4 tree; 8: Node8 tree
+  bool merge_leaves = true;  // binary tree to single triangles, leaves formed by the wide collapse
 };
 
 struct BuiltBvh {

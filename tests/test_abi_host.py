@@ -113,13 +113,14 @@ def test_host_bvh_options(R, leaf, bins):
     sc.release()
 
 
-@pytest.mark.parametrize("width,leaf,split", [(8, 4, 0), (8, 2, 0), (8, 1, 0), (4, 4, 50), (8, 3, 100)])
-def test_host_bvh_wide_and_split(R, width, leaf, split):
+@pytest.mark.parametrize("width,leaf,split,merge", [(8, 4, 0, 0), (8, 2, 0, 0), (8, 1, 0, 0), (4, 4, 50, 2),
+                                                    (8, 3, 100, 0), (4, 2, 0, 1), (4, 4, 0, 2)])
+def test_host_bvh_wide_and_split(R, width, leaf, split, merge):
     """Eight-wide trees (octant-ordered groups, merged leaves) and early split
     clipping (a triangle in several leaves) find the brute-force closest hit."""
     for s, n in ((W.tiny_room(), 4000), (W.urban_block(), 1000)):
         sc = R.Scene(None, s.vertices, s.indices, s.tri_material, width=width, max_leaf_size=leaf,
-                     split_pct=split)
+                     split_pct=split, merge_leaves=merge)
         info = sc.info()
         assert info["n_tris"] == s.n_tris and info["n_nodes"] > 0
         assert sc.selfcheck(n, 13) == 0
@@ -128,7 +129,7 @@ def test_host_bvh_wide_and_split(R, width, leaf, split):
 
 def test_bvh_option_validation(R):
     s = W.tiny_room()
-    for bad in (dict(width=6), dict(width=8, max_leaf_size=5), dict(split_pct=201)):
+    for bad in (dict(width=6), dict(width=8, max_leaf_size=5), dict(split_pct=201), dict(merge_leaves=3)):
         with pytest.raises(R.RadarError) as e:
             R.Scene(None, s.vertices, s.indices, s.tri_material, **bad)
         assert e.value.status == R.RR_EINVAL
