@@ -300,9 +300,9 @@ def main():
     cnt = R.rr_profile_read(c)
     R.rr_profile_enable(c, 0)
 
-    # timed region: K scans; HIP events around every bounce launch on the
-    # scan's stream (torch's current stream)
-    R.rr_profile_enable(c, R.RR_PROFILE_TIME)
+    # timed region: K scans; HIP events around every trace launch on the
+    # scan's stream (torch's current stream); the other launches carry none
+    R.rr_profile_enable(c, R.RR_PROFILE_TRACE_TIME)
     R.rr_profile_read(c)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -316,6 +316,12 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     prof = R.rr_profile_read(c)
+    # per-kernel breakdown from an untimed pass with events around every launch
+    R.rr_profile_enable(c, R.RR_PROFILE_TIME)
+    for _ in range(args.steps):
+        R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img)
+    torch.cuda.synchronize()
+    split = R.rr_profile_read(c)
     R.rr_profile_enable(c, 0)
 
     ms_per_step = ms / args.steps
@@ -324,7 +330,7 @@ def main():
 
     # roofline of the dominant kernel (k_trace): algorithmic bytes and flops
     # per launch from the counting pass, time per launch from the live events
-    launches_per_scan = p["max_bounces"]
+    launches_per_scan = prof["trace_launches"] / args.steps
     bytes_scan = (cnt["node_visits"] * NODE_BYTES + cnt["tri_tests"] * TRI_BYTES
                   + cnt["rays"] * (TRACE_RAY_BYTES + HIT_RECORD_BYTES))
     flops_scan = cnt["node_visits"] * NODE_FLOPS + cnt["tri_tests"] * TRI_FLOPS
@@ -346,9 +352,9 @@ def main():
                 node_visits_per_segment=round(cnt["node_visits"] / max(cnt["rays"], 1), 2),
                 tri_tests_per_segment=round(cnt["tri_tests"] / max(cnt["rays"], 1), 2),
                 trace_level_ms=[round(x / args.steps, 4)
-                                for x in prof["trace_level_ms"][:p["max_bounces"]]],
-                shade_ms_per_scan=round(prof["shade_ms"] / args.steps, 4),
-                raygen_ms_per_scan=round(prof["raygen_ms"] / args.steps, 4))
+                                for x in split["trace_level_ms"][:p["max_bounces"]]],
+                shade_ms_per_scan=round(split["shade_ms"] / args.steps, 4),
+                raygen_ms_per_scan=round(split["raygen_ms"] / args.steps, 4))
 
     out = {
         "metric": "Mray-segments/s", "value": round(seg_rate, 2), "unit": "Mray-segments/s",
@@ -360,7 +366,8 @@ def main():
                    "n_bins": p["n_bins"], "segments_per_scan": segs,
                    "rays_per_depth": st["rays_per_depth"][:p["max_bounces"]],
                    "scans_per_s": round(scans_per_s, 2), "bvh_nodes": info["n_nodes"],
-                   "bvh_depth": info["max_depth"], "wall_s": round(wall, 3)},
+                   "bvh_depth": info["max_depth"], "wall_s": round(wall, 3),
+                   "tuning": R.rr_get_tuning(c)},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -344,6 +344,7 @@ rr_status rr_graph_destroy(rr_graph* g);
 /* ---------------------------------------------------------------- profiling */
 #define RR_PROFILE_TIME 1u  /* bracket every kernel launch of a scan with HIP events */
 #define RR_PROFILE_COUNT 2u /* use the counting kernels: node visits, triangle tests */
+#define RR_PROFILE_TRACE_TIME 4u /* bracket only the trace launches with HIP events */
 
 typedef struct {
   uint64_t trace_launches;     /* closest-hit (trace) launches recorded */

@@ -72,7 +72,7 @@ class rr_profile(C.Structure):
                 ("max_ray_iters", C.c_uint64 * RR_MAX_BOUNCES)]
 
 
-RR_PROFILE_TIME, RR_PROFILE_COUNT = 1, 2
+RR_PROFILE_TIME, RR_PROFILE_COUNT, RR_PROFILE_TRACE_TIME = 1, 2, 4
 
 
 class rr_tuning(C.Structure):

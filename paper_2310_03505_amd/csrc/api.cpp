@@ -295,7 +295,8 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   a.masked = masked ? 1u : 0u;
   a.counters = d_ctr;
   a.prof = (ctx->prof_flags & RR_PROFILE_COUNT) ? ctx->d_prof : nullptr;
-  const bool timed = (ctx->prof_flags & RR_PROFILE_TIME) != 0;
+  const bool timed_all = (ctx->prof_flags & RR_PROFILE_TIME) != 0;
+  const bool timed_trace = timed_all || (ctx->prof_flags & RR_PROFILE_TRACE_TIME) != 0;
   // trace: persistent, enough waves to fill every CU; raygen/shade: grid-stride
   uint32_t trace_grid = std::max(1u, (uint32_t)ctx->n_cu * ctx->trace_waves_per_cu / (kTraceBlock / 64u));
   trace_grid = std::min(trace_grid, kSpillLanes / (uint32_t)kTraceBlock);
@@ -309,6 +310,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   a.shade_batch = ctx->shade_batch;
   const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
   auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
+    const bool timed = kind == 1 ? timed_trace : timed_all;
     rr_context::EvPair ev{};
     if (timed) {
       for (hipEvent_t* e : {&ev.a, &ev.b}) {
@@ -775,7 +777,8 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
 
 rr_status rr_profile_enable(rr_context* ctx, uint32_t flags) {
   if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
-  if (flags & ~(RR_PROFILE_TIME | RR_PROFILE_COUNT)) return fail(ctx, RR_EINVAL, "unknown profile flags");
+  if (flags & ~(RR_PROFILE_TIME | RR_PROFILE_COUNT | RR_PROFILE_TRACE_TIME))
+    return fail(ctx, RR_EINVAL, "unknown profile flags");
   DeviceGuard g(ctx->device);
   if ((flags & RR_PROFILE_COUNT) && !ctx->d_prof) {
     HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->d_prof), kProfWords * sizeof(unsigned long long)));
