@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # timed-variant dispatches), scaled by what the same counters read for a
 # plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
 # all of them).  Valid only for the kernel sources it was taken on.
-TRACE_HBM = dict(workload="urban_block_200k", fetch_kib=55481.3, write_kib=20666.5,
+TRACE_HBM = dict(workload="urban_block_200k", fetch_kib=55205.9, write_kib=20226.5,
                  fetch_scale=2.0, write_scale=1.0,
-                 sources_sha256="e11bb16dafc2989039078d6fa64a29fe9152e428a537b975bfe4bdfde3836311")
+                 sources_sha256="236aece52e48d02abfa5ec76b1e34f1eb688b3313ec16b6c0e9e0d9965cbf3d6")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
