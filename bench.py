@@ -77,6 +77,17 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, threads: int, n_cols: int):
     import numpy as np
     import oracle
@@ -86,10 +97,16 @@ def cpu_baseline(scene, threads: int, n_cols: int):
     out = oracle.scan_scene(scene, columns=cols, threads=threads, energy=False)
     dt = time.perf_counter() - t0
     segs = int(out["segments"].sum())
+    # one thread on two of those columns
+    t1 = time.perf_counter()
+    one = oracle.scan_scene(scene, columns=cols[:2], threads=1, energy=False)
+    dt1 = time.perf_counter() - t1
+    segs1 = int(one["segments"].sum())
     return dict(value=segs / dt / 1e6, unit="Mray-segments/s", cores=threads, kind="oracle",
                 sample=f"{n_cols} of {naz} azimuth columns of the same scan ({segs} segments, "
                        f"{dt:.1f} s wall, brute force over all triangles)",
-                scans_per_s=(segs / dt) / (segs / n_cols * naz))
+                scans_per_s_extrapolated=(segs / dt) / (segs / n_cols * naz),
+                one_thread_value=segs1 / dt1 / 1e6, cpu_model=cpu_model())
 
 
 def bench_trajectory(args):
@@ -346,7 +363,12 @@ def main():
     else:
         roof = dict(bound="alu", achieved=round(tfl, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(alu_frac, 4), traffic=trace_traffic(wname))
+    # random 64-byte gather peak at this scene's working set (nodes,
+    # triangles, hit attributes), the ceiling of node and triangle fetches
+    gather = R.rr_measure_gather(c, max(int(info["device_bytes"]), 1 << 20))
     roof.update(kernel="k_trace", launch_ms=round(launch_ms, 4),
+                gather_peak_gbs=round(gather, 1), gather_working_set=int(info["device_bytes"]),
+                frac_of_gather_peak=round(gbs / gather, 4),
                 bytes_per_launch=int(bytes_launch), flops_per_launch=int(flops_launch),
                 other_fraction=round(alu_frac if roof["bound"] == "hbm" else mem_frac, 4),
                 node_visits_per_segment=round(cnt["node_visits"] / max(cnt["rays"], 1), 2),

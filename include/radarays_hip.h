@@ -374,6 +374,13 @@ rr_status rr_profile_enable(rr_context* ctx, uint32_t flags);
  * resets them. */
 rr_status rr_profile_read(rr_context* ctx, rr_profile* out);
 
+/* Bandwidth probe for the roofline: random 64-byte row gathers (the access
+ * pattern of node and triangle fetches) over a device working set of
+ * `working_set_bytes` (>= 64 KiB, <= 16 GiB), `reads_mb` MiB read in total;
+ * returns the achieved read rate in GB/s.  Allocates and frees its buffers
+ * and synchronizes the device. */
+rr_status rr_measure_gather(rr_context* ctx, uint64_t working_set_bytes, uint32_t reads_mb, double* gbs);
+
 #ifdef __cplusplus
 }
 #endif

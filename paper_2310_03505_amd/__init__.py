@@ -106,7 +106,7 @@ EXPORTS = (
     "rr_radar_scan_batch", "rr_batch_workspace_query", "rr_profile_enable", "rr_profile_read",
     "rr_set_tuning", "rr_get_tuning", "rr_server_create", "rr_server_submit", "rr_server_wait",
     "rr_server_poll", "rr_server_get_stats", "rr_server_reset_stats", "rr_server_destroy",
-    "rr_autotune", "rr_graph_create", "rr_graph_launch", "rr_graph_destroy",
+    "rr_autotune", "rr_graph_create", "rr_graph_launch", "rr_graph_destroy", "rr_measure_gather",
 )
 
 _lib = None
@@ -161,6 +161,7 @@ def load_library():
                                  P(vp)]),
         "rr_graph_launch": (st, [vp, P(rr_scan_desc), vp]),
         "rr_graph_destroy": (st, [vp]),
+        "rr_measure_gather": (st, [vp, C.c_uint64, C.c_uint32, P(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -417,6 +418,13 @@ def rr_graph_launch(graph, scans=None, images=None, stream=None):
 
 def rr_graph_destroy(graph):
     _check(load_library().rr_graph_destroy(graph))
+
+
+def rr_measure_gather(ctx, working_set_bytes: int, reads_mb: int = 4096) -> float:
+    """Random 64-byte gather rate (GB/s) over a device working set."""
+    out = C.c_double()
+    _check(load_library().rr_measure_gather(ctx, working_set_bytes, reads_mb, C.byref(out)), ctx)
+    return float(out.value)
 
 
 def rr_profile_enable(ctx, flags: int):

@@ -788,6 +788,49 @@ rr_status rr_profile_enable(rr_context* ctx, uint32_t flags) {
   return RR_OK;
 }
 
+rr_status rr_measure_gather(rr_context* ctx, uint64_t ws_bytes, uint32_t reads_mb, double* gbs) {
+  if (!ctx || !gbs) return fail(ctx, RR_EINVAL, "NULL argument");
+  if (ws_bytes < (64u << 10) || ws_bytes > (16ull << 30)) return fail(ctx, RR_EINVAL, "working set out of range");
+  if (reads_mb == 0 || reads_mb > (1u << 20)) return fail(ctx, RR_EINVAL, "reads_mb out of range");
+  DeviceGuard g(ctx->device);
+  const uint32_t threads = (uint32_t)ctx->n_cu * 2048u;  // 32 waves per CU
+  const uint64_t n_rows64 = ws_bytes / 64u;
+  if (n_rows64 >= (1ull << 32)) return fail(ctx, RR_EINVAL, "working set out of range");
+  const uint32_t n_rows = (uint32_t)n_rows64;
+  const uint32_t steps = std::max<uint32_t>(1u, (uint32_t)(((uint64_t)reads_mb << 20) / (16ull * threads)));
+  void* buf = nullptr;
+  void* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rr_status s = RR_OK;
+  auto bail = [&](rr_status st) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (buf) (void)hipFree(buf);
+    if (out) (void)hipFree(out);
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&buf, (size_t)n_rows * 64u)) != hipSuccess ||
+      (e = hipMalloc(&out, sizeof(float) * threads)) != hipSuccess)
+    return bail(fail(ctx, RR_ENOMEM, "gather probe buffers: %s", hipGetErrorString(e)));
+  if ((e = hipMemset(buf, 0, (size_t)n_rows * 64u)) != hipSuccess || (e = hipEventCreate(&e0)) != hipSuccess ||
+      (e = hipEventCreate(&e1)) != hipSuccess)
+    return bail(fail(ctx, RR_EDEVICE, "gather probe: %s", hipGetErrorString(e)));
+  const float4* b4 = static_cast<const float4*>(buf);
+  float* o = static_cast<float*>(out);
+  // one warm pass, then the timed one
+  if ((e = launch_gather(b4, n_rows, steps, o, threads, nullptr)) != hipSuccess ||
+      (e = hipEventRecord(e0, nullptr)) != hipSuccess ||
+      (e = launch_gather(b4, n_rows, steps, o, threads, nullptr)) != hipSuccess ||
+      (e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+    return bail(fail(ctx, RR_EDEVICE, "gather probe: %s", hipGetErrorString(e)));
+  float ms = 0.0f;
+  if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+    return bail(fail(ctx, RR_EDEVICE, "gather probe: %s", hipGetErrorString(e)));
+  *gbs = 16.0 * threads * (double)steps / (ms * 1e-3) / 1e9;
+  return bail(s);
+}
+
 rr_status rr_profile_read(rr_context* ctx, rr_profile* out) {
   if (!ctx || !out) return fail(ctx, RR_EINVAL, "NULL argument");
   DeviceGuard g(ctx->device);

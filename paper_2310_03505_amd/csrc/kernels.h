@@ -51,6 +51,10 @@ hipError_t put_blob(void* dst_dev, const void* src, size_t bytes, hipStream_t st
 hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t count0,
                         hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
+// `threads` (a multiple of 256) lanes, each reading 16 B per step from a
+// hashed 64-byte row of `buf` (n_rows rows); one float per lane to `out`.
+hipError_t launch_gather(const float4* buf, uint32_t n_rows, uint32_t steps, float* out, uint32_t threads,
+                         hipStream_t st);
 hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st);

@@ -1276,6 +1276,33 @@ __global__ void k_clear(unsigned long long* acc, size_t n_acc, uint32_t* counter
   if (i < (size_t)kCtrWords) counters[i] = (i == (size_t)kCtrCount) ? count0 : 0u;
 }
 
+// Random 64-byte gathers over a working set (a bandwidth probe with the
+// access pattern of node and triangle fetches): each group of four lanes
+// reads one 64-byte row per step at a hashed index, coalesced as 4 x 16 B.
+__global__ void k_gather(const float4* buf, uint32_t n_rows, uint32_t steps, float* out) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t group = t >> 2, part = t & 3u;
+  float acc = 0.0f;
+  uint32_t h = group * 2654435761u + 0x9E3779B9u;
+#pragma unroll 4
+  for (uint32_t i = 0; i < steps; ++i) {
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    const float4 v = buf[(size_t)(h % n_rows) * 4u + part];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  out[t] = acc;
+}
+
+hipError_t launch_gather(const float4* buf, uint32_t n_rows, uint32_t steps, float* out, uint32_t threads,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(threads / 256u), dim3(256), 0, st, buf, n_rows, steps, out);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int32_t* p, size_t n, int32_t v) {
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) p[j] = v;
