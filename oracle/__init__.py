@@ -49,6 +49,13 @@ class Params(C.Structure):
                 ("seed", C.c_uint64), ("scan_id", C.c_uint32), ("flags", C.c_uint32)]
 
 
+class PostParams(C.Structure):
+    _fields_ = [("blur_sigma_bins", C.c_float), ("uniform_amp", C.c_float), ("perlin_amp", C.c_float),
+                ("perlin_cell_az", C.c_float), ("perlin_cell_bins", C.c_float), ("db_floor", C.c_float),
+                ("max_value", C.c_uint32), ("reserved0", C.c_uint32), ("seed", C.c_uint64),
+                ("scan_id", C.c_uint32), ("reserved1", C.c_uint32)]
+
+
 class Material(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("n", C.c_float), ("reflectance", C.c_float),
                 ("A", C.c_float), ("B", C.c_float), ("C", C.c_float)]
@@ -83,6 +90,10 @@ def _load():
                                      P(C.c_uint32), C.c_uint32, P(C.c_uint8), P(C.c_double),
                                      P(C.c_int32), P(C.c_uint8), P(C.c_double),
                                      P(C.c_uint64), C.c_int]
+            lib.orc_perlin.restype = C.c_double
+            lib.orc_perlin.argtypes = [C.c_uint64, C.c_uint32, C.c_double, C.c_double]
+            lib.orc_post.argtypes = [P(C.c_float), C.c_uint32, C.c_uint32, P(PostParams),
+                                     P(C.c_float), P(C.c_uint8), P(C.c_double)]
             _lib = lib
     return _lib
 
@@ -230,3 +241,32 @@ def scan_scene(scene, **kw):
     params = kw.pop("params", scene.params)
     return scan(scene.vertices, scene.indices, scene.tri_material, pose, params,
                 scene.materials, **kw)
+
+
+# ---------------------------------------------------------------- epilogue
+POST_DEFAULTS = dict(blur_sigma_bins=0.0, uniform_amp=0.0, perlin_amp=0.0, perlin_cell_az=16.0,
+                     perlin_cell_bins=64.0, db_floor=-100.0, max_value=255, seed=0x5EED, scan_id=0)
+
+
+def make_post(p: dict) -> PostParams:
+    q = dict(POST_DEFAULTS, **p)
+    return PostParams(q["blur_sigma_bins"], q["uniform_amp"], q["perlin_amp"], q["perlin_cell_az"],
+                      q["perlin_cell_bins"], q["db_floor"], q["max_value"], 0, q["seed"], q["scan_id"], 0)
+
+
+def perlin(seed: int, scan_id: int, x: float, y: float) -> float:
+    return float(_load().orc_perlin(seed, scan_id, x, y))
+
+
+def postprocess(image, post: dict):
+    """Blur, noise, dB and 8-bit map of a float32 [n_az][n_bins] image.
+    Returns (dB float32, pixels uint8, pixel value before rounding float64)."""
+    img = np.ascontiguousarray(image, dtype=np.float32)
+    n_az, n_bins = img.shape
+    db = np.empty_like(img)
+    u8 = np.empty(img.shape, np.uint8)
+    pre = np.empty(img.shape, np.float64)
+    pp = make_post(post)
+    _load().orc_post(_ptr(img, C.c_float), n_az, n_bins, C.byref(pp), _ptr(db, C.c_float),
+                     _ptr(u8, C.c_uint8), _ptr(pre, C.c_double))
+    return db, u8, pre

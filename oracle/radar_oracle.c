@@ -712,3 +712,102 @@ int orc_scan(const float* vertices, uint32_t nv, const uint32_t* indices, uint32
   free(en_local);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Polar-image epilogue (Sec. III-B "Polar Image", Sec. III-C "Noise"),     */
+/* in float64, each step as the readings define it:                         */
+/*   1. measurement noise: each azimuth column blurred along range with a   */
+/*      Gaussian of std. dev. sigma bins, weights exp(-m^2 / (2 sigma^2))   */
+/*      for |m| <= ceil(3 sigma), normalised to sum 1, zero beyond the ends;*/
+/*   2. system noise: uniform_amp * u per pixel, u from Philox with counter */
+/*      (k, bin, 1, 0); ambient noise: perlin_amp * (0.5 + 0.5 n), n the   */
+/*      2-D gradient noise of Perlin ("Improving noise", SIGGRAPH 2002) at  */
+/*      (k / cell_az, bin / cell_bins), lattice gradients picked by the top */
+/*      three bits of Philox (i, j, 2, 0) from the eight vectors (+-1, +-1),*/
+/*      (+-1, 0), (0, +-1), fade t^3 (t (6t - 15) + 10);                    */
+/*   3. L = 10 log10(E) (E_0 = 1: the image is already a fraction of each   */
+/*      azimuth's emitted energy), -inf for E <= 0;                         */
+/*   4. pixel = floor(max_value * (L - floor) / (0 - floor) + 0.5), clamped */
+/*      to [0, max_value] (L above 0 dB is cut to max_value).               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  float blur_sigma_bins, uniform_amp, perlin_amp, perlin_cell_az, perlin_cell_bins, db_floor;
+  uint32_t max_value, reserved0;
+  uint64_t seed;
+  uint32_t scan_id, reserved1;
+} orc_post_params;
+
+static double orc_u53(uint64_t x) { return (double)(x >> 11) * (1.0 / 9007199254740992.0); }
+
+static double fade5(double t) { return t * t * t * (t * (t * 6.0 - 15.0) + 10.0); }
+
+static double grad_dot(uint64_t key[2], int64_t i, int64_t j, double dx, double dy) {
+  static const double gx[8] = {1.0, -1.0, 1.0, -1.0, 1.0, -1.0, 0.0, 0.0};
+  static const double gy[8] = {1.0, 1.0, -1.0, -1.0, 0.0, 0.0, 1.0, -1.0};
+  uint64_t ctr[4] = {(uint64_t)i, (uint64_t)j, 2u, 0u}, x[4];
+  orc_philox4x64_10(key, ctr, x);
+  unsigned g = (unsigned)(x[0] >> 61);
+  return gx[g] * dx + gy[g] * dy;
+}
+
+double orc_perlin(uint64_t seed, uint32_t scan_id, double x, double y) {
+  uint64_t key[2] = {seed, scan_id};
+  double fx0 = floor(x), fy0 = floor(y);
+  int64_t i = (int64_t)fx0, j = (int64_t)fy0;
+  double fx = x - fx0, fy = y - fy0;
+  double n00 = grad_dot(key, i, j, fx, fy);
+  double n10 = grad_dot(key, i + 1, j, fx - 1.0, fy);
+  double n01 = grad_dot(key, i, j + 1, fx, fy - 1.0);
+  double n11 = grad_dot(key, i + 1, j + 1, fx - 1.0, fy - 1.0);
+  double u = fade5(fx), v = fade5(fy);
+  double nx0 = n00 + u * (n10 - n00);
+  double nx1 = n01 + u * (n11 - n01);
+  return nx0 + v * (nx1 - nx0);
+}
+
+/* db_out (float, may be NULL), u8_out (may be NULL), pre_out (may be NULL):
+ * max_value * (L - floor) / (0 - floor) before rounding, for the tests. */
+void orc_post(const float* image, uint32_t n_az, uint32_t n_bins, const orc_post_params* p,
+              float* db_out, uint8_t* u8_out, double* pre_out) {
+  double sigma = p->blur_sigma_bins;
+  int R = sigma > 0.0 ? (int)ceil(3.0 * sigma) : 0;
+  double* w = (double*)malloc(sizeof(double) * (size_t)(2 * R + 1));
+  double wsum = 0.0;
+  for (int m = -R; m <= R; ++m) {
+    w[m + R] = R ? exp(-((double)m * (double)m) / (2.0 * sigma * sigma)) : 1.0;
+    wsum += w[m + R];
+  }
+  for (int m = -R; m <= R; ++m) w[m + R] = w[m + R] / wsum;
+  uint64_t key[2] = {p->seed, p->scan_id};
+  double floor_db = p->db_floor;
+  for (uint32_t k = 0; k < n_az; ++k) {
+    for (uint32_t b = 0; b < n_bins; ++b) {
+      double e = 0.0;
+      for (int m = -R; m <= R; ++m) {
+        long j = (long)b + m;
+        if (j < 0 || j >= (long)n_bins) continue;
+        e += w[m + R] * (double)image[(size_t)k * n_bins + (size_t)j];
+      }
+      if (p->uniform_amp > 0.0f) {
+        uint64_t ctr[4] = {k, b, 1u, 0u}, x[4];
+        orc_philox4x64_10(key, ctr, x);
+        e += (double)p->uniform_amp * orc_u53(x[0]);
+      }
+      if (p->perlin_amp > 0.0f) {
+        double n = orc_perlin(p->seed, p->scan_id, (double)k / (double)p->perlin_cell_az,
+                              (double)b / (double)p->perlin_cell_bins);
+        e += (double)p->perlin_amp * (0.5 + 0.5 * n);
+      }
+      double L = e > 0.0 ? 10.0 * log10(e) : -INFINITY;
+      double pre = e > 0.0 ? (double)p->max_value * (L - floor_db) / (0.0 - floor_db) : -INFINITY;
+      double q = floor(pre + 0.5);
+      if (!(q > 0.0)) q = 0.0;
+      if (q > (double)p->max_value) q = (double)p->max_value;
+      size_t o = (size_t)k * n_bins + b;
+      if (db_out) db_out[o] = (float)L;
+      if (u8_out) u8_out[o] = (uint8_t)q;
+      if (pre_out) pre_out[o] = pre;
+    }
+  }
+  free(w);
+}
