@@ -719,8 +719,8 @@ int orc_scan(const float* vertices, uint32_t nv, const uint32_t* indices, uint32
 /*   1. measurement noise: each azimuth column blurred along range with a   */
 /*      Gaussian of std. dev. sigma bins, weights exp(-m^2 / (2 sigma^2))   */
 /*      for |m| <= ceil(3 sigma), normalised to sum 1, zero beyond the ends;*/
-/*   2. system noise: uniform_amp * u per pixel, u from Philox with counter */
-/*      (k, bin, 1, 0); ambient noise: perlin_amp * (0.5 + 0.5 n), n the   */
+/*   2. system noise: uniform_amp * u per pixel, u from word (bin mod 4) of */
+/*      Philox with counter (k, bin div 4, 1, 0); ambient noise: perlin_amp * (0.5 + 0.5 n), n the   */
 /*      2-D gradient noise of Perlin ("Improving noise", SIGGRAPH 2002) at  */
 /*      (k / cell_az, bin / cell_bins), lattice gradients picked by the top */
 /*      three bits of Philox (i, j, 2, 0) from the eight vectors (+-1, +-1),*/
@@ -789,9 +789,9 @@ void orc_post(const float* image, uint32_t n_az, uint32_t n_bins, const orc_post
         e += w[m + R] * (double)image[(size_t)k * n_bins + (size_t)j];
       }
       if (p->uniform_amp > 0.0f) {
-        uint64_t ctr[4] = {k, b, 1u, 0u}, x[4];
+        uint64_t ctr[4] = {k, b / 4u, 1u, 0u}, x[4];
         orc_philox4x64_10(key, ctr, x);
-        e += (double)p->uniform_amp * orc_u53(x[0]);
+        e += (double)p->uniform_amp * orc_u53(x[b % 4u]);
       }
       if (p->perlin_amp > 0.0f) {
         double n = orc_perlin(p->seed, p->scan_id, (double)k / (double)p->perlin_cell_az,
