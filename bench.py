@@ -195,6 +195,101 @@ def bench_trajectory(args):
     print(json.dumps(out), flush=True)
 
 
+POST_BYTES_PER_PIXEL = 9   # float32 energy read, float32 dB and 8-bit pixel written
+POST_FULL = dict(blur_sigma_bins=2.0, uniform_amp=1e-7, perlin_amp=1e-6, perlin_cell_az=16.0,
+                 perlin_cell_bins=64.0, seed=12345, scan_id=0)
+
+
+def bench_post(args):
+    """The polar-image epilogue (range blur, uniform and gradient noise, dB,
+    8-bit) over 64 images of the urban block's shape (400 x 3776) in one
+    launch, inputs resident; then the same epilogue fused into a full urban
+    block scan against the plain scan."""
+    import numpy as np
+    import torch
+    import paper_2310_03505_amd as R
+    import workloads as W
+    n_img, n_az, n_bins = 64, 400, 3776
+    log(f"bench: epilogue, {n_img} images of {n_az} x {n_bins}")
+    base = torch.from_numpy(W.polar_images(31, 8, n_az, n_bins)).cuda()
+    imgs = base.repeat(n_img // 8, 1, 1).contiguous()
+    db = torch.empty_like(imgs)
+    u8 = torch.empty(imgs.shape, dtype=torch.uint8, device="cuda")
+    ctx = R.Context(0)
+    c = ctx.handle
+    for _ in range(max(args.warmup, 1)):
+        R.rr_postprocess(c, imgs, POST_FULL, db=db, u8=u8)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        R.rr_postprocess(c, imgs, POST_FULL, db=db, u8=u8)
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
+    px = n_img * n_az * n_bins
+    gbs = px * POST_BYTES_PER_PIXEL / (launch_ms / 1e3) / 1e9
+    roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None, kernel="k_post",
+                launch_ms=round(launch_ms, 4), bytes_per_launch=px * POST_BYTES_PER_PIXEL)
+    # the epilogue without noise (blur, dB, 8-bit only) for the split
+    for _ in range(2):
+        R.rr_postprocess(c, imgs, dict(blur_sigma_bins=2.0), db=db, u8=u8)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        R.rr_postprocess(c, imgs, dict(blur_sigma_bins=2.0), db=db, u8=u8)
+    e1.record()
+    torch.cuda.synchronize()
+    roof["launch_ms_without_noise"] = round(e0.elapsed_time(e1) / args.steps, 4)
+    # fused into the scan: urban block scan + epilogue against the plain scan
+    scene = W.urban_block()
+    p = scene.params
+    sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+    img = torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+    d1, u1 = torch.empty_like(img), torch.empty(img.shape, dtype=torch.uint8, device="cuda")
+    fused = {}
+    for mode in ("plain", "fused", "plain", "fused"):
+        e0.record()
+        for _ in range(5):
+            if mode == "plain":
+                R.rr_radar_scan(c, sc.handle, scene.pose, p, scene.materials, image=img)
+            else:
+                R.rr_radar_scan_post(c, sc.handle, scene.pose, p, scene.materials, POST_FULL, image=img,
+                                     db=d1, u8=u1)
+        e1.record()
+        torch.cuda.synchronize()
+        fused[mode] = e0.elapsed_time(e1) / 5
+    sc.release()
+    out = {
+        "metric": "Mpixel/s", "value": round(px / (launch_ms / 1e3) / 1e6, 1), "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(launch_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "polar_epilogue_64x400x3776", "n_images": n_img, "n_azimuth": n_az,
+                   "n_bins": n_bins, "post": POST_FULL, "wall_s": round(wall, 3),
+                   "urban_scan_ms": round(fused["plain"], 4),
+                   "urban_scan_fused_epilogue_ms": round(fused["fused"], 4)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        host = imgs[:2].cpu().numpy()
+        t0 = time.perf_counter()
+        for i in range(2):
+            oracle.postprocess(host[i], dict(POST_FULL, scan_id=i))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=round(2 * n_az * n_bins / dt / 1e6, 3), unit="Mpixel/s", cores=1,
+                                   kind="oracle", sample=f"2 of the {n_img} images ({dt:.1f} s, one thread)",
+                                   cpu_model=cpu_model())
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args):
     """Replays the seeded Poisson stream (200 requests/s from 32 robots,
     random poses, 100..800 azimuths, 256..4096 rays/beam, 2..5 bounces) into
@@ -259,7 +354,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory", "serve"])
+    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory", "serve", "post"])
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed request stream (serve workload)")
     ap.add_argument("--serve-rate-scale", type=float, default=1.0,
@@ -294,6 +389,8 @@ def main():
         return bench_trajectory(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "post":
+        return bench_post(args)
     scene, wname = workload(args.workload)
     p = scene.params
     log(f"bench: {wname}, {scene.n_tris} tris, {p['n_azimuth']}x{p['rays_per_beam']}, "

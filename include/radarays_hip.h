@@ -250,6 +250,62 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* scene, const rr_s
 /* Workspace bytes rr_radar_scan_batch needs for these scans. */
 rr_status rr_batch_workspace_query(const rr_scan_desc* scans, uint32_t n_scans, size_t* bytes);
 
+/* ---------------------------------------------------------------- epilogue */
+/* Polar-image epilogue (Sec. III-B "Polar Image", Sec. III-C "Noise"), in
+ * float64, in this order for each pixel (azimuth k, bin b) of an image E:
+ *  1. measurement noise: E is blurred along range with a Gaussian of
+ *     blur_sigma_bins bins: taps |m| <= ceil(3 sigma), weights
+ *     exp(-m^2 / (2 sigma^2)) normalised to sum 1, zero beyond the column
+ *     ends (sigma = 0: no blur);
+ *  2. system noise: + uniform_amp * u, u in [0, 1) from word (b mod 4) of
+ *     Philox4x64-10 with key (seed, scan_id) and counter (k, b div 4, 1, 0),
+ *     u = (word >> 11) * 2^-53;
+ *  3. ambient noise: + perlin_amp * (1 + n) / 2, n in [-1, 1] the 2-D
+ *     gradient noise of Perlin (SIGGRAPH 2002, quintic fade) at
+ *     (k / perlin_cell_az, b / perlin_cell_bins); the gradient of lattice
+ *     point (i, j) is entry (top 3 bits of word 0 of Philox with counter
+ *     (i, j, 2, 0)) of (1,1), (-1,1), (1,-1), (-1,-1), (1,0), (-1,0), (0,1),
+ *     (0,-1);
+ *  4. L = 10 log10(E) dB (the image is a fraction of the emitted energy, so
+ *     E_0 = 1), -inf for E <= 0;
+ *  5. pixel = floor(max_value * (L - db_floor) / (0 - db_floor) + 1/2),
+ *     clamped to [0, max_value]: 0 dB and above give max_value. */
+typedef struct {
+  float blur_sigma_bins;  /* 0..16 */
+  float uniform_amp;      /* >= 0 (0 = no system noise) */
+  float perlin_amp;       /* >= 0 (0 = no ambient noise) */
+  float perlin_cell_az;   /* lattice spacing in azimuth columns, >= 1 when perlin_amp > 0 */
+  float perlin_cell_bins; /* lattice spacing in range bins, >= 1 when perlin_amp > 0 */
+  float db_floor;         /* dB that maps to pixel 0, finite and < 0 (e.g. -100) */
+  uint32_t max_value;     /* pixel value at 0 dB, 1..255 */
+  uint32_t reserved0;     /* must be 0 */
+  uint64_t seed;
+  uint32_t scan_id;       /* image i of a call uses scan_id + i */
+  uint32_t reserved1;     /* must be 0 */
+} rr_post_params;
+
+/* Epilogue of n_images float images of n_azimuth x n_bins, contiguous,
+ * row-major [image][azimuth][bin], in device memory (images_dev).  Outputs
+ * (device memory, same layout, either may be NULL but not both): db_dev
+ * float32 dB (step 4), u8_dev 8-bit pixels (step 5).  The outputs must not
+ * overlap the input.  n_images, n_azimuth, n_bins in 0..65535 (0 = nothing
+ * to do).  Stream-ordered on `stream` (NULL = the default stream); no
+ * allocation.  EINVAL for out-of-range parameters or NULL pointers. */
+rr_status rr_postprocess(rr_context* ctx, const float* images_dev, uint32_t n_images, uint32_t n_azimuth,
+                         uint32_t n_bins, const rr_post_params* post, float* db_dev, uint8_t* u8_dev,
+                         void* stream);
+
+/* rr_radar_scan with the epilogue fused into the scan's last launch: the
+ * fixed-point accumulator is converted to the float image (written to
+ * image_dev unless NULL) and steps 1-5 run on it in the same launch.  The
+ * outputs equal rr_radar_scan followed by rr_postprocess of its image with
+ * the same post parameters, bit for bit.  At least one of image_dev, db_dev
+ * and u8_dev must be non-NULL. */
+rr_status rr_radar_scan_post(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
+                             const rr_sensor_params* params, const rr_material* materials,
+                             uint32_t n_materials, const rr_post_params* post, float* image_dev,
+                             float* db_dev, uint8_t* u8_dev, rr_scan_stats* stats, void* stream);
+
 /* ---------------------------------------------------------------- serving */
 /* A server owns a context and a resident scene and turns a stream of scan
  * requests into batches (continuous batching).  Requests wait in arrival

@@ -99,6 +99,13 @@ class rr_scan_desc(C.Structure):
     _fields_ = [("pose", rr_pose), ("params", rr_sensor_params), ("image_dev", C.c_void_p)]
 
 
+class rr_post_params(C.Structure):
+    _fields_ = [("blur_sigma_bins", C.c_float), ("uniform_amp", C.c_float), ("perlin_amp", C.c_float),
+                ("perlin_cell_az", C.c_float), ("perlin_cell_bins", C.c_float), ("db_floor", C.c_float),
+                ("max_value", C.c_uint32), ("reserved0", C.c_uint32), ("seed", C.c_uint64),
+                ("scan_id", C.c_uint32), ("reserved1", C.c_uint32)]
+
+
 EXPORTS = (
     "rr_status_str", "rr_create", "rr_destroy", "rr_last_error", "rr_scene_upload",
     "rr_bvh_build", "rr_bvh_get_info", "rr_bvh_selfcheck", "rr_scene_release",
@@ -107,6 +114,7 @@ EXPORTS = (
     "rr_set_tuning", "rr_get_tuning", "rr_server_create", "rr_server_submit", "rr_server_wait",
     "rr_server_poll", "rr_server_get_stats", "rr_server_reset_stats", "rr_server_destroy",
     "rr_autotune", "rr_graph_create", "rr_graph_launch", "rr_graph_destroy", "rr_measure_gather",
+    "rr_postprocess", "rr_radar_scan_post",
 )
 
 _lib = None
@@ -162,6 +170,9 @@ def load_library():
         "rr_graph_launch": (st, [vp, P(rr_scan_desc), vp]),
         "rr_graph_destroy": (st, [vp]),
         "rr_measure_gather": (st, [vp, C.c_uint64, C.c_uint32, P(C.c_double)]),
+        "rr_postprocess": (st, [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, P(rr_post_params), vp, vp, vp]),
+        "rr_radar_scan_post": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material), C.c_uint32,
+                                    P(rr_post_params), vp, vp, vp, P(rr_scan_stats), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -485,6 +496,64 @@ def rr_server_reset_stats(srv):
 
 def rr_server_destroy(srv):
     _check(load_library().rr_server_destroy(srv))
+
+
+# ------------------------------------------------------------------ epilogue
+POST_DEFAULTS = dict(blur_sigma_bins=0.0, uniform_amp=0.0, perlin_amp=0.0, perlin_cell_az=16.0,
+                     perlin_cell_bins=64.0, db_floor=-100.0, max_value=255, seed=0x5EED, scan_id=0)
+
+
+def make_post(post: dict) -> rr_post_params:
+    unknown = set(post) - set(POST_DEFAULTS)
+    if unknown:
+        raise ValueError(f"unknown epilogue parameters: {sorted(unknown)}")
+    q = dict(POST_DEFAULTS, **post)
+    return rr_post_params(q["blur_sigma_bins"], q["uniform_amp"], q["perlin_amp"], q["perlin_cell_az"],
+                          q["perlin_cell_bins"], q["db_floor"], q["max_value"], 0, q["seed"], q["scan_id"], 0)
+
+
+def rr_postprocess(ctx, images, post: dict, db=None, u8=None, want_db=True, want_u8=True, stream=None):
+    """Epilogue of float32 CUDA images [n_az, n_bins] or [n_images, n_az,
+    n_bins] (contiguous).  Returns (db, u8); outputs are allocated when None
+    and wanted."""
+    import torch
+    if images.dtype != torch.float32 or not images.is_contiguous() or images.dim() not in (2, 3):
+        raise ValueError("images must be a contiguous float32 tensor of 2 or 3 dimensions")
+    shape = images.shape
+    n_img, n_az, n_bins = (1, *shape) if images.dim() == 2 else shape
+    if db is None and want_db:
+        db = torch.empty(shape, dtype=torch.float32, device=images.device)
+    if u8 is None and want_u8:
+        u8 = torch.empty(shape, dtype=torch.uint8, device=images.device)
+    for t, dt in ((db, torch.float32), (u8, torch.uint8)):
+        if t is not None and (t.dtype != dt or t.shape != shape or not t.is_contiguous()):
+            raise ValueError("outputs must be contiguous, of the images' shape, float32 (dB) and uint8")
+    pp = make_post(post)
+    _check(load_library().rr_postprocess(ctx, _ptr(images), n_img, n_az, n_bins, C.byref(pp), _ptr(db),
+                                         _ptr(u8), _stream_handle(stream)), ctx)
+    return db, u8
+
+
+def rr_radar_scan_post(ctx, scene, pose: dict, params: dict, materials, post: dict, image=None, db=None,
+                       u8=None, want_image=True, want_db=True, want_u8=True, stats=False, stream=None):
+    """rr_radar_scan with the epilogue fused into its last launch.  Returns
+    (image, db, u8, stats-or-None)."""
+    import torch
+    shape = (params["n_azimuth"], params["n_bins"])
+    if image is None and want_image:
+        image = torch.empty(shape, dtype=torch.float32, device="cuda")
+    if db is None and want_db:
+        db = torch.empty(shape, dtype=torch.float32, device="cuda")
+    if u8 is None and want_u8:
+        u8 = torch.empty(shape, dtype=torch.uint8, device="cuda")
+    st = rr_scan_stats() if stats else None
+    mats = make_materials(materials)
+    pr, ps, pp = make_pose(pose), make_params(params), make_post(post)
+    _check(load_library().rr_radar_scan_post(ctx, scene, C.byref(pr), C.byref(ps), mats, len(materials),
+                                             C.byref(pp), _ptr(image), _ptr(db), _ptr(u8),
+                                             C.byref(st) if st is not None else None,
+                                             _stream_handle(stream)), ctx)
+    return image, db, u8, (_stats_dict(st) if st is not None else None)
 
 
 # ------------------------------------------------------------------ convenience

@@ -247,7 +247,8 @@ rr_status check_scene(rr_context* ctx, const rr_scene* sc) {
 rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
-              float beam_width_for_mats, uint32_t* counters_host, bool upload) {
+              float beam_width_for_mats, uint32_t* counters_host, bool upload, const PostArgs* post) {
+  if (post && scans.size() != 1) return fail(ctx, RR_EINVAL, "the fused epilogue takes one scan");
   Layout L;
   make_layout(ps, (uint32_t)scans.size(), L, ctx->fused != 0);
   if (ws_bytes < L.total)
@@ -362,7 +363,19 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     if ((rs = timed_launch(2, d, [&] { return launch_shade(a, sgrid, st); }))) return rs;
     level_bound = std::min<uint64_t>(level_bound * 2, L.cap);
   }
-  HIP_TRY(ctx, launch_finalize(d_scans, (uint32_t)scans.size(), d_acc, max_cells, st));
+  if (post) {
+    // finalize and epilogue in one launch
+    PostArgs pa = *post;
+    pa.img = nullptr;
+    pa.acc = d_acc;
+    pa.image = scans[0].image;
+    pa.n_az = scans[0].n_az;
+    pa.n_bins = scans[0].n_bins;
+    pa.n_images = 1;
+    HIP_TRY(ctx, launch_post(pa, st));
+  } else {
+    HIP_TRY(ctx, launch_finalize(d_scans, (uint32_t)scans.size(), d_acc, max_cells, st));
+  }
   if (accum_out)
     HIP_TRY(ctx, hipMemcpyAsync(accum_out, d_acc, 8 * L.acc_cells, hipMemcpyDeviceToDevice, st));
   if (counters_host)
@@ -379,6 +392,42 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     stats->overflow = ctx->h_ctr[kCtrOverflow];
     if (stats->overflow) return fail(ctx, RR_EOVERFLOW, "ray queue overflow");
   }
+  return RR_OK;
+}
+
+rr_status make_post_args(rr_context* ctx, const rr_post_params* p, PostArgs& a) {
+  if (!p) return fail(ctx, RR_EINVAL, "post parameters are NULL");
+  a = PostArgs{};
+  const double sigma = p->blur_sigma_bins;
+  if (!(sigma >= 0.0 && sigma <= 16.0)) return fail(ctx, RR_EINVAL, "blur_sigma_bins must be in [0, 16]");
+  if (!(p->uniform_amp >= 0.0f && std::isfinite(p->uniform_amp)))
+    return fail(ctx, RR_EINVAL, "uniform_amp must be finite and >= 0");
+  if (!(p->perlin_amp >= 0.0f && std::isfinite(p->perlin_amp)))
+    return fail(ctx, RR_EINVAL, "perlin_amp must be finite and >= 0");
+  if (p->perlin_amp > 0.0f && !(p->perlin_cell_az >= 1.0f && p->perlin_cell_bins >= 1.0f &&
+                                std::isfinite(p->perlin_cell_az) && std::isfinite(p->perlin_cell_bins)))
+    return fail(ctx, RR_EINVAL, "perlin cell sizes must be finite and >= 1");
+  if (!(p->db_floor < 0.0f && std::isfinite(p->db_floor)))
+    return fail(ctx, RR_EINVAL, "db_floor must be finite and < 0");
+  if (p->max_value < 1 || p->max_value > 255) return fail(ctx, RR_EINVAL, "max_value must be in 1..255");
+  if (p->reserved0 || p->reserved1) return fail(ctx, RR_EINVAL, "reserved fields must be 0");
+  // blur taps m = -R..R, weights exp(-m^2 / (2 sigma^2)) normalised to sum 1
+  const int R = sigma > 0.0 ? (int)std::ceil(3.0 * sigma) : 0;
+  double wsum = 0.0;
+  for (int m = -R; m <= R; ++m) {
+    a.w[m + R] = R ? std::exp(-((double)m * (double)m) / (2.0 * sigma * sigma)) : 1.0;
+    wsum += a.w[m + R];
+  }
+  for (int m = -R; m <= R; ++m) a.w[m + R] = a.w[m + R] / wsum;
+  a.R = R;
+  a.uamp = p->uniform_amp;
+  a.pamp = p->perlin_amp;
+  a.cell_az = p->perlin_amp > 0.0f ? p->perlin_cell_az : 1.0;
+  a.cell_bins = p->perlin_amp > 0.0f ? p->perlin_cell_bins : 1.0;
+  a.db_floor = p->db_floor;
+  a.max_value = (double)p->max_value;
+  a.seed = p->seed;
+  a.scan_id = p->scan_id;
   return RR_OK;
 }
 
@@ -630,13 +679,23 @@ rr_status rr_batch_workspace_query(const rr_scan_desc* scans, uint32_t n, size_t
 static rr_status scan_common(rr_context* ctx, const rr_scene* sc, const rr_pose* pose,
                              const rr_sensor_params* params, const rr_material* mats, uint32_t n_mats,
                              const uint8_t* mask, float* image, int32_t* records, uint64_t* accum,
-                             void* ws, size_t ws_bytes, rr_scan_stats* stats, void* stream) {
+                             void* ws, size_t ws_bytes, rr_scan_stats* stats, void* stream,
+                             const rr_post_params* post = nullptr, float* db = nullptr,
+                             uint8_t* u8 = nullptr) {
   if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
   rr_status s;
   if ((s = check_scene(ctx, sc)) || (s = check_params(ctx, params)) || (s = check_pose(ctx, pose)) ||
       (s = check_materials(ctx, mats, n_mats, sc)))
     return s;
-  if (!image) return fail(ctx, RR_EINVAL, "image_dev is NULL");
+  PostArgs pa{};
+  if (post) {
+    if ((s = make_post_args(ctx, post, pa))) return s;
+    if (!image && !db && !u8) return fail(ctx, RR_EINVAL, "image_dev, db_dev and u8_dev are all NULL");
+    pa.db = db;
+    pa.u8 = u8;
+  } else if (!image) {
+    return fail(ctx, RR_EINVAL, "image_dev is NULL");
+  }
   DeviceGuard g(ctx->device);
   Layout L;
   make_layout(&params, 1, L, ctx->fused != 0);
@@ -651,7 +710,8 @@ static rr_status scan_common(rr_context* ctx, const rr_scene* sc, const rr_pose*
   scans[0].records = records;
   scans[0].mask = mask;
   return run(ctx, sc, scans, &params, mats, n_mats, static_cast<char*>(ws), ws_bytes, stats,
-             static_cast<hipStream_t>(stream), accum, params->beam_width_rad);
+             static_cast<hipStream_t>(stream), accum, params->beam_width_rad, nullptr, true,
+             post ? &pa : nullptr);
 }
 
 rr_status rr_radar_scan(rr_context* ctx, const rr_scene* sc, const rr_pose* pose,
@@ -676,6 +736,44 @@ rr_status rr_radar_scan_records(rr_context* ctx, const rr_scene* sc, const rr_po
                                 uint64_t* accum_dev, rr_scan_stats* stats, void* stream) {
   return scan_common(ctx, sc, pose, params, mats, n_mats, mask, image_dev, records_dev, accum_dev, nullptr,
                      0, stats, stream);
+}
+
+rr_status rr_radar_scan_post(rr_context* ctx, const rr_scene* sc, const rr_pose* pose,
+                             const rr_sensor_params* params, const rr_material* mats, uint32_t n_mats,
+                             const rr_post_params* post, float* image_dev, float* db_dev, uint8_t* u8_dev,
+                             rr_scan_stats* stats, void* stream) {
+  if (!post) return fail(ctx, RR_EINVAL, "post parameters are NULL");
+  return scan_common(ctx, sc, pose, params, mats, n_mats, nullptr, image_dev, nullptr, nullptr, nullptr, 0,
+                     stats, stream, post, db_dev, u8_dev);
+}
+
+rr_status rr_postprocess(rr_context* ctx, const float* images, uint32_t n_images, uint32_t n_az,
+                         uint32_t n_bins, const rr_post_params* post, float* db, uint8_t* u8, void* stream) {
+  PostArgs a;
+  rr_status s;
+  if ((s = make_post_args(ctx, post, a))) return s;
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  if (n_images > 65535 || n_az > 65535 || n_bins > 65535)
+    return fail(ctx, RR_EINVAL, "n_images, n_azimuth and n_bins must be <= 65535");
+  if (n_images == 0 || n_az == 0 || n_bins == 0) return RR_OK;
+  if (!images) return fail(ctx, RR_EINVAL, "images_dev is NULL");
+  if (!db && !u8) return fail(ctx, RR_EINVAL, "db_dev and u8_dev are both NULL");
+  const size_t n = (size_t)n_images * n_az * n_bins;
+  auto overlaps = [&](const void* p, size_t bytes) {
+    uintptr_t a0 = reinterpret_cast<uintptr_t>(images), a1 = a0 + 4 * n;
+    uintptr_t b0 = reinterpret_cast<uintptr_t>(p), b1 = b0 + bytes;
+    return p && a0 < b1 && b0 < a1;
+  };
+  if (overlaps(db, 4 * n) || overlaps(u8, n)) return fail(ctx, RR_EINVAL, "an output overlaps the input");
+  a.img = images;
+  a.db = db;
+  a.u8 = u8;
+  a.n_az = n_az;
+  a.n_bins = n_bins;
+  a.n_images = n_images;
+  DeviceGuard g(ctx->device);
+  HIP_TRY(ctx, launch_post(a, static_cast<hipStream_t>(stream)));
+  return RR_OK;
 }
 
 rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan_desc* descs, uint32_t n,

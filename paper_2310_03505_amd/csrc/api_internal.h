@@ -9,6 +9,7 @@
 #include "../../include/radarays_hip.h"
 #include "bvh.h"
 #include "kernels.h"
+#include "post.h"
 #include "rr_internal.h"
 
 struct rr_context {
@@ -100,7 +101,10 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
               float beam_width_for_mats, uint32_t* counters_host = nullptr,
-              bool upload_tables = true);
+              bool upload_tables = true, const PostArgs* post = nullptr);
+// Validates an epilogue parameter block and fills the launch arguments
+// (blur weights included); the caller sets the image pointers and sizes.
+rr_status make_post_args(rr_context* ctx, const rr_post_params* p, PostArgs& a);
 // Uploads the scan table (prim_base / acc_base filled) and the material
 // table of a set of scans into workspace `ws`.
 rr_status upload_tables(rr_context* ctx, std::vector<DevScan>& scans, const rr_sensor_params* const* ps,

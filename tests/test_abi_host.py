@@ -154,3 +154,21 @@ def test_deep_median_fallback_bounds_depth(R):
         assert sc.info()["max_stack"] <= (96 if width == 4 else 44)
         assert sc.selfcheck(3000, 11) == 0
         sc.release()
+
+
+def test_postprocess_validation_without_device(R):
+    """The epilogue checks its parameter block before it needs a context."""
+    lib = R.load_library()
+    good = R.make_post({})
+    st = lib.rr_postprocess(None, None, 1, 1, 1, R.C.byref(good), None, None, None)
+    assert st == R.RR_EINVAL and b"context" in lib.rr_last_error(None)
+    for bad, word in ((dict(blur_sigma_bins=16.01), b"blur"), (dict(blur_sigma_bins=float("nan")), b"blur"),
+                      (dict(uniform_amp=-1e-9), b"uniform"), (dict(perlin_amp=float("inf")), b"perlin"),
+                      (dict(perlin_amp=1.0, perlin_cell_az=0.5), b"cell"), (dict(db_floor=0.0), b"db_floor"),
+                      (dict(db_floor=float("-inf")), b"db_floor"), (dict(max_value=0), b"max_value"),
+                      (dict(max_value=256), b"max_value")):
+        pp = R.make_post(bad)
+        st = lib.rr_postprocess(None, None, 1, 1, 1, R.C.byref(pp), None, None, None)
+        assert st == R.RR_EINVAL and word in lib.rr_last_error(None), bad
+    with pytest.raises(ValueError):
+        R.make_post(dict(sigma=1.0))

@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for the radar-scan path.
 
 This package only builds inputs: triangle meshes, material tables, sensor
-poses, sensor parameters and request streams.  It holds none of the radar
+poses, sensor parameters, request streams and polar images for the
+epilogue.  It holds none of the radar
 method's arithmetic (no ray sampling, no intersection, no shading), so both
 the CPU oracle and the HIP library can be fed from it without sharing any
 code of the method.
@@ -16,3 +17,4 @@ from .scenes import (  # noqa: F401
     transform_scene,
 )
 from .poses import spline_poses, request_stream, street_points  # noqa: F401
+from .images import polar_images  # noqa: F401
