@@ -426,6 +426,12 @@ rr_status make_post_args(rr_context* ctx, const rr_post_params* p, PostArgs& a) 
   a.cell_bins = p->perlin_amp > 0.0f ? p->perlin_cell_bins : 1.0;
   a.db_floor = p->db_floor;
   a.max_value = (double)p->max_value;
+  a.px_scale = a.max_value / (0.0 - a.db_floor);
+  // lattice rows one 1024-bin tile can touch: floor(1023 / cell) + 2, plus
+  // two for the rounding of the quotients
+  a.gcap = p->perlin_amp > 0.0f
+               ? (uint32_t)std::min(std::floor(1023.0 / a.cell_bins) + 4.0, (double)kPostTile + 4.0)
+               : 0u;
   a.seed = p->seed;
   a.scan_id = p->scan_id;
   return RR_OK;

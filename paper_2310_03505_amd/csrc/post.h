@@ -28,9 +28,17 @@ struct PostArgs {
   double uamp, pamp;            // uniform and gradient-noise amplitudes
   double cell_az, cell_bins;    // gradient-noise lattice spacing (>= 1)
   double db_floor, max_value;
+  double px_scale;              // max_value / (0 - db_floor)
   uint64_t seed;
   uint32_t scan_id;             // image i uses scan_id + i
+  uint32_t gcap;                // gradient-table rows per lattice column (0: no gradient noise)
 };
+
+// Dynamic LDS of one k_post workgroup: the gradient table (2 x gcap float2)
+// and, with a blur, the float64 tile of 1024 bins plus the halo.
+inline size_t post_lds_bytes(const PostArgs& a) {
+  return (size_t)2 * a.gcap * 8 + (a.R > 0 ? (size_t)(kPostTile + 2 * a.R) * 8 : 0);
+}
 
 hipError_t launch_post(const PostArgs& a, hipStream_t st);
 
