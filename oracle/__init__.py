@@ -25,7 +25,8 @@ CFLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-pthread", "-ffp-contract=of
           "-fno-fast-math", "-fexcess-precision=standard"]
 
 E_SLOTS = ("emitted", "returned_in", "returned_out", "escaped", "absorbed",
-           "terminated", "cut")
+           "terminated", "cut", "blocked")
+FLAG_AIR_PATH = 16
 
 
 def build(force: bool = True) -> str:
@@ -193,7 +194,9 @@ def scan(vertices, indices, tri_material, pose: dict, params: dict, materials,
     Returns a dict with ``image`` float64 [n_cols, n_bins], ``columns``,
     ``segments`` (uint64 per column) and, if asked, ``records`` int32
     [n_cols * N_s, 2^B - 1], ``exempt`` bool [n_cols * N_s] and ``energy``
-    float64 [n_cols, 7] (slots in E_SLOTS).
+    float64 [n_cols, 8] (slots in E_SLOTS).  With the air-path flag,
+    ``air_records`` int32 [n_cols * N_s, 2^B - 1] holds each hit's air-path
+    outcome (-2 none, 0 returned, 1 blocked, 2 beyond the last bin).
     """
     lib = _load()
     V = np.ascontiguousarray(vertices, dtype=np.float32)
@@ -210,9 +213,10 @@ def scan(vertices, indices, tri_material, pose: dict, params: dict, materials,
     nb, ns = params["n_bins"], params["rays_per_beam"]
     nheap = (1 << params["max_bounces"]) - 1
     img = np.zeros((ncol, nb), dtype=np.float64)
-    rec = np.empty((ncol * ns, nheap), dtype=np.int32) if records else None
+    air = bool(params.get("flags", 0) & FLAG_AIR_PATH)
+    rec = np.empty((ncol * ns, 2 * nheap if air else nheap), dtype=np.int32) if records else None
     ex = np.zeros(ncol * ns, dtype=np.uint8) if exempt else None
-    en = np.zeros((ncol, 7), dtype=np.float64) if energy else None
+    en = np.zeros((ncol, len(E_SLOTS)), dtype=np.float64) if energy else None
     segs = np.zeros(ncol, dtype=np.uint64)
     mask = None
     if primary_mask is not None:
@@ -227,7 +231,9 @@ def scan(vertices, indices, tri_material, pose: dict, params: dict, materials,
         raise ValueError("oracle scan rejected its arguments")
     out = dict(image=img, columns=cols, segments=segs)
     if records:
-        out["records"] = rec
+        out["records"] = rec[:, :nheap]
+        if air:
+            out["air_records"] = rec[:, nheap:]
     if exempt:
         out["exempt"] = ex.astype(bool)
     if energy:

@@ -34,6 +34,7 @@
 #define ORC_FIXED_PATTERN 2u
 #define ORC_MIRROR_PAIRS 4u
 #define ORC_RETURN_ALL 8u
+#define ORC_AIR_PATH 16u
 
 #define ORC_DIELECTRIC 0u
 #define ORC_METAL 1u
@@ -57,7 +58,7 @@ typedef struct {
 } orc_material;
 
 /* energy bookkeeping slots, per column */
-enum { E_EMITTED = 0, E_RET_IN, E_RET_OUT, E_ESCAPED, E_ABSORBED, E_TERMINATED, E_CUT, E_NSLOTS };
+enum { E_EMITTED = 0, E_RET_IN, E_RET_OUT, E_ESCAPED, E_ABSORBED, E_TERMINATED, E_CUT, E_BLOCKED, E_NSLOTS };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw,        */
@@ -424,7 +425,8 @@ typedef struct {
   const orc_pose* pose;
   prim_consts pc;
   float r_max;
-  uint32_t n_heap; /* 2^B - 1 */
+  uint32_t n_heap;     /* 2^B - 1 */
+  uint32_t rec_stride; /* records per primary: n_heap, twice that with air-path returns */
   /* columns */
   const uint32_t* columns;
   uint32_t n_columns;
@@ -448,12 +450,37 @@ typedef struct {
 } oray;
 
 typedef struct {
-  double* img;     /* column row */
-  double* energy;  /* column energy slots */
-  int32_t* rec;    /* primary's records or NULL */
+  double* img;      /* column row */
+  double* energy;   /* column energy slots */
+  int32_t* rec;     /* primary's records or NULL */
+  int32_t* air_rec; /* primary's air-path outcomes or NULL */
+  double axis[3];   /* the column's beam axis in the world frame */
   int exempt;
   uint64_t segments;
 } prim_state;
+
+/* Visibility of the sensor along an air path: does any triangle other than
+ * `excl` meet the segment from o along unit s at 0 < t <= dist (the range
+ * rule of the closest-hit test)?  Flags the primary when a blocking
+ * triangle is hit within 1e-5 of an edge or of the segment's end. */
+static int air_blocked(const scan_ctx* c, const float o[3], const float s[3], float dist, int32_t excl,
+                       prim_state* ps) {
+  int blocked = 0;
+  for (uint32_t j = 0; j < c->nt; ++j) {
+    if ((int32_t)j == excl || c->degenerate[j]) continue;
+    float t;
+    if (!mt_hit(o, s, c->v0 + 3 * j, c->e1 + 3 * j, c->e2 + 3 * j, dist, &t)) continue;
+    blocked = 1;
+    double u, v;
+    bary64(o, s, c->v0 + 3 * j, c->e1 + 3 * j, c->e2 + 3 * j, &u, &v);
+    double w = 1.0 - u - v;
+    double mn = u < v ? u : v;
+    mn = mn < w ? mn : w;
+    if (!(mn >= 1e-5)) ps->exempt = 1;
+    if (fabs((double)t - (double)dist) < 1e-5 * (double)dist) ps->exempt = 1;
+  }
+  return blocked;
+}
 
 static void trace_ray(const scan_ctx* c, const oray* r, prim_state* ps) {
   const orc_params* prm = c->prm;
@@ -513,7 +540,88 @@ static void trace_ray(const scan_ctx* c, const oray* r, prim_state* ps) {
   }
   ps->energy[E_ABSORBED] += r->E * (1.0 - it.R - it.T);
 
-  double e_refl = r->E * it.R - e_ret;
+  /* return along the air path (Sec. III-A, multi-path reflection): from a
+   * hit at depth >= 1 of a ray travelling in air straight back to the
+   * sensor.  Its window angle is the one between the mean reflection and
+   * the direction to the sensor; it leaves from the offset origin of the
+   * reflected child, needs the sensor on the incoming side of the surface
+   * and an unblocked segment, takes the receive gain of its arrival
+   * direction and lands at half the round-trip path.  Its energy comes out
+   * of the reflected share, at most what the retrace return left. */
+  double e_air = 0.0;
+  if ((prm->flags & ORC_AIR_PATH) && r->depth >= 1 && r->n_cur == 1.0f) {
+    float ph[3], po[3], v[3];
+    for (int a = 0; a < 3; ++a) {
+      float td = best_t * r->d[a];
+      ph[a] = r->o[a] + td;
+    }
+    orc_offset(ph, it.nf, po);
+    for (int a = 0; a < 3; ++a) v[a] = c->pose->position[a] - po[a];
+    float dist = sqrtf(dotf(v, v));
+    float s[3] = {0.0f, 0.0f, 0.0f};
+    if (dist > 0.0f) {
+      s[0] = v[0] / dist;
+      s[1] = v[1] / dist;
+      s[2] = v[2] / dist;
+    }
+    if (dist > 0.0f && dotf(s, it.nf) > 0.0f) {
+      double w_air;
+      if (prm->flags & ORC_RETURN_ALL) {
+        w_air = 1.0;
+      } else {
+        double ca = (double)it.refl_dir[0] * s[0] + (double)it.refl_dir[1] * s[1] + (double)it.refl_dir[2] * s[2];
+        if (ca < 0.0) ca = 0.0;
+        if (ca > 1.0) ca = 1.0;
+        const double* wn = c->win[c->mat[j]];
+        w_air = wn[1] + wn[2] * ca + wn[3] * pow(ca, (double)m->C);
+        w_air = w_air < 0.0 ? 0.0 : (w_air > 1.0 ? 1.0 : w_air);
+      }
+      e_air = r->E * it.R * w_air;
+      double room = r->E * it.R - e_ret;
+      if (e_air > room) e_air = room;
+      double g_air = 1.0;
+      if (prm->flags & ORC_BEAM_GAIN) {
+        /* angle between the beam axis and the arrival direction (sensor
+         * towards the origin of the return), in float64 from the exact
+         * difference of the two float32 points: atan2(|a x w|, a . w) */
+        const double* ax = ps->axis;
+        double w0 = (double)po[0] - (double)c->pose->position[0];
+        double w1 = (double)po[1] - (double)c->pose->position[1];
+        double w2 = (double)po[2] - (double)c->pose->position[2];
+        double x0 = ax[1] * w2 - ax[2] * w1, x1 = ax[2] * w0 - ax[0] * w2, x2 = ax[0] * w1 - ax[1] * w0;
+        double alpha = atan2(sqrt(x0 * x0 + x1 * x1 + x2 * x2), ax[0] * w0 + ax[1] * w1 + ax[2] * w2);
+        if (c->pc.sigma_r > 0.0) {
+          double z = alpha / c->pc.sigma_r;
+          g_air = exp(-0.5 * z * z);
+        } else {
+          g_air = alpha == 0.0 ? 1.0 : 0.0;
+        }
+      }
+      float range_air = (range + dist) * 0.5f;
+      float qa = range_air / prm->bin_size_m;
+      {
+        double qd = (double)range_air / (double)prm->bin_size_m;
+        if (fabs(qd - floor(qd + 0.5)) < 1e-5) ps->exempt = 1;
+      }
+      int32_t outcome;
+      if (qa < (float)prm->n_bins) {
+        if (air_blocked(c, po, s, dist, (int32_t)j, ps)) {
+          ps->energy[E_BLOCKED] += e_air;
+          outcome = 1;
+        } else {
+          ps->img[(uint32_t)qa] += e_air * g_air;
+          ps->energy[E_RET_IN] += e_air;
+          outcome = 0;
+        }
+      } else {
+        ps->energy[E_RET_OUT] += e_air;
+        outcome = 2;
+      }
+      if (ps->air_rec) ps->air_rec[r->heap - 1] = outcome;
+    }
+  }
+
+  double e_refl = r->E * it.R - e_ret - e_air;
   double e_refr = it.has_refract ? r->E * it.T : 0.0;
   if (r->depth + 1 >= prm->max_bounces) {
     ps->energy[E_TERMINATED] += e_refl + e_refr;
@@ -579,7 +687,14 @@ static void do_column(scan_ctx* c, uint32_t ci) {
     prim_state ps;
     ps.img = img;
     ps.energy = en;
-    ps.rec = c->records ? c->records + lp * c->n_heap : NULL;
+    ps.rec = c->records ? c->records + lp * c->rec_stride : NULL;
+    ps.air_rec = (c->records && (prm->flags & ORC_AIR_PATH)) ? ps.rec + c->n_heap : NULL;
+    {
+      /* beam axis of column k: the azimuth direction rotated by the pose */
+      double phi = 2.0 * M_PI * (double)k / (double)prm->n_azimuth;
+      double a0 = cos(phi), a1 = sin(phi);
+      for (int a = 0; a < 3; ++a) ps.axis[a] = c->pc.R[a][0] * a0 + c->pc.R[a][1] * a1;
+    }
     ps.exempt = 0;
     ps.segments = 0;
     oray r;
@@ -614,10 +729,14 @@ static void* worker(void* arg) {
  *   records  optional [n_columns * N_s][2^B - 1] int32 in heap order
  *            (heap id 1 = primary, 2h = reflected child, 2h+1 = refracted
  *            child); entry = original triangle id, -1 for a miss, -2 for a
- *            segment that was never spawned
+ *            segment that was never spawned.  With air-path returns each
+ *            primary has 2 (2^B - 1) entries; the second half holds the
+ *            air-path outcome of each segment's hit: -2 none attempted,
+ *            0 returned, 1 blocked, 2 beyond the last bin (not tested)
  *   exempt   optional [n_columns * N_s] uint8 near-degenerate flags
- *   energy   optional [n_columns][7] float64: emitted, returned in range,
- *            returned out of range, escaped, absorbed, depth-terminated, cut
+ *   energy   optional [n_columns][8] float64: emitted, returned in range,
+ *            returned out of range, escaped, absorbed, depth-terminated, cut,
+ *            blocked air-path returns
  *   segments optional [n_columns] uint64 closest-hit queries per column
  * Returns 0, or -1 on an invalid argument.
  */
@@ -678,6 +797,7 @@ int orc_scan(const float* vertices, uint32_t nv, const uint32_t* indices, uint32
   make_prim_consts(prm, pose, &c.pc);
   c.r_max = (float)prm->n_bins * prm->bin_size_m;
   c.n_heap = (1u << prm->max_bounces) - 1u;
+  c.rec_stride = (prm->flags & ORC_AIR_PATH) ? 2u * c.n_heap : c.n_heap;
   c.columns = columns;
   c.n_columns = n_columns;
   c.primary_mask = primary_mask;
@@ -688,7 +808,7 @@ int orc_scan(const float* vertices, uint32_t nv, const uint32_t* indices, uint32
   memset(image, 0, sizeof(double) * (size_t)n_columns * prm->n_bins);
   memset(c.energy, 0, sizeof(double) * (size_t)n_columns * E_NSLOTS);
   if (records) {
-    size_t nrec = (size_t)n_columns * prm->rays_per_beam * c.n_heap;
+    size_t nrec = (size_t)n_columns * prm->rays_per_beam * c.rec_stride;
     for (size_t q = 0; q < nrec; ++q) records[q] = -2;
   }
   if (exempt) memset(exempt, 0, (size_t)n_columns * prm->rays_per_beam);
