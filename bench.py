@@ -369,6 +369,8 @@ def main():
                     help="compress the stream's arrival times by this factor (load x scale)")
     ap.add_argument("--serve-one-per-launch", action="store_true",
                     help="serve one request per launch on one stream (baseline)")
+    ap.add_argument("--air", action="store_true",
+                    help="also return along the air path (one visibility ray per hit at depth >= 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -400,6 +402,9 @@ def main():
     if args.workload == "post":
         return bench_post(args)
     scene, wname = workload(args.workload)
+    if args.air:
+        scene.params = dict(scene.params, flags=scene.params["flags"] | R.RR_AIR_PATH)
+        wname += "_air"
     p = scene.params
     log(f"bench: {wname}, {scene.n_tris} tris, {p['n_azimuth']}x{p['rays_per_beam']}, "
         f"B={p['max_bounces']}, bins={p['n_bins']}")
@@ -481,6 +486,7 @@ def main():
                 trace_level_ms=[round(x / args.steps, 4)
                                 for x in split["trace_level_ms"][:p["max_bounces"]]],
                 shade_ms_per_scan=round(split["shade_ms"] / args.steps, 4),
+                visibility_ms_per_scan=round(split["shadow_ms"] / args.steps, 4),
                 raygen_ms_per_scan=round(split["raygen_ms"] / args.steps, 4))
 
     out = {
@@ -492,6 +498,7 @@ def main():
                    "rays_per_beam": p["rays_per_beam"], "max_bounces": p["max_bounces"],
                    "n_bins": p["n_bins"], "segments_per_scan": segs,
                    "rays_per_depth": st["rays_per_depth"][:p["max_bounces"]],
+                   "air_rays_per_scan": st["air_rays"],
                    "scans_per_s": round(scans_per_s, 2), "bvh_nodes": info["n_nodes"],
                    "bvh_depth": info["max_depth"], "wall_s": round(wall, 3),
                    "tuning": R.rr_get_tuning(c)},

@@ -47,6 +47,17 @@ typedef int32_t rr_status;
 #define RR_FIXED_PATTERN 2u  /* every azimuth uses the same cone offsets */
 #define RR_MIRROR_PAIRS 4u   /* odd rays mirror the azimuth offset of ray i-1 */
 #define RR_RETURN_ALL 8u     /* return all reflected energy (w = 1; lidar-like) */
+/* Also return along the air path (Sec. III-A, multi-path reflection): from
+ * every hit at depth >= 1 of a ray in air, straight back to the sensor when
+ * the sensor is on the incoming side of the surface and no triangle blocks
+ * the segment (one visibility ray each).  Window angle between the mean
+ * reflection and the direction to the sensor; energy taken from the
+ * reflected share (at most what the retrace return left); range = half the
+ * round trip; receive gain (with RR_BEAM_GAIN) from the angle between the
+ * beam axis and the arrival direction.  Needs a four-wide BVH and the
+ * level-by-level launches (EINVAL otherwise); the workspace grows by 48
+ * bytes per ray of the largest level. */
+#define RR_AIR_PATH 16u
 
 /* material kinds */
 #define RR_DIELECTRIC 0u /* Fresnel reflection + Snell refraction, lossless */
@@ -140,7 +151,7 @@ typedef struct {
   uint64_t segments;
   uint64_t rays_per_depth[RR_MAX_BOUNCES];
   uint32_t overflow; /* nonzero: a ray queue overflowed (a library bug) */
-  uint32_t reserved;
+  uint32_t air_rays; /* air-path visibility rays traced (RR_AIR_PATH) */
 } rr_scan_stats;
 
 /* One scan of a batch. */
@@ -224,7 +235,11 @@ rr_status rr_radar_scan_ws(rr_context* ctx, const rr_scene* scene, const rr_pose
  *  records_dev  int32 [n_azimuth * rays_per_beam][2^B - 1], heap order per
  *               primary (slot h-1 for heap id h; 1 = primary, 2h = reflected
  *               child, 2h+1 = refracted child): original triangle id of the
- *               segment's hit, -1 for a miss, -2 for a segment never spawned
+ *               segment's hit, -1 for a miss, -2 for a segment never spawned.
+ *               With RR_AIR_PATH each primary has 2 (2^B - 1) entries; the
+ *               second half holds the air-path outcome of each segment's
+ *               hit: -2 none, 0 returned, 1 blocked, 2 beyond the last bin.
+ *               EINVAL if n_azimuth * rays_per_beam * entries >= 2^32.
  *  accum_dev    uint64 [n_azimuth * n_bins]: the fixed-point accumulator
  *               (energy * 2^56) the image is converted from
  * primary_mask_dev (optional) uint8 [n_azimuth * rays_per_beam]: primaries
@@ -420,6 +435,7 @@ typedef struct {
   uint64_t tail_wave_iters[RR_MAX_BOUNCES];
   uint64_t tail_active_lanes[RR_MAX_BOUNCES];
   uint64_t max_ray_iters[RR_MAX_BOUNCES]; /* most loop iterations of one ray */
+  double shadow_ms;            /* air-path visibility launches (RR_PROFILE_TIME) */
 } rr_profile;
 
 /* Measurement hooks for benchmarks (not needed for scans).  Enabling with

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libradarays_hip.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ESTATE, RR_EOVERFLOW = 0, -1, -2, -3, -4, -5
-RR_BEAM_GAIN, RR_FIXED_PATTERN, RR_MIRROR_PAIRS, RR_RETURN_ALL = 1, 2, 4, 8
+RR_BEAM_GAIN, RR_FIXED_PATTERN, RR_MIRROR_PAIRS, RR_RETURN_ALL, RR_AIR_PATH = 1, 2, 4, 8, 16
 RR_DIELECTRIC, RR_METAL, RR_LAMBERTIAN = 0, 1, 2
 RR_MAX_BOUNCES = 8
 
@@ -57,7 +57,7 @@ class rr_bvh_info(C.Structure):
 
 class rr_scan_stats(C.Structure):
     _fields_ = [("segments", C.c_uint64), ("rays_per_depth", C.c_uint64 * RR_MAX_BOUNCES),
-                ("overflow", C.c_uint32), ("reserved", C.c_uint32)]
+                ("overflow", C.c_uint32), ("air_rays", C.c_uint32)]
 
 
 class rr_profile(C.Structure):
@@ -69,7 +69,7 @@ class rr_profile(C.Structure):
                 ("active_lanes", C.c_uint64 * RR_MAX_BOUNCES),
                 ("tail_wave_iters", C.c_uint64 * RR_MAX_BOUNCES),
                 ("tail_active_lanes", C.c_uint64 * RR_MAX_BOUNCES),
-                ("max_ray_iters", C.c_uint64 * RR_MAX_BOUNCES)]
+                ("max_ray_iters", C.c_uint64 * RR_MAX_BOUNCES), ("shadow_ms", C.c_double)]
 
 
 RR_PROFILE_TIME, RR_PROFILE_COUNT, RR_PROFILE_TRACE_TIME = 1, 2, 4
@@ -276,7 +276,7 @@ def rr_workspace_query(params: dict) -> int:
 
 def _stats_dict(st: rr_scan_stats) -> dict:
     return dict(segments=int(st.segments), rays_per_depth=[int(x) for x in st.rays_per_depth],
-                overflow=int(st.overflow))
+                overflow=int(st.overflow), air_rays=int(st.air_rays))
 
 
 def rr_radar_scan(ctx, scene, pose: dict, params: dict, materials, image=None, stats=False,
@@ -313,12 +313,17 @@ def rr_radar_scan_records(ctx, scene, pose: dict, params: dict, materials, prima
                           records=True, accum=True, stats=True, stream=None):
     """Debug/parity scan.  Returns dict(image, records, accum, stats) with
     CUDA tensors (records int32 [N_p, 2^B-1], accum int64 view of the uint64
-    fixed-point accumulator)."""
+    fixed-point accumulator); with RR_AIR_PATH also air_records int32
+    [N_p, 2^B-1], the air-path outcome of each hit (-2 none, 0 returned,
+    1 blocked, 2 beyond the last bin)."""
     import torch
     n_az, n_s, nb, B = (params["n_azimuth"], params["rays_per_beam"], params["n_bins"],
                         params["max_bounces"])
+    nheap = (1 << B) - 1
+    air = bool(params.get("flags", 0) & RR_AIR_PATH)
     image = torch.empty((n_az, nb), dtype=torch.float32, device="cuda")
-    rec = torch.empty((n_az * n_s, (1 << B) - 1), dtype=torch.int32, device="cuda") if records else None
+    rec = torch.empty((n_az * n_s, 2 * nheap if air else nheap), dtype=torch.int32,
+                      device="cuda") if records else None
     acc = torch.empty((n_az, nb), dtype=torch.int64, device="cuda") if accum else None
     st = rr_scan_stats() if stats else None
     mats = make_materials(materials)
@@ -327,8 +332,10 @@ def rr_radar_scan_records(ctx, scene, pose: dict, params: dict, materials, prima
         ctx, scene, C.byref(pr), C.byref(ps), mats, len(materials), _ptr(primary_mask),
         _ptr(image), _ptr(rec), _ptr(acc), C.byref(st) if st is not None else None,
         _stream_handle(stream)), ctx)
-    return dict(image=image, records=rec, accum=acc,
-                stats=_stats_dict(st) if st is not None else None)
+    out = dict(image=image, records=rec, accum=acc, stats=_stats_dict(st) if st is not None else None)
+    if rec is not None and air:
+        out["records"], out["air_records"] = rec[:, :nheap], rec[:, nheap:]
+    return out
 
 
 def make_scan_descs(scans, images):
@@ -452,7 +459,7 @@ def rr_profile_read(ctx) -> dict:
                 wave_iters=list(p.wave_iters), active_lanes=list(p.active_lanes),
                 tail_wave_iters=list(p.tail_wave_iters),
                 tail_active_lanes=list(p.tail_active_lanes),
-                max_ray_iters=list(p.max_ray_iters))
+                max_ray_iters=list(p.max_ray_iters), shadow_ms=float(p.shadow_ms))
 
 
 def rr_server_create(ctx, scene, materials, n_slots: int = 0, max_batch_scans: int = 0,

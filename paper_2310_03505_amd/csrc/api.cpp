@@ -63,7 +63,7 @@ rr_status check_params(rr_context* ctx, const rr_sensor_params* p) {
     return fail(ctx, RR_EINVAL, "energy_cutoff must be finite and >= 0");
   if (!std::isfinite((float)p->n_bins * p->bin_size_m))
     return fail(ctx, RR_EINVAL, "n_bins * bin_size_m overflows");
-  if (p->flags & ~15u) return fail(ctx, RR_EINVAL, "unknown flag bits 0x%x", p->flags);
+  if (p->flags & ~31u) return fail(ctx, RR_EINVAL, "unknown flag bits 0x%x", p->flags);
   return RR_OK;
 }
 
@@ -197,6 +197,7 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool 
     L.n_first += np;
     L.acc_cells += (uint64_t)p.n_azimuth * p.n_bins;
     L.max_b = std::max(L.max_b, p.max_bounces);
+    L.air = L.air || (p.flags & RR_AIR_PATH) != 0;
     for (uint32_t d = 1; d < p.max_bounces; ++d) level[d] += np << d;
   }
   L.cap = L.n_first;
@@ -217,6 +218,15 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool 
   o += align256(sizeof(int32_t) * (size_t)kSpill * kSpillLanes);
   L.off_wq = o;
   if (fused) o += align256(kWqBytes);
+  if (L.air) {
+    // at most one visibility ray per hit of a level
+    L.off_shq[0] = o;
+    o += align256(16 * cap);
+    L.off_shq[1] = o;
+    o += align256(16 * cap);
+    L.off_shq[2] = o;
+    o += align256(16 * cap);
+  }
   for (int q = 0; q < 2; ++q) {
     L.off_q[q][0] = o;
     o += align256(16 * cap);
@@ -269,12 +279,24 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   }
   bool masked = false;
   for (const DevScan& q : scans) masked = masked || q.mask != nullptr;
+  if (L.air) {
+    if (sc->bvh.width == 8) return fail(ctx, RR_EINVAL, "air-path returns need a four-wide BVH");
+    if (ctx->fused) return fail(ctx, RR_EINVAL, "air-path returns need the level-by-level launches");
+  }
+  for (size_t i = 0; i < scans.size(); ++i) {
+    // record slots (with the air-path outcomes) are 32-bit indices
+    const uint64_t stride = (uint64_t)((1u << scans[i].max_b) - 1u) * ((scans[i].flags & RR_AIR_PATH) ? 2u : 1u);
+    if (scans[i].records && (uint64_t)scans[i].n_prim * stride > 0xffffffffull)
+      return fail(ctx, RR_EINVAL, "records exceed 2^32 entries");
+  }
   // without masks every primary has a fixed queue slot and level 0 is full
   HIP_TRY(ctx, launch_clear(d_acc, (size_t)L.acc_cells, d_ctr, masked ? 0u : (uint32_t)L.n_first, st));
   for (size_t i = 0; i < scans.size(); ++i)
     if (scans[i].records)
       HIP_TRY(ctx, launch_fill_i32(scans[i].records,
-                                   (size_t)scans[i].n_prim * ((1u << scans[i].max_b) - 1u), -2, st));
+                                   (size_t)scans[i].n_prim * ((1u << scans[i].max_b) - 1u) *
+                                       ((scans[i].flags & RR_AIR_PATH) ? 2u : 1u),
+                                   -2, st));
   LevelArgs a{};
   if (sc->bvh.width == 8) {
     if (ctx->fused) return fail(ctx, RR_EINVAL, "the one-launch mode needs a four-wide BVH");
@@ -309,6 +331,13 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   a.wq_pool = kWqPool;
   a.wq_hits = kWqHits;
   a.shade_batch = ctx->shade_batch;
+  a.air = L.air ? 1u : 0u;
+  if (L.air) {
+    a.shq = ShadowView{reinterpret_cast<float4*>(ws + L.off_shq[0]), reinterpret_cast<float4*>(ws + L.off_shq[1]),
+                       reinterpret_cast<uint4*>(ws + L.off_shq[2])};
+    // outcome records exist only for a single scan (the records entry point)
+    a.air_rec = (scans.size() == 1 && (scans[0].flags & RR_AIR_PATH)) ? scans[0].records : nullptr;
+  }
   const uint32_t flat_cap = (uint32_t)ctx->n_cu * 8u;
   auto timed_launch = [&](int kind, uint32_t depth, auto&& fn) -> rr_status {
     const bool timed = kind == 1 ? timed_trace : timed_all;
@@ -361,6 +390,11 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     uint64_t sblocks = (level_bound + kBlock - 1) / kBlock;
     uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), (uint64_t)ctx->n_cu * 12u);
     if ((rs = timed_launch(2, d, [&] { return launch_shade(a, sgrid, st); }))) return rs;
+    if (L.air && d >= 1) {
+      // visibility of the sensor for this level's air-path returns
+      uint32_t vgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
+      if ((rs = timed_launch(3, d, [&] { return launch_shadow(a, vgrid, st); }))) return rs;
+    }
     level_bound = std::min<uint64_t>(level_bound * 2, L.cap);
   }
   if (post) {
@@ -390,6 +424,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
       stats->segments += c;
     }
     stats->overflow = ctx->h_ctr[kCtrOverflow];
+    for (uint32_t d = 1; d < L.max_b; ++d) stats->air_rays += ctx->h_ctr[kCtrShadow + d];
     if (stats->overflow) return fail(ctx, RR_EOVERFLOW, "ray queue overflow");
   }
   return RR_OK;
@@ -838,6 +873,7 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
       total.segments += st.segments;
       for (uint32_t d = 0; d < RR_MAX_BOUNCES; ++d) total.rays_per_depth[d] += st.rays_per_depth[d];
       total.overflow |= st.overflow;
+      total.air_rays += st.air_rays;
     }
   }
   if (stats) *stats = total;
@@ -949,6 +985,8 @@ rr_status rr_profile_read(rr_context* ctx, rr_profile* out) {
       out->trace_launches++;
     } else if (p.kind == 2) {
       out->shade_ms += ms;
+    } else if (p.kind == 3) {
+      out->shadow_ms += ms;
     } else {
       out->raygen_ms += ms;
     }

@@ -24,7 +24,7 @@ struct rr_context {
   struct EvPair {
     hipEvent_t a, b;
     uint32_t depth;
-    int kind;  // 0 raygen, 1 trace, 2 shade
+    int kind;  // 0 raygen, 1 trace, 2 shade, 3 air-path visibility
   };
   std::vector<hipEvent_t> ev_free;
   std::vector<EvPair> ev_used;
@@ -68,6 +68,8 @@ namespace rr {
 // Workspace layout of a set of scans (see api.cpp).
 struct Layout {
   size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0, off_wq = 0;
+  size_t off_shq[3] = {};  // air-path visibility rays (only when a scan has the flag)
+  bool air = false;
   size_t off_q[2][4] = {};
   size_t total = 0;
   uint64_t cap = 0;       // rays per queue

@@ -14,6 +14,12 @@ struct QueueView {
   uint32_t* m;
 };
 
+struct ShadowView {
+  float4* a;
+  float4* b;
+  uint4* c;
+};
+
 // Arguments shared by the per-level kernels.
 struct LevelArgs {
   const Node4* nodes;   // four-wide tree, or
@@ -41,6 +47,9 @@ struct LevelArgs {
   uint32_t shade_batch;  // fused scan: finished rays that start a shade phase (1..64)
   uint32_t* counters;
   unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)
+  uint32_t air;         // some scan returns along the air path: shade emits visibility rays
+  ShadowView shq;       // visibility rays of the level (capacity cap)
+  int32_t* air_rec;     // air-path outcome records of the one scan that has records, or null
 };
 
 // Copies `bytes` (multiple of 4) from host memory into device memory by
@@ -58,6 +67,10 @@ hipError_t launch_gather(const float4* buf, uint32_t n_rows, uint32_t steps, flo
 hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st);
+// Visibility of the sensor for the air-path returns of level a.depth (the
+// closest-hit traversal bounded by each ray's distance to the sensor); the
+// unblocked returns are added to the accumulator.
+hipError_t launch_shadow(const LevelArgs& a, uint32_t grid, hipStream_t st);
 // All bounce levels in one persistent launch (primaries from queue `in`).
 hipError_t launch_scan(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_finalize(const DevScan* scans, uint32_t n_scans, const unsigned long long* acc,

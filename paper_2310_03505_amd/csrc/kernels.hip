@@ -93,7 +93,12 @@ __device__ __forceinline__ void normalize3(float& x, float& y, float& z) {
 // tests, and a box is culled only beyond the current minimum, so batching
 // leaves changes speed, never the result.  A lane finishes its ray once its
 // stack is empty and the ring has passed its last entry.
-template <bool kCount>
+//
+// kShadow: the same traversal for the air-path visibility rays of the level,
+// each bounded by its distance to the sensor (a triangle at 0 < t <= dist
+// blocks it).  A ray stops walking at its first blocker, and an unblocked
+// return is added to the image accumulator.
+template <bool kCount, bool kShadow>
 __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   __shared__ int32_t lds_stack[kStack * kTraceBlock];
   __shared__ uint32_t lds_leaf[kTraceBlock / 64][kLeafRing];     // leaf reference
@@ -104,8 +109,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
-  const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
-  uint32_t* cursor = A.counters + kCtrWork + A.depth;
+  const uint32_t n_in = min(A.counters[(kShadow ? kCtrShadow : kCtrCount) + A.depth], A.cap);
+  uint32_t* cursor = A.counters + (kShadow ? kCtrShadowWork : kCtrWork) + A.depth;
   const Node4* __restrict__ nodes = A.nodes;
   const float4* __restrict__ tris = A.tris;
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -148,13 +153,21 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         const bool mine = !valid && rank < take;
         if (mine) {
           const uint32_t my = pool_next + rank;
-          const float4 a = A.in.a[my];
-          const float4 b = A.in.b[my];
-          const uint32_t m = A.in.m[my];
-          excl = A.in.c[my].w;
-          const uint32_t medium = (m >> 8) & 0xffu;
-          const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
-          best_t = (A.scans[m >> 16].r_max - a.w) / n_cur;
+          float4 a, b;
+          if constexpr (kShadow) {
+            a = A.shq.a[my];
+            b = A.shq.b[my];
+            excl = A.shq.c[my].w;
+            best_t = a.w;
+          } else {
+            a = A.in.a[my];
+            b = A.in.b[my];
+            const uint32_t m = A.in.m[my];
+            excl = A.in.c[my].w;
+            const uint32_t medium = (m >> 8) & 0xffu;
+            const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
+            best_t = (A.scans[m >> 16].r_max - a.w) / n_cur;
+          }
           lds_best[threadIdx.x] = ((unsigned long long)__float_as_uint(best_t) << 32) | 0xffffffffull;
           ox = a.x;
           oy = a.y;
@@ -230,7 +243,12 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
       }
       ring_tail += n;
       __builtin_amdgcn_wave_barrier();
-      if (valid) best_t = __uint_as_float((uint32_t)(lds_best[threadIdx.x] >> 32));
+      if (valid) {
+        const unsigned long long mine = lds_best[threadIdx.x];
+        best_t = __uint_as_float((uint32_t)(mine >> 32));
+        // a visibility ray is done at its first blocker
+        if (kShadow && (uint32_t)mine != 0xffffffffu) trav_done = true;
+      }
     } else {
       uint32_t leaves = 0;  // hit leaf children of this lane's node
       int32_t lref[4] = {0, 0, 0, 0};
@@ -329,7 +347,20 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
     if (valid && trav_done && (int32_t)(ring_tail - last_pos) >= 0) {
       if (kCount) cnt_max_visits = max(cnt_max_visits, visits);
       const unsigned long long b = lds_best[threadIdx.x];
-      A.hits[ridx] = make_uint2((uint32_t)(b >> 32), (uint32_t)b);
+      if constexpr (kShadow) {
+        const bool blocked = (uint32_t)b != 0xffffffffu;
+        if (!blocked) {
+          const uint4 c = A.shq.c[ridx];
+          const unsigned long long qv = ((unsigned long long)c.y << 32) | c.x;
+          if (qv) atomicAdd(A.acc + c.z, qv);
+        }
+        if (A.air_rec) {
+          const uint32_t slot = __float_as_uint(A.shq.b[ridx].w);
+          if (slot != 0xffffffffu) A.air_rec[slot] = blocked ? 1 : 0;
+        }
+      } else {
+        A.hits[ridx] = make_uint2((uint32_t)(b >> 32), (uint32_t)b);
+      }
       valid = false;
     }
   }
@@ -675,13 +706,22 @@ struct Shaded {
   double e_refl = 0.0, e_refr = 0.0;
   uint32_t pid = 0, r_meta = 0, t_meta = 0;
   int32_t hit = -1;
+  // air-path return to test for visibility: origin, direction and distance
+  // to the sensor, its cell, fixed-point energy and outcome record slot
+  bool has_air = false;
+  float aox = 0, aoy = 0, aoz = 0, asx = 0, asy = 0, asz = 0, adist = 0;
+  uint32_t acell = 0, aslot = 0xffffffffu;
+  unsigned long long aqv = 0;
 };
 
 // Interaction of ray (a, b, c, m) with its closest hit (t bits, original
 // triangle id, -1 for a miss): the record, the Snell/Fresnel split (float64
 // energies), the standard-BRDF return over the beam window (Eq. 3-5), the
 // range bin (Sec. III-B) and the two children with offset origins.  The
-// bounce depth is that of the ray's heap id.
+// bounce depth is that of the ray's heap id.  kAirPath: scans with the air-path
+// flag also get the return along the air path (Sec. III-A, multi-path
+// reflection) from hits at depth >= 1 in air, for a visibility ray to decide.
+template <bool kAirPath>
 __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, const float4 b, const uint4 c,
                                           uint32_t m, uint32_t t_bits, int32_t hit, Shaded& o) {
   const uint32_t heap = m & 0xffu;
@@ -691,10 +731,11 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
   o.pid = c.z;
   o.hit = hit;
   const DevScan* S = A.scans + scan;
-  if (S->records) {
-    const size_t nheap = (1u << S->max_b) - 1u;
-    S->records[(size_t)o.pid * nheap + heap - 1] = hit >= 0 ? hit : -1;
-  }
+  // records per primary: the hit of every heap slot, then (air-path scans)
+  // the air-path outcome of every slot
+  const uint32_t nheap = (1u << S->max_b) - 1u;
+  const size_t rbase = (size_t)o.pid * ((S->flags & kFlagAirPath) ? 2u * nheap : nheap);
+  if (S->records) S->records[rbase + heap - 1] = hit >= 0 ? hit : -1;
   if (hit < 0) return;
   const float t = __uint_as_float(t_bits);
   const double E = __hiloint2double((int)c.y, (int)c.x);
@@ -768,20 +809,90 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
   const double e_ret = E * R * w;
   o.range = L + n_cur * t;
   const float q = o.range / S->bin_size;
+  const uint32_t col = o.pid / S->n_s;
   if (q < (float)S->n_bins) {
     const uint32_t bin = (uint32_t)q;
     o.qv = __double2ull_rn(e_ret * (double)o.g * kFixedScale);
     if (o.qv) {
-      const uint32_t k = o.pid / S->n_s;
-      o.cell = (uint32_t)(S->acc_base + (uint64_t)k * S->n_bins + bin);
+      o.cell = (uint32_t)(S->acc_base + (uint64_t)col * S->n_bins + bin);
       o.has_q = true;
+    }
+  }
+  const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
+  double e_air = 0.0;
+  if constexpr (kAirPath) {
+    if ((S->flags & kFlagAirPath) && depth >= 1u && medium == kAir) {
+      // from the reflected child's offset origin straight to the sensor
+      const float aox = offset1(px, nfx), aoy = offset1(py, nfy), aoz = offset1(pz, nfz);
+      const float vx = S->pos[0] - aox, vy = S->pos[1] - aoy, vz = S->pos[2] - aoz;
+      const float dist = sqrtf(dot3(vx, vy, vz, vx, vy, vz));
+      float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+      if (dist > 0.0f) {
+        sx = vx / dist;
+        sy = vy / dist;
+        sz = vz / dist;
+      }
+      if (dist > 0.0f && dot3(sx, sy, sz, nfx, nfy, nfz) > 0.0f) {
+        double w_air;
+        if (S->flags & 8u) {
+          w_air = 1.0;
+        } else {
+          double ca = (double)o.rdx * sx + (double)o.rdy * sy + (double)o.rdz * sz;
+          ca = ca < 0.0 ? 0.0 : (ca > 1.0 ? 1.0 : ca);
+          w_air = M.a + M.beta * ca + M.s * pow(ca, (double)M.C);
+          w_air = w_air < 0.0 ? 0.0 : (w_air > 1.0 ? 1.0 : w_air);
+        }
+        e_air = E * R * w_air;
+        const double room = E * R - e_ret;
+        if (e_air > room) e_air = room;
+        double g_air = 1.0;
+        if (S->flags & 1u) {
+          // angle between the column's beam axis and the arrival direction
+          const double phi = 2.0 * M_PI * (double)col / (double)S->n_az;
+          const double c0 = cos(phi), s0 = sin(phi);
+          const double ax0 = S->R[0] * c0 + S->R[1] * s0;
+          const double ax1 = S->R[3] * c0 + S->R[4] * s0;
+          const double ax2 = S->R[6] * c0 + S->R[7] * s0;
+          const double w0 = (double)aox - (double)S->pos[0];
+          const double w1 = (double)aoy - (double)S->pos[1];
+          const double w2 = (double)aoz - (double)S->pos[2];
+          const double x0 = ax1 * w2 - ax2 * w1, x1 = ax2 * w0 - ax0 * w2, x2 = ax0 * w1 - ax1 * w0;
+          const double alpha = atan2(sqrt(x0 * x0 + x1 * x1 + x2 * x2), ax0 * w0 + ax1 * w1 + ax2 * w2);
+          if (S->sigma_r > 0.0) {
+            const double z = alpha / S->sigma_r;
+            g_air = exp(-0.5 * z * z);
+          } else {
+            g_air = alpha == 0.0 ? 1.0 : 0.0;
+          }
+        }
+        const float range_air = (o.range + dist) * 0.5f;
+        const float qa = range_air / S->bin_size;
+        const size_t aslot = rbase + nheap + heap - 1;
+        if (qa < (float)S->n_bins) {
+          o.aqv = __double2ull_rn(e_air * g_air * kFixedScale);
+          // a visibility ray only where it can add energy or a record is kept
+          if (o.aqv || S->records) {
+            o.has_air = true;
+            o.aox = aox;
+            o.aoy = aoy;
+            o.aoz = aoz;
+            o.asx = sx;
+            o.asy = sy;
+            o.asz = sz;
+            o.adist = dist;
+            o.acell = (uint32_t)(S->acc_base + (uint64_t)col * S->n_bins + (uint32_t)qa);
+            o.aslot = S->records ? (uint32_t)aslot : 0xffffffffu;
+          }
+        } else if (S->records) {
+          S->records[aslot] = 2;
+        }
+      }
     }
   }
   if (depth + 1 < S->max_b) {
     const double ecut = (double)S->e_cut;
-    o.e_refl = E * R - e_ret;
+    o.e_refl = E * R - e_ret - e_air;
     o.e_refr = refract ? E * T : 0.0;
-    const float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
     if (o.e_refl > ecut) {
       o.has_r = true;
       o.rox = offset1(px, nfx);
@@ -802,7 +913,7 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
 // Interaction at the hit of every ray of the level (Sec. III-A): Snell and
 // Fresnel split, the retrace return through the beam window of the standard
 // BRDF, range binning (Sec. III-B) and the two children.
-template <bool kCount>
+template <bool kCount, bool kAirPath>
 __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
   // returns of the block's rays are summed in an LDS hash table keyed by
   // accumulator cell and flushed with one global atomic per cell at the end;
@@ -810,8 +921,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
   // share azimuths and so few cells
   __shared__ uint32_t h_key[kHashSlots];
   __shared__ unsigned long long h_val[kHashSlots];
-  __shared__ uint32_t s_cnt[kBlock / 64][2];
-  __shared__ uint32_t s_base;
+  __shared__ uint32_t s_cnt[kBlock / 64][3];
+  __shared__ uint32_t s_base, s_abase;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wid = threadIdx.x >> 6;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
@@ -834,7 +945,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
       const int32_t hit = (int32_t)h.y;
       const float4 a = hit >= 0 ? A.in.a[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       const float4 b = hit >= 0 ? A.in.b[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      shade_hit(A, a, b, A.in.c[idx], A.in.m[idx], h.x, hit, o);
+      shade_hit<kAirPath>(A, a, b, A.in.c[idx], A.in.m[idx], h.x, hit, o);
       if (kCount && hit >= 0) ++cnt_hits;
     }
     const bool has_q = o.has_q, has_r = o.has_r, has_t = o.has_t;
@@ -859,22 +970,41 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
     // ---- children: one atomic per block iteration for both kinds
     const uint64_t mr = __ballot(has_r);
     const uint64_t mt = __ballot(has_t);
+    const uint64_t ma = kAirPath ? __ballot(o.has_air) : 0ull;
     const uint32_t nr = (uint32_t)__popcll(mr);
     const uint32_t nt = (uint32_t)__popcll(mt);
     if (lane == 0) {
       s_cnt[wid][0] = nr;
       s_cnt[wid][1] = nt;
+      s_cnt[wid][2] = (uint32_t)__popcll(ma);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      uint32_t total = 0;
-      for (uint32_t w = 0; w < kBlock / 64; ++w) total += s_cnt[w][0] + s_cnt[w][1];
+      uint32_t total = 0, total_a = 0;
+      for (uint32_t w = 0; w < kBlock / 64; ++w) {
+        total += s_cnt[w][0] + s_cnt[w][1];
+        total_a += s_cnt[w][2];
+      }
       s_base = total ? atomicAdd(A.counters + kCtrCount + A.depth + 1, total) : 0u;
+      if (kAirPath) s_abase = total_a ? atomicAdd(A.counters + kCtrShadow + A.depth, total_a) : 0u;
     }
     __syncthreads();
-    uint32_t ob = s_base;
-    for (uint32_t w = 0; w < wid; ++w) ob += s_cnt[w][0] + s_cnt[w][1];
+    uint32_t ob = s_base, oa = kAirPath ? s_abase : 0u;
+    for (uint32_t w = 0; w < wid; ++w) {
+      ob += s_cnt[w][0] + s_cnt[w][1];
+      if (kAirPath) oa += s_cnt[w][2];
+    }
     __syncthreads();  // s_cnt / s_base are rewritten by the next iteration
+    if (kAirPath && o.has_air) {
+      const uint32_t slot = oa + (uint32_t)__popcll(ma & lanes_below);
+      if (slot < A.cap) {
+        A.shq.a[slot] = make_float4(o.aox, o.aoy, o.aoz, o.adist);
+        A.shq.b[slot] = make_float4(o.asx, o.asy, o.asz, __uint_as_float(o.aslot));
+        A.shq.c[slot] = make_uint4((uint32_t)o.aqv, (uint32_t)(o.aqv >> 32), o.acell, (uint32_t)o.hit);
+      } else {
+        atomicOr(A.counters + kCtrOverflow, 1u);
+      }
+    }
     if (has_r) {
       const uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
       if (slot < A.cap)
@@ -1048,7 +1178,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
         const float4 a = e[0], b = e[1];
         const uint4 c = reinterpret_cast<const uint4*>(e)[2];
         const uint4 d = reinterpret_cast<const uint4*>(e)[3];
-        shade_hit(A, a, b, c, d.x, d.y, (int32_t)d.z, o);
+        shade_hit<false>(A, a, b, c, d.x, d.y, (int32_t)d.z, o);
         if (o.has_q) atomicAdd(A.acc + o.cell, o.qv);
         child_depth = 32u - (uint32_t)__clz(d.x & 0xffu);  // depth of the ray + 1
         if (kCount && o.hit >= 0) ++cnt_hits;
@@ -1337,9 +1467,14 @@ hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
     return hipGetLastError();
   }
   if (a.prof)
-    hipLaunchKernelGGL(k_trace<true>, g, b, 0, st, a);
+    hipLaunchKernelGGL((k_trace<true, false>), g, b, 0, st, a);
   else
-    hipLaunchKernelGGL(k_trace<false>, g, b, 0, st, a);
+    hipLaunchKernelGGL((k_trace<false, false>), g, b, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_shadow(const LevelArgs& a, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_trace<false, true>), dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1353,10 +1488,18 @@ hipError_t launch_scan(const LevelArgs& a, uint32_t grid, hipStream_t st) {
 }
 
 hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st) {
-  if (a.prof)
-    hipLaunchKernelGGL(k_shade<true>, dim3(grid ? grid : 1), dim3(kBlock), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_shade<false>, dim3(grid ? grid : 1), dim3(kBlock), 0, st, a);
+  const dim3 g(grid ? grid : 1), b(kBlock);
+  if (a.air) {
+    if (a.prof)
+      hipLaunchKernelGGL((k_shade<true, true>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_shade<false, true>), g, b, 0, st, a);
+  } else {
+    if (a.prof)
+      hipLaunchKernelGGL((k_shade<true, false>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_shade<false, false>), g, b, 0, st, a);
+  }
   return hipGetLastError();
 }
 

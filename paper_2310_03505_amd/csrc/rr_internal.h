@@ -95,11 +95,23 @@ constexpr uint32_t kAir = 255u;
 constexpr size_t kRayBytes = 16 + 16 + 16 + 4;
 
 // counters block (uint32): [0..8] rays per depth, [16..24] work cursors,
-// [32] overflow flag
+// [32] overflow flag, [40..48] air-path visibility rays per depth, [48..56]
+// their work cursors
 constexpr int kCtrCount = 0;
 constexpr int kCtrWork = 16;
 constexpr int kCtrOverflow = 32;
+constexpr int kCtrShadow = 40;
+constexpr int kCtrShadowWork = 48;
 constexpr int kCtrWords = 64;
+
+// Air-path visibility ray (one per air-path return to test), three arrays:
+//   a = (o.x, o.y, o.z, dist)   offset origin, distance to the sensor
+//   b = (s.x, s.y, s.z, slot)   unit direction to the sensor; slot = record
+//                               index of the outcome (bits), 0xffffffff none
+//   c = (q lo, q hi, cell, excl) fixed-point energy of the return, its
+//                               accumulator cell, the triangle just hit
+constexpr size_t kShadowBytes = 16 + 16 + 16;
+constexpr uint32_t kFlagAirPath = 16u;
 
 constexpr double kFixedScale = 72057594037927936.0;  // 2^56
 constexpr double kFixedInv = 1.0 / 72057594037927936.0;

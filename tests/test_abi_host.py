@@ -172,3 +172,16 @@ def test_postprocess_validation_without_device(R):
         assert st == R.RR_EINVAL and word in lib.rr_last_error(None), bad
     with pytest.raises(ValueError):
         R.make_post(dict(sigma=1.0))
+
+
+def test_air_path_workspace_and_flags(R):
+    """The air-path flag adds three 16-byte arrays of one entry per ray of the
+    largest level (the visibility rays); unknown flag bits are refused."""
+    p = W.urban_block().params
+    n = R.rr_workspace_query(p)
+    na = R.rr_workspace_query(dict(p, flags=p["flags"] | R.RR_AIR_PATH))
+    cap = 400 * 1024 * 8
+    assert 3 * 16 * cap <= na - n < 3 * 16 * cap + 1024
+    with pytest.raises(R.RadarError) as e:
+        R.rr_workspace_query(dict(p, flags=32))
+    assert e.value.status == R.RR_EINVAL

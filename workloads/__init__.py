@@ -8,7 +8,7 @@ the CPU oracle and the HIP library can be fed from it without sharing any
 code of the method.
 """
 from .scenes import (  # noqa: F401
-    FLAG_BEAM_GAIN, FLAG_FIXED_PATTERN, FLAG_MIRROR_PAIRS, FLAG_RETURN_ALL,
+    FLAG_BEAM_GAIN, FLAG_FIXED_PATTERN, FLAG_MIRROR_PAIRS, FLAG_RETURN_ALL, FLAG_AIR_PATH,
     KIND_DIELECTRIC, KIND_METAL, KIND_LAMBERTIAN,
     Scene, material_dielectric, material_metal, material_lambertian,
     sensor_params, identity_pose, yaw_pose,

@@ -28,6 +28,7 @@ FLAG_BEAM_GAIN = 1
 FLAG_FIXED_PATTERN = 2
 FLAG_MIRROR_PAIRS = 4
 FLAG_RETURN_ALL = 8
+FLAG_AIR_PATH = 16
 
 KIND_DIELECTRIC = 0
 KIND_METAL = 1
