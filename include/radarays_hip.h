@@ -55,8 +55,10 @@ typedef int32_t rr_status;
  * reflected share (at most what the retrace return left); range = half the
  * round trip; receive gain (with RR_BEAM_GAIN) from the angle between the
  * beam axis and the arrival direction.  Needs a four-wide BVH and the
- * level-by-level launches (EINVAL otherwise); the workspace grows by 48
- * bytes per ray of the largest level. */
+ * level-by-level launches (EINVAL otherwise).  The visibility rays of every
+ * level are traced together in one launch after the last level; the
+ * workspace grows by 48 bytes per possible hit at depth >= 1,
+ * N_p (2^B - 2). */
 #define RR_AIR_PATH 16u
 
 /* material kinds */

@@ -219,13 +219,15 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool 
   L.off_wq = o;
   if (fused) o += align256(kWqBytes);
   if (L.air) {
-    // at most one visibility ray per hit of a level
+    // at most one visibility ray per hit at depth >= 1, all levels together
+    for (uint32_t d = 1; d < RR_MAX_BOUNCES; ++d) L.shq_cap += level[d];
+    const size_t sc = (size_t)std::max<uint64_t>(L.shq_cap, 1);
     L.off_shq[0] = o;
-    o += align256(16 * cap);
+    o += align256(16 * sc);
     L.off_shq[1] = o;
-    o += align256(16 * cap);
+    o += align256(16 * sc);
     L.off_shq[2] = o;
-    o += align256(16 * cap);
+    o += align256(16 * sc);
   }
   for (int q = 0; q < 2; ++q) {
     L.off_q[q][0] = o;
@@ -335,6 +337,8 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   if (L.air) {
     a.shq = ShadowView{reinterpret_cast<float4*>(ws + L.off_shq[0]), reinterpret_cast<float4*>(ws + L.off_shq[1]),
                        reinterpret_cast<uint4*>(ws + L.off_shq[2])};
+    if (L.shq_cap >= (1ull << 32)) return fail(ctx, RR_ENOMEM, "visibility rays exceed 2^32");
+    a.shq_cap = (uint32_t)L.shq_cap;
     // outcome records exist only for a single scan (the records entry point)
     a.air_rec = (scans.size() == 1 && (scans[0].flags & RR_AIR_PATH)) ? scans[0].records : nullptr;
   }
@@ -390,12 +394,14 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     uint64_t sblocks = (level_bound + kBlock - 1) / kBlock;
     uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), (uint64_t)ctx->n_cu * 12u);
     if ((rs = timed_launch(2, d, [&] { return launch_shade(a, sgrid, st); }))) return rs;
-    if (L.air && d >= 1) {
-      // visibility of the sensor for this level's air-path returns
-      uint32_t vgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
-      if ((rs = timed_launch(3, d, [&] { return launch_shadow(a, vgrid, st); }))) return rs;
-    }
     level_bound = std::min<uint64_t>(level_bound * 2, L.cap);
+  }
+  if (L.air && L.max_b > 1) {
+    // visibility of the sensor for the air-path returns of every level, in one launch
+    a.depth = 0;
+    uint64_t vblocks = (L.shq_cap + kTraceBlock - 1) / kTraceBlock;
+    uint32_t vgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(vblocks, 1), trace_grid);
+    if ((rs = timed_launch(3, 0, [&] { return launch_shadow(a, vgrid, st); }))) return rs;
   }
   if (post) {
     // finalize and epilogue in one launch
@@ -424,7 +430,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
       stats->segments += c;
     }
     stats->overflow = ctx->h_ctr[kCtrOverflow];
-    for (uint32_t d = 1; d < L.max_b; ++d) stats->air_rays += ctx->h_ctr[kCtrShadow + d];
+    stats->air_rays = ctx->h_ctr[kCtrShadow];
     if (stats->overflow) return fail(ctx, RR_EOVERFLOW, "ray queue overflow");
   }
   return RR_OK;

@@ -70,6 +70,7 @@ struct Layout {
   size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0, off_wq = 0;
   size_t off_shq[3] = {};  // air-path visibility rays (only when a scan has the flag)
   bool air = false;
+  uint64_t shq_cap = 0;    // at most one visibility ray per hit at depth >= 1
   size_t off_q[2][4] = {};
   size_t total = 0;
   uint64_t cap = 0;       // rays per queue

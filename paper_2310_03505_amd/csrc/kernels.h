@@ -48,7 +48,8 @@ struct LevelArgs {
   uint32_t* counters;
   unsigned long long* prof;  // non-null: counting variants (nodes, triangles, rays, hits)
   uint32_t air;         // some scan returns along the air path: shade emits visibility rays
-  ShadowView shq;       // visibility rays of the level (capacity cap)
+  ShadowView shq;       // visibility rays of every level, traced after the last one
+  uint32_t shq_cap;     // their capacity
   int32_t* air_rec;     // air-path outcome records of the one scan that has records, or null
 };
 
@@ -67,9 +68,9 @@ hipError_t launch_gather(const float4* buf, uint32_t n_rows, uint32_t steps, flo
 hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st);
-// Visibility of the sensor for the air-path returns of level a.depth (the
+// Visibility of the sensor for the air-path returns of every level (the
 // closest-hit traversal bounded by each ray's distance to the sensor); the
-// unblocked returns are added to the accumulator.
+// unblocked returns are added to the accumulator.  a.depth must be 0.
 hipError_t launch_shadow(const LevelArgs& a, uint32_t grid, hipStream_t st);
 // All bounce levels in one persistent launch (primaries from queue `in`).
 hipError_t launch_scan(const LevelArgs& a, uint32_t grid, hipStream_t st);

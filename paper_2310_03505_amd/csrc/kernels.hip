@@ -109,8 +109,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
   const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
-  const uint32_t n_in = min(A.counters[(kShadow ? kCtrShadow : kCtrCount) + A.depth], A.cap);
-  uint32_t* cursor = A.counters + (kShadow ? kCtrShadowWork : kCtrWork) + A.depth;
+  const uint32_t n_in = kShadow ? min(A.counters[kCtrShadow], A.shq_cap) : min(A.counters[kCtrCount + A.depth], A.cap);
+  uint32_t* cursor = kShadow ? A.counters + kCtrShadowWork : A.counters + kCtrWork + A.depth;
   const Node4* __restrict__ nodes = A.nodes;
   const float4* __restrict__ tris = A.tris;
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -986,7 +986,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
         total_a += s_cnt[w][2];
       }
       s_base = total ? atomicAdd(A.counters + kCtrCount + A.depth + 1, total) : 0u;
-      if (kAirPath) s_abase = total_a ? atomicAdd(A.counters + kCtrShadow + A.depth, total_a) : 0u;
+      if (kAirPath) s_abase = total_a ? atomicAdd(A.counters + kCtrShadow, total_a) : 0u;
     }
     __syncthreads();
     uint32_t ob = s_base, oa = kAirPath ? s_abase : 0u;
@@ -997,7 +997,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
     __syncthreads();  // s_cnt / s_base are rewritten by the next iteration
     if (kAirPath && o.has_air) {
       const uint32_t slot = oa + (uint32_t)__popcll(ma & lanes_below);
-      if (slot < A.cap) {
+      if (slot < A.shq_cap) {
         A.shq.a[slot] = make_float4(o.aox, o.aoy, o.aoz, o.adist);
         A.shq.b[slot] = make_float4(o.asx, o.asy, o.asz, __uint_as_float(o.aslot));
         A.shq.c[slot] = make_uint4((uint32_t)o.aqv, (uint32_t)(o.aqv >> 32), o.acell, (uint32_t)o.hit);

@@ -95,8 +95,8 @@ constexpr uint32_t kAir = 255u;
 constexpr size_t kRayBytes = 16 + 16 + 16 + 4;
 
 // counters block (uint32): [0..8] rays per depth, [16..24] work cursors,
-// [32] overflow flag, [40..48] air-path visibility rays per depth, [48..56]
-// their work cursors
+// [32] overflow flag, [40] air-path visibility rays of the scan, [48] their
+// work cursor
 constexpr int kCtrCount = 0;
 constexpr int kCtrWork = 16;
 constexpr int kCtrOverflow = 32;

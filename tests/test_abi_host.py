@@ -175,12 +175,13 @@ def test_postprocess_validation_without_device(R):
 
 
 def test_air_path_workspace_and_flags(R):
-    """The air-path flag adds three 16-byte arrays of one entry per ray of the
-    largest level (the visibility rays); unknown flag bits are refused."""
+    """The air-path flag adds three 16-byte arrays with one entry per
+    possible hit at depth >= 1, N_p (2 + 4 + ... + 2^(B-1)) (the visibility
+    rays of every level); unknown flag bits are refused."""
     p = W.urban_block().params
     n = R.rr_workspace_query(p)
     na = R.rr_workspace_query(dict(p, flags=p["flags"] | R.RR_AIR_PATH))
-    cap = 400 * 1024 * 8
+    cap = 400 * 1024 * (2 + 4 + 8)
     assert 3 * 16 * cap <= na - n < 3 * 16 * cap + 1024
     with pytest.raises(R.RadarError) as e:
         R.rr_workspace_query(dict(p, flags=32))
