@@ -298,6 +298,74 @@ def bench_post(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_build(args):
+    """BVH build on the GPU (linear BVH) against the host SAH build, on the
+    urban block (0.2 M triangles) and the large scene (2 M): build time,
+    refit time (HIP events around rr_bvh_refit after moving every vertex),
+    and the urban scan over each tree."""
+    import numpy as np
+    import torch
+    import paper_2310_03505_amd as R
+    import workloads as W
+    ctx = R.Context(0)
+    c = ctx.handle
+    rows = {}
+    for name, scene in (("urban_block_200k", W.urban_block()), ("large_scene_2m", W.large_scene())):
+        log(f"bench: BVH builds on {name}")
+        host = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+        hinfo = host.info()
+        gpu_ms = []
+        for _ in range(max(args.warmup, 1) + 3):
+            g = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material, builder=1)
+            ginfo = g.info()
+            gpu_ms.append(ginfo["build_ms"])
+            g.release()
+        g = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material, builder=1)
+        ginfo = g.info()
+        V = torch.from_numpy(scene.vertices).cuda()
+        V2 = V + torch.tensor([0.01, -0.02, 0.005], device="cuda")
+        for _ in range(2):
+            g.refit(V2)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(10):
+            g.refit(V2 if k % 2 == 0 else V)
+        e1.record()
+        torch.cuda.synchronize()
+        refit_ms = e0.elapsed_time(e1) / 10
+        g.refit(V)
+        row = dict(n_tris=scene.n_tris, host_sah_build_ms=round(hinfo["build_ms"], 2),
+                   gpu_build_ms=round(float(np.median(gpu_ms[max(args.warmup, 1):])), 3),
+                   gpu_refit_ms=round(refit_ms, 4), host_nodes=hinfo["n_nodes"], gpu_nodes=ginfo["n_nodes"],
+                   host_depth=hinfo["max_depth"], gpu_depth=ginfo["max_depth"])
+        if name == "urban_block_200k":
+            p = scene.params
+            img = torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+            for label, sc in (("host_sah", host), ("gpu_lbvh", g)):
+                for _ in range(3):
+                    R.rr_radar_scan(c, sc.handle, scene.pose, p, scene.materials, image=img)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(args.steps):
+                    R.rr_radar_scan(c, sc.handle, scene.pose, p, scene.materials, image=img)
+                e1.record()
+                torch.cuda.synchronize()
+                row[f"scan_ms_{label}"] = round(e0.elapsed_time(e1) / args.steps, 4)
+        rows[name] = row
+        host.release()
+        g.release()
+    big = rows["large_scene_2m"]
+    out = {
+        "metric": "Mtris/s", "value": round(big["n_tris"] / big["gpu_build_ms"] / 1e3, 1), "unit": "Mtris/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": big["gpu_build_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "bvh_build_gpu_lbvh", "scenes": rows},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args):
     """Replays the seeded Poisson stream (200 requests/s from 32 robots,
     random poses, 100..800 azimuths, 256..4096 rays/beam, 2..5 bounces) into
@@ -362,7 +430,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory", "serve", "post"])
+    ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory", "serve", "post", "build"])
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed request stream (serve workload)")
     ap.add_argument("--serve-rate-scale", type=float, default=1.0,
@@ -401,6 +469,8 @@ def main():
         return bench_serve(args)
     if args.workload == "post":
         return bench_post(args)
+    if args.workload == "build":
+        return bench_build(args)
     scene, wname = workload(args.workload)
     if args.air:
         scene.params = dict(scene.params, flags=scene.params["flags"] | R.RR_AIR_PATH)

@@ -132,7 +132,14 @@ typedef struct {
                              leaves of at most max_leaf_size references
                              (always so for width 8); 2: leaves are those of
                              the binary SAH build */
-  uint32_t reserved[2];
+  uint32_t builder;       /* 0: binned SAH on the host (default); 1: linear BVH
+                             built on the GPU (Morton-sorted triangles, binary
+                             radix tree, collapsed to four-wide nodes; leaves are
+                             subtrees of at most max_leaf_size triangles; width 4
+                             and split_pct 0 only) -- about ten times faster to
+                             build, slower to trace, and refittable
+                             (rr_bvh_refit) */
+  uint32_t reserved[1];
 } rr_bvh_options;
 
 typedef struct {
@@ -193,6 +200,19 @@ rr_status rr_scene_upload(rr_context* ctx, const float* vertices, uint32_t nv,
 rr_status rr_bvh_build(rr_context* ctx, rr_scene* scene, const rr_bvh_options* opt);
 
 rr_status rr_bvh_get_info(const rr_scene* scene, rr_bvh_info* out);
+
+/* Moves the vertices of a scene whose BVH was built on the GPU (builder 1):
+ * vertices_dev holds nv x 3 floats in device memory, nv equal to the count
+ * uploaded, indices and materials unchanged (for moving objects).  The tree
+ * keeps its structure; triangles, normals, boxes and node frames are
+ * recomputed on the GPU, stream-ordered on `stream` with no allocation, so
+ * scans issued after it on that stream see the new geometry.  Triangles
+ * that were degenerate at build time stay out of the tree.  ESTATE if the
+ * BVH was built on the host; EINVAL for a NULL pointer or a vertex count
+ * other than the uploaded one (coordinates in device memory are not
+ * checked). */
+rr_status rr_bvh_refit(rr_context* ctx, rr_scene* scene, const float* vertices_dev, uint32_t nv,
+                       void* stream);
 
 /* Host check of the built hierarchy: traces n_rays random rays (origins in
  * the scene bounds, seeded) through it on the CPU and through a brute-force

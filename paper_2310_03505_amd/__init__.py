@@ -46,7 +46,7 @@ class rr_material(C.Structure):
 class rr_bvh_options(C.Structure):
     _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32),
                 ("n_threads", C.c_uint32), ("split_pct", C.c_uint32), ("width", C.c_uint32),
-                ("merge_leaves", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+                ("merge_leaves", C.c_uint32), ("builder", C.c_uint32), ("reserved", C.c_uint32 * 1)]
 
 
 class rr_bvh_info(C.Structure):
@@ -114,7 +114,7 @@ EXPORTS = (
     "rr_set_tuning", "rr_get_tuning", "rr_server_create", "rr_server_submit", "rr_server_wait",
     "rr_server_poll", "rr_server_get_stats", "rr_server_reset_stats", "rr_server_destroy",
     "rr_autotune", "rr_graph_create", "rr_graph_launch", "rr_graph_destroy", "rr_measure_gather",
-    "rr_postprocess", "rr_radar_scan_post",
+    "rr_postprocess", "rr_radar_scan_post", "rr_bvh_refit",
 )
 
 _lib = None
@@ -170,6 +170,7 @@ def load_library():
         "rr_graph_launch": (st, [vp, P(rr_scan_desc), vp]),
         "rr_graph_destroy": (st, [vp]),
         "rr_measure_gather": (st, [vp, C.c_uint64, C.c_uint32, P(C.c_double)]),
+        "rr_bvh_refit": (st, [vp, vp, vp, C.c_uint32, vp]),
         "rr_postprocess": (st, [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, P(rr_post_params), vp, vp, vp]),
         "rr_radar_scan_post": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material), C.c_uint32,
                                     P(rr_post_params), vp, vp, vp, P(rr_scan_stats), vp]),
@@ -246,9 +247,19 @@ def rr_scene_upload(ctx, vertices, indices, tri_material):
 
 
 def rr_bvh_build(ctx, scene, max_leaf_size: int = 0, sah_bins: int = 0, n_threads: int = 0,
-                 split_pct: int = 0, width: int = 0, merge_leaves: int = 0):
-    opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, split_pct, width, merge_leaves)
+                 split_pct: int = 0, width: int = 0, merge_leaves: int = 0, builder: int = 0):
+    """builder 0: binned SAH on the host; 1: linear BVH on the GPU."""
+    opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, split_pct, width, merge_leaves, builder)
     _check(load_library().rr_bvh_build(ctx, scene, C.byref(opt)), ctx)
+
+
+def rr_bvh_refit(ctx, scene, vertices, stream=None):
+    """New vertex positions (a float32 CUDA tensor [nv, 3]) for a scene whose
+    BVH was built on the GPU; the tree is refitted on the GPU."""
+    import torch
+    if vertices.dtype != torch.float32 or not vertices.is_contiguous() or vertices.dim() != 2:
+        raise ValueError("vertices must be a contiguous float32 tensor [nv, 3]")
+    _check(load_library().rr_bvh_refit(ctx, scene, _ptr(vertices), vertices.shape[0], _stream_handle(stream)), ctx)
 
 
 def rr_bvh_get_info(scene) -> dict:
@@ -592,6 +603,9 @@ class Scene:
 
     def info(self) -> dict:
         return rr_bvh_get_info(self.handle)
+
+    def refit(self, vertices, stream=None):
+        rr_bvh_refit(self._c, self.handle, vertices, stream)
 
     def selfcheck(self, n_rays=10000, seed=1) -> int:
         return rr_bvh_selfcheck(self.handle, n_rays, seed)

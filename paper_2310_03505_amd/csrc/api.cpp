@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -303,10 +304,10 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   if (sc->bvh.width == 8) {
     if (ctx->fused) return fail(ctx, RR_EINVAL, "the one-launch mode needs a four-wide BVH");
     a.nodes8 = static_cast<const Node8*>(sc->d_nodes);
-    a.n_nodes = (uint32_t)sc->bvh.nodes8.size();
+    a.n_nodes = sc->n_nodes;
   } else {
     a.nodes = static_cast<const Node4*>(sc->d_nodes);
-    a.n_nodes = (uint32_t)sc->bvh.nodes.size();
+    a.n_nodes = sc->n_nodes;
   }
   a.tris = sc->d_tris;
   a.aux = sc->d_aux;
@@ -604,10 +605,103 @@ rr_status rr_scene_upload(rr_context* ctx, const float* V, uint32_t nv, const ui
   return RR_OK;
 }
 
+namespace {
+
+void free_scene_device(rr_scene* sc) {
+  if (sc->d_nodes) (void)hipFree(sc->d_nodes);
+  if (sc->d_tris) (void)hipFree(sc->d_tris);
+  if (sc->d_aux) (void)hipFree(sc->d_aux);
+  sc->d_nodes = nullptr;
+  sc->d_tris = nullptr;
+  sc->d_aux = nullptr;
+  if (sc->gb) {
+    rr::gpu_bvh_free(*sc->gb);
+    delete sc->gb;
+    sc->gb = nullptr;
+  }
+}
+
+// Linear BVH built on the GPU from the scene's mesh (uploaded here).
+rr_status build_on_gpu(rr_context* ctx, rr_scene* sc, uint32_t max_leaf) {
+  using namespace rr;
+  if (!ctx) return fail(ctx, RR_EINVAL, "the GPU builder needs a context");
+  if (sc->nt >= kMaxLeafTris) return fail(ctx, RR_EINVAL, "scene has %u triangles, more than 2^27", sc->nt);
+  DeviceGuard dg(ctx->device);
+  auto t0 = std::chrono::steady_clock::now();
+  free_scene_device(sc);
+  sc->gb = new GpuBvh();
+  GpuBvh& g = *sc->gb;
+  g.nv = sc->nv;
+  g.nt = sc->nt;
+  g.max_leaf = max_leaf;
+  const size_t nt = std::max<uint32_t>(sc->nt, 1), nv = std::max<uint32_t>(sc->nv, 1);
+  struct Alloc {
+    void** p;
+    size_t bytes;
+  } allocs[] = {
+      {reinterpret_cast<void**>(&g.V), 12 * nv},          {reinterpret_cast<void**>(&g.F), 12 * nt},
+      {reinterpret_cast<void**>(&g.M), 2 * nt},           {reinterpret_cast<void**>(&g.sorted), 4 * nt},
+      {reinterpret_cast<void**>(&g.child), 8 * nt},       {reinterpret_cast<void**>(&g.parent), 8 * nt},
+      {reinterpret_cast<void**>(&g.range), 8 * nt},       {reinterpret_cast<void**>(&g.head), 4 * nt},
+      {reinterpret_cast<void**>(&g.box), 48 * nt},        {reinterpret_cast<void**>(&g.flag), 4 * nt},
+      {reinterpret_cast<void**>(&g.misc), 64},            {reinterpret_cast<void**>(&g.keys), 8 * nt},
+      {reinterpret_cast<void**>(&g.ids), 4 * nt},         {reinterpret_cast<void**>(&sc->d_nodes), 64 * nt},
+      {reinterpret_cast<void**>(&sc->d_tris), 48 * nt},   {reinterpret_cast<void**>(&sc->d_aux), 16 * nt},
+  };
+  size_t total = 0;
+  for (const Alloc& a : allocs) {
+    HIP_TRY(ctx, hipMalloc(a.p, a.bytes));
+    total += a.bytes;
+  }
+  // scratch of the sort and the scan (rocPRIM reports the sizes)
+  {
+    size_t sb = 0, cb = 0;
+    HIP_TRY(ctx, rocprim_sizes(nt, &sb, &cb));
+    g.temp_bytes = std::max<size_t>(std::max(sb, cb), 256);
+    HIP_TRY(ctx, hipMalloc(&g.temp, g.temp_bytes));
+  }
+  if (sc->nv) HIP_TRY(ctx, hipMemcpy(g.V, sc->V.data(), 12 * (size_t)sc->nv, hipMemcpyHostToDevice));
+  if (sc->nt) {
+    HIP_TRY(ctx, hipMemcpy(g.F, sc->F.data(), 12 * (size_t)sc->nt, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(g.M, sc->M.data(), 2 * (size_t)sc->nt, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(ctx, gpu_bvh_build(g, static_cast<Node4*>(sc->d_nodes), sc->d_tris, sc->d_aux, nullptr));
+  auto t1 = std::chrono::steady_clock::now();
+  BuiltBvh& b = sc->bvh;
+  b = BuiltBvh();
+  b.width = 4;
+  b.n_tris = sc->nt;
+  b.n_hittable = g.m;
+  b.n_refs = g.m;
+  b.n_leaves = g.n_leaves;
+  b.max_depth = g.max_depth;
+  b.max_stack = g.max_stack;
+  b.pad = g.pad;
+  b.build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  sc->n_nodes = g.n_nodes;
+  sc->dev_bytes = 64 * (size_t)g.n_nodes + 48 * (size_t)std::max<uint32_t>(g.m, 1) + 16 * nt;
+  if (b.max_stack > (uint32_t)(kStack + kSpill))
+    return fail(ctx, RR_EOVERFLOW, "BVH needs %u stack entries, more than %u", b.max_stack, kStack + kSpill);
+  sc->built = true;
+  (void)total;
+  return RR_OK;
+}
+
+}  // namespace
+
 rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt) {
   if (!sc) return fail(ctx, RR_EINVAL, "scene is NULL");
   if (sc->ctx != ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
   BvhBuildOptions o;
+  if (opt && opt->builder > 1) return fail(ctx, RR_EINVAL, "builder must be 0 (host) or 1 (GPU)");
+  if (opt && opt->builder == 1) {
+    const uint32_t leaf = opt->max_leaf_size ? opt->max_leaf_size : 2u;
+    if (leaf > 16) return fail(ctx, RR_EINVAL, "max_leaf_size out of [1, 16]");
+    if (opt->width && opt->width != 4) return fail(ctx, RR_EINVAL, "the GPU builder makes four-wide trees");
+    if (opt->split_pct) return fail(ctx, RR_EINVAL, "the GPU builder does not split triangles");
+    sc->built = false;
+    return build_on_gpu(ctx, sc, leaf);
+  }
   if (opt) {
     if (opt->max_leaf_size) o.max_leaf = opt->max_leaf_size;
     if (opt->sah_bins) o.bins = opt->sah_bins;
@@ -635,14 +729,10 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
   if (sc->bvh.width == 8 && sc->bvh.tris.size() / 3 >= kMaxTris8)
     return fail(ctx, RR_EINVAL, "an eight-wide BVH addresses fewer than 2^24 triangle references");
   sc->built = true;
+  sc->n_nodes = (uint32_t)(sc->bvh.width == 8 ? sc->bvh.nodes8.size() : sc->bvh.nodes.size());
   if (!ctx) return RR_OK;
   DeviceGuard g(ctx->device);
-  if (sc->d_nodes) (void)hipFree(sc->d_nodes);
-  if (sc->d_tris) (void)hipFree(sc->d_tris);
-  if (sc->d_aux) (void)hipFree(sc->d_aux);
-  sc->d_nodes = nullptr;
-  sc->d_tris = nullptr;
-  sc->d_aux = nullptr;
+  free_scene_device(sc);
   size_t bn = sc->bvh.width == 8 ? sizeof(Node8) * sc->bvh.nodes8.size() : sizeof(Node4) * sc->bvh.nodes.size();
   size_t bt = sizeof(float4) * std::max<size_t>(sc->bvh.tris.size(), 3);
   size_t ba = sizeof(float4) * std::max<size_t>(sc->bvh.aux.size(), 1);
@@ -669,7 +759,7 @@ rr_status rr_bvh_get_info(const rr_scene* sc, rr_bvh_info* out) {
   std::memset(out, 0, sizeof *out);
   out->n_tris = sc->bvh.n_tris;
   out->n_hittable = sc->bvh.n_hittable;
-  out->n_nodes = (uint32_t)(sc->bvh.width == 8 ? sc->bvh.nodes8.size() : sc->bvh.nodes.size());
+  out->n_nodes = sc->n_nodes;
   out->n_leaves = sc->bvh.n_leaves;
   out->max_depth = sc->bvh.max_depth;
   out->max_stack = sc->bvh.max_stack;
@@ -682,7 +772,75 @@ rr_status rr_bvh_get_info(const rr_scene* sc, rr_bvh_info* out) {
 rr_status rr_bvh_selfcheck(const rr_scene* sc, uint32_t n_rays, uint64_t seed, uint64_t* mismatches) {
   if (!sc || !mismatches) return fail(nullptr, RR_EINVAL, "NULL argument");
   if (!sc->built) return fail(nullptr, RR_ESTATE, "scene has no BVH");
-  *mismatches = bvh_selfcheck(sc->bvh, n_rays, seed);
+  if (!sc->gb) {
+    *mismatches = bvh_selfcheck(sc->bvh, n_rays, seed);
+    return RR_OK;
+  }
+  // a tree built on the GPU: download it and check it on the host, plus
+  // that its leaves hold every hittable triangle of the current vertices
+  // exactly once
+  const rr::GpuBvh& g = *sc->gb;
+  DeviceGuard dg(sc->ctx->device);
+  rr::BuiltBvh b;
+  b.width = 4;
+  b.n_tris = g.nt;
+  b.nodes.resize(sc->n_nodes);
+  b.tris.resize(3 * (size_t)g.m);
+  b.aux.resize(g.nt);
+  std::vector<float> V(3 * (size_t)g.nv);
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(b.nodes.data(), sc->d_nodes, sizeof(rr::Node4) * b.nodes.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+      (g.m && hipMemcpy(b.tris.data(), sc->d_tris, sizeof(float4) * b.tris.size(), hipMemcpyDeviceToHost) != hipSuccess) ||
+      (g.nt && hipMemcpy(b.aux.data(), sc->d_aux, sizeof(float4) * b.aux.size(), hipMemcpyDeviceToHost) != hipSuccess) ||
+      (g.nv && hipMemcpy(V.data(), g.V, 4 * V.size(), hipMemcpyDeviceToHost) != hipSuccess))
+    return fail(sc->ctx, RR_EDEVICE, "download of the GPU-built tree failed");
+  bool first = true;
+  for (uint32_t p = 0; p < g.m; ++p) {
+    const float4* t = &b.tris[3 * (size_t)p];
+    const float v0[3] = {t[0].x, t[0].y, t[0].z};
+    for (int k = 0; k < 3; ++k) {
+      const float q[3] = {v0[k], v0[k] + (&t[1].x)[k], v0[k] + (&t[2].x)[k]};
+      for (float x : q) {
+        b.lo[k] = first ? x : std::min(b.lo[k], x);
+        b.hi[k] = first ? x : std::max(b.hi[k], x);
+      }
+    }
+    first = false;
+  }
+  uint64_t bad = rr::bvh_selfcheck(b, n_rays, seed);
+  std::vector<uint8_t> seen(g.nt, 0);
+  for (uint32_t p = 0; p < g.m; ++p) {
+    uint32_t id;
+    std::memcpy(&id, &b.tris[3 * (size_t)p].w, 4);
+    if (id >= g.nt || seen[id]++) ++bad;
+  }
+  for (uint32_t j = 0; j < g.nt; ++j) {
+    const float* p0 = &V[3 * (size_t)sc->F[3 * (size_t)j + 0]];
+    const float* p1 = &V[3 * (size_t)sc->F[3 * (size_t)j + 1]];
+    const float* p2 = &V[3 * (size_t)sc->F[3 * (size_t)j + 2]];
+    float e1[3], e2[3];
+    for (int a = 0; a < 3; ++a) {
+      e1[a] = p1[a] - p0[a];
+      e2[a] = p2[a] - p0[a];
+    }
+    const float n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2];
+    const float n2 = e1[0] * e2[1] - e1[1] * e2[0];
+    const bool hittable = rr::dot3(n0, n1, n2, n0, n1, n2) > 0.0f;
+    if (hittable != (seen[j] == 1)) ++bad;
+  }
+  *mismatches = bad;
+  return RR_OK;
+}
+
+rr_status rr_bvh_refit(rr_context* ctx, rr_scene* sc, const float* vertices_dev, uint32_t nv, void* stream) {
+  if (!sc || !vertices_dev) return fail(ctx, RR_EINVAL, "NULL argument");
+  if (sc->ctx != ctx || !ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
+  if (!sc->built || !sc->gb) return fail(ctx, RR_ESTATE, "refit needs a BVH built on the GPU (builder 1)");
+  if (nv != sc->gb->nv) return fail(ctx, RR_EINVAL, "refit takes %u vertices, got %u", sc->gb->nv, nv);
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (nv) HIP_TRY(ctx, hipMemcpyAsync(sc->gb->V, vertices_dev, 12 * (size_t)nv, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(ctx, rr::gpu_bvh_refit(*sc->gb, static_cast<rr::Node4*>(sc->d_nodes), sc->d_tris, sc->d_aux, st));
   return RR_OK;
 }
 
@@ -691,9 +849,7 @@ rr_status rr_scene_release(rr_context* ctx, rr_scene* sc) {
   if (sc->ctx != ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
   if (ctx) {
     DeviceGuard g(ctx->device);
-    if (sc->d_nodes) (void)hipFree(sc->d_nodes);
-    if (sc->d_tris) (void)hipFree(sc->d_tris);
-    if (sc->d_aux) (void)hipFree(sc->d_aux);
+    free_scene_device(sc);
   }
   delete sc;
   return RR_OK;

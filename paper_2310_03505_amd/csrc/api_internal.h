@@ -8,6 +8,7 @@
 
 #include "../../include/radarays_hip.h"
 #include "bvh.h"
+#include "bvh_gpu.h"
 #include "kernels.h"
 #include "post.h"
 #include "rr_internal.h"
@@ -49,6 +50,8 @@ struct rr_scene {
   bool built = false;
   rr::BuiltBvh bvh;
   void* d_nodes = nullptr;  // rr::Node4 or rr::Node8 array, as bvh.width says
+  uint32_t n_nodes = 0;     // nodes in d_nodes
+  rr::GpuBvh* gb = nullptr; // state of a tree built on the GPU (kept for refits)
   float4* d_tris = nullptr;
   float4* d_aux = nullptr;
   uint64_t dev_bytes = 0;

@@ -1,0 +1,486 @@
+// bvh_gpu.hip -- linear BVH on the GPU: Morton codes of the triangle
+// centroids, a radix sort, the binary radix tree of Karras ("Maximizing
+// parallelism in the construction of BVHs, octrees, and k-d trees", HPG
+// 2012), bottom-up boxes with one visit counter per inner node, and a
+// collapse of every other level into the four-wide quantised nodes the
+// traversal kernels read.  Every inner node covers a contiguous range of the
+// sorted triangles, so a subtree of at most max_leaf triangles becomes one
+// leaf without copying.  A refit keeps the tree and recomputes triangles,
+// normals, boxes and node frames from moved vertices.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "bvh_gpu.h"
+
+#pragma clang fp contract(off)
+
+namespace rr {
+
+namespace {
+
+constexpr int kB = 256;
+// misc words: [0..2] centroid minimum and [3..5] maximum (order-preserving
+// encodings), [6] largest coordinate magnitude (float bits, >= 1), [7]
+// hittable triangles, [8] four-wide nodes, [9] leaves, [10] deepest
+// four-wide node, [11] deepest binary inner node
+constexpr int kMiscWords = 16;
+
+__device__ __forceinline__ uint32_t fenc(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float fdec(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// triangle j: vertices, edges, geometric normal (the host build's float32
+// operations, so normals match bit for bit); nn > 0 marks a hittable one
+struct Tri {
+  float p0[3], p1[3], p2[3], e1[3], e2[3], n[3], nn;
+};
+__device__ __forceinline__ void load_tri(const GpuBvh& g, uint32_t j, Tri& t) {
+  const float* a = g.V + 3u * g.F[3u * j + 0u];
+  const float* b = g.V + 3u * g.F[3u * j + 1u];
+  const float* c = g.V + 3u * g.F[3u * j + 2u];
+  for (int k = 0; k < 3; ++k) {
+    t.p0[k] = a[k];
+    t.p1[k] = b[k];
+    t.p2[k] = c[k];
+    t.e1[k] = t.p1[k] - t.p0[k];
+    t.e2[k] = t.p2[k] - t.p0[k];
+  }
+  t.n[0] = t.e1[1] * t.e2[2] - t.e1[2] * t.e2[1];
+  t.n[1] = t.e1[2] * t.e2[0] - t.e1[0] * t.e2[2];
+  t.n[2] = t.e1[0] * t.e2[1] - t.e1[1] * t.e2[0];
+  t.nn = dot3(t.n[0], t.n[1], t.n[2], t.n[0], t.n[1], t.n[2]);
+}
+
+__device__ __forceinline__ void tri_box(const Tri& t, float lo[3], float hi[3]) {
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = fminf(fminf(t.p0[k], t.p1[k]), t.p2[k]);
+    hi[k] = fmaxf(fmaxf(t.p0[k], t.p1[k]), t.p2[k]);
+  }
+}
+
+__device__ __forceinline__ float4 aux_of(const GpuBvh& g, uint32_t j, const Tri& t) {
+  if (!(t.nn > 0.0f)) return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const float len = sqrtf(t.nn);
+  return make_float4(t.n[0] / len, t.n[1] / len, t.n[2] / len, __uint_as_float((uint32_t)g.M[j]));
+}
+
+__global__ void k_init_misc(uint32_t* misc, bool refit) {
+  const uint32_t i = threadIdx.x;
+  if (i >= (uint32_t)kMiscWords) return;
+  if (refit) {
+    if (i == 6) misc[i] = __float_as_uint(1.0f);
+    return;
+  }
+  misc[i] = i < 3 ? 0xffffffffu : (i == 6 ? __float_as_uint(1.0f) : 0u);
+}
+
+// per triangle: normal record, hittable count, centroid (into `cen`),
+// centroid bounds and the largest coordinate magnitude (block-reduced)
+__global__ void __launch_bounds__(kB) k_prep(GpuBvh g, float4* aux, float4* cen, bool build) {
+  __shared__ uint32_t s_lo[3], s_hi[3], s_mag, s_cnt;
+  if (threadIdx.x < 3) {
+    s_lo[threadIdx.x] = 0xffffffffu;
+    s_hi[threadIdx.x] = 0u;
+  }
+  if (threadIdx.x == 0) {
+    s_mag = __float_as_uint(1.0f);
+    s_cnt = 0;
+  }
+  __syncthreads();
+  const uint32_t j = blockIdx.x * kB + threadIdx.x;
+  if (j < g.nt) {
+    Tri t;
+    load_tri(g, j, t);
+    aux[j] = aux_of(g, j, t);
+    const bool ok = t.nn > 0.0f;
+    if (ok) {
+      float lo[3], hi[3], mag = 1.0f;
+      tri_box(t, lo, hi);
+      float c[3];
+      for (int k = 0; k < 3; ++k) {
+        c[k] = 0.5f * (lo[k] + hi[k]);
+        mag = fmaxf(mag, fmaxf(fabsf(lo[k]), fabsf(hi[k])));
+      }
+      atomicMax(&s_mag, __float_as_uint(mag));  // positive floats order as their bits
+      if (build) {
+        cen[j] = make_float4(c[0], c[1], c[2], 1.0f);
+        for (int k = 0; k < 3; ++k) {
+          atomicMin(&s_lo[k], fenc(c[k]));
+          atomicMax(&s_hi[k], fenc(c[k]));
+        }
+        atomicAdd(&s_cnt, 1u);
+      }
+    } else if (build) {
+      cen[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(g.misc + 6, s_mag);
+    if (build) {
+      for (int k = 0; k < 3; ++k) {
+        atomicMin(g.misc + k, s_lo[k]);
+        atomicMax(g.misc + 3 + k, s_hi[k]);
+      }
+      atomicAdd(g.misc + 7, s_cnt);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+  x = (x * 0x00010001u) & 0xFF0000FFu;
+  x = (x * 0x00000101u) & 0x0F00F00Fu;
+  x = (x * 0x00000011u) & 0xC30C30C3u;
+  x = (x * 0x00000005u) & 0x49249249u;
+  return x;
+}
+
+// 30-bit Morton key of the centroid in the centroid bounds; unhittable
+// triangles get a key above every valid one and sort last
+__global__ void __launch_bounds__(kB) k_morton(GpuBvh g, const float4* cen) {
+  const uint32_t j = blockIdx.x * kB + threadIdx.x;
+  if (j >= g.nt) return;
+  const float4 c = cen[j];
+  uint32_t key = 0xffffffffu;
+  if (c.w > 0.0f) {
+    const float cc[3] = {c.x, c.y, c.z};
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+      const float lo = fdec(g.misc[k]), hi = fdec(g.misc[3 + k]);
+      const float ext = hi - lo;
+      float u = ext > 0.0f ? (cc[k] - lo) / ext * 1024.0f : 0.0f;
+      u = fminf(fmaxf(u, 0.0f), 1023.0f);
+      q[k] = (uint32_t)u;
+    }
+    key = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+  }
+  g.keys[j] = key;
+  g.ids[j] = j;
+}
+
+// common-prefix length of sorted keys a and b (index bits break ties)
+__device__ __forceinline__ int delta(const uint32_t* key, int m, int a, int b) {
+  if (b < 0 || b >= m) return -1;
+  const uint32_t ka = key[a], kb = key[b];
+  if (ka == kb) return 32 + __clz((uint32_t)(a ^ b));
+  return __clz(ka ^ kb);
+}
+
+// inner node i of the binary radix tree: its key range and split
+__global__ void __launch_bounds__(kB) k_internal(GpuBvh g) {
+  const int m = (int)g.misc[7];
+  const int i = (int)(blockIdx.x * kB + threadIdx.x);
+  if (i >= m - 1) return;
+  const uint32_t* key = g.keys + g.nt;  // sorted keys
+  const int d = (delta(key, m, i, i + 1) - delta(key, m, i, i - 1)) >= 0 ? 1 : -1;
+  const int dmin = delta(key, m, i, i - d);
+  int lmax = 2;
+  while (delta(key, m, i, i + lmax * d) > dmin) lmax *= 2;
+  int l = 0;
+  for (int t = lmax / 2; t >= 1; t /= 2)
+    if (delta(key, m, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = delta(key, m, i, j);
+  int s = 0;
+  for (int t = (l + 1) / 2; t >= 1; t = t == 1 ? 0 : (t + 1) / 2)
+    if (delta(key, m, i, i + (s + t) * d) > dnode) s += t;
+  const int split = i + s * d + (d < 0 ? -1 : 0);
+  const int first = min(i, j), last = max(i, j);
+  const int left = first == split ? ~split : split;
+  const int right = last == split + 1 ? ~(split + 1) : split + 1;
+  g.child[2 * i + 0] = left;
+  g.child[2 * i + 1] = right;
+  g.range[2 * i + 0] = (uint32_t)first;
+  g.range[2 * i + 1] = (uint32_t)last;
+  g.parent[left >= 0 ? left : (m - 1) + ~left] = i;
+  g.parent[right >= 0 ? right : (m - 1) + ~right] = i;
+  if (i == 0) g.parent[0] = -1;
+}
+
+__device__ __forceinline__ float ld_acq(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// per sorted position: the leaf-order triangle, its box, then up the tree;
+// the second of two children to arrive at an inner node forms its box
+__global__ void __launch_bounds__(kB) k_leaves(GpuBvh g, float4* tris) {
+  const int m = (int)g.misc[7];
+  const int p = (int)(blockIdx.x * kB + threadIdx.x);
+  if (p >= m) return;
+  const uint32_t orig = g.sorted[p];
+  Tri t;
+  load_tri(g, orig, t);
+  tris[3 * p + 0] = make_float4(t.p0[0], t.p0[1], t.p0[2], __uint_as_float(orig));
+  tris[3 * p + 1] = make_float4(t.e1[0], t.e1[1], t.e1[2], 0.0f);
+  tris[3 * p + 2] = make_float4(t.e2[0], t.e2[1], t.e2[2], 0.0f);
+  float lo[3], hi[3];
+  tri_box(t, lo, hi);
+  float* b = g.box + 6u * (uint32_t)((m - 1) + p);
+  for (int k = 0; k < 3; ++k) {
+    b[k] = lo[k];
+    b[3 + k] = hi[k];
+  }
+  if (m < 2) return;
+  int node = g.parent[(m - 1) + p];
+  for (int guard = 0; node >= 0 && guard < 128; ++guard) {
+    __threadfence();
+    const uint32_t seen = __hip_atomic_fetch_add(g.flag + node, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (seen == 0u) return;  // the sibling subtree is not done yet
+    const int l = g.child[2 * node], r = g.child[2 * node + 1];
+    const float* bl = g.box + 6u * (uint32_t)(l >= 0 ? l : (m - 1) + ~l);
+    const float* br = g.box + 6u * (uint32_t)(r >= 0 ? r : (m - 1) + ~r);
+    float* bn = g.box + 6u * (uint32_t)node;
+    for (int k = 0; k < 3; ++k) {
+      bn[k] = fminf(ld_acq(bl + k), ld_acq(br + k));
+      bn[3 + k] = fmaxf(ld_acq(bl + 3 + k), ld_acq(br + 3 + k));
+    }
+    node = g.parent[node];
+  }
+}
+
+// four-wide nodes sit at even binary depths; a subtree of at most max_leaf
+// triangles is a leaf and is not opened
+__global__ void __launch_bounds__(kB) k_heads(GpuBvh g) {
+  const int m = (int)g.misc[7];
+  const int i = (int)(blockIdx.x * kB + threadIdx.x);
+  if (i >= (int)g.nt) return;
+  uint32_t is_head = 0;
+  if (i < m - 1) {
+    int depth = 0;
+    for (int n = g.parent[i]; n >= 0 && depth < 128; n = g.parent[n]) ++depth;
+    const uint32_t count = g.range[2 * i + 1] - g.range[2 * i] + 1u;
+    is_head = (i == 0 || ((depth & 1) == 0 && count > g.max_leaf)) ? 1u : 0u;
+    atomicMax(g.misc + 11, (uint32_t)depth);
+    if (is_head) atomicMax(g.misc + 10, (uint32_t)depth / 2u);
+  }
+  g.flag[i] = is_head;
+}
+
+__global__ void __launch_bounds__(kB) k_head_index(GpuBvh g, const uint32_t* scanned) {
+  const int m = (int)g.misc[7];
+  const int i = (int)(blockIdx.x * kB + threadIdx.x);
+  if (i >= m - 1) return;
+  g.head[i] = g.flag[i] ? (int32_t)scanned[i] : -1;
+  if (i == m - 2) g.misc[8] = scanned[i] + g.flag[i];
+}
+
+// the host build's node frame: origin at the low corner, the smallest power
+// of two step with the extent within 255 steps
+__device__ __forceinline__ void quantise_axis(float lo, float hi, float& origin, uint32_t& ebyte) {
+  origin = lo;
+  const double ext = (double)hi - (double)lo;
+  int e = -126;
+  if (ext > 0.0) {
+    frexp(ext / 255.0, &e);
+    while (e > -126 && ext <= 255.0 * ldexp(1.0, e - 1)) --e;
+    while (ext > 255.0 * ldexp(1.0, e)) ++e;
+    e = max(e, -126);
+  }
+  ebyte = (uint32_t)(e + 127);
+}
+
+struct Kid {
+  int32_t ref;
+  float lo[3], hi[3];
+  bool empty;
+};
+
+__device__ void write_node(Node4* out, const Kid* kids, int n_kids, float pad) {
+  float clo[4][3], chi[4][3];
+  float nlo[3] = {INFINITY, INFINITY, INFINITY}, nhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int j = 0; j < n_kids; ++j)
+    for (int a = 0; a < 3; ++a) {
+      clo[j][a] = kids[j].empty ? 0.0f : kids[j].lo[a] - pad;
+      chi[j][a] = kids[j].empty ? 0.0f : kids[j].hi[a] + pad;
+      if (!kids[j].empty) {
+        nlo[a] = fminf(nlo[a], clo[j][a]);
+        nhi[a] = fmaxf(nhi[a], chi[j][a]);
+      }
+    }
+  for (int a = 0; a < 3; ++a)
+    if (!(nlo[a] <= nhi[a])) nlo[a] = nhi[a] = 0.0f;
+  float origin[3];
+  uint32_t eb[3];
+  for (int a = 0; a < 3; ++a) quantise_axis(nlo[a], nhi[a], origin[a], eb[a]);
+  uint32_t qlo[3] = {0u, 0u, 0u}, qhi[3] = {0u, 0u, 0u};
+  int32_t ref[4] = {kEmpty, kEmpty, kEmpty, kEmpty};
+  for (int j = 0; j < n_kids; ++j) {
+    for (int a = 0; a < 3; ++a) {
+      const double sc = ldexp(1.0, (int)eb[a] - 127);
+      const double lo = floor(((double)clo[j][a] - (double)origin[a]) / sc);
+      const double hi = ceil(((double)chi[j][a] - (double)origin[a]) / sc);
+      const uint32_t ql = (uint32_t)fmin(255.0, fmax(0.0, lo));
+      const uint32_t qh = (uint32_t)fmin(255.0, fmax(0.0, hi));
+      qlo[a] |= ql << (8 * j);
+      qhi[a] |= qh << (8 * j);
+    }
+    ref[j] = kids[j].ref;
+  }
+  Node4 nd;
+  nd.w0 = make_float4(origin[0], origin[1], origin[2], __uint_as_float(eb[0] | (eb[1] << 8) | (eb[2] << 16)));
+  nd.w1 = make_uint4(qlo[0], qhi[0], qlo[1], qhi[1]);
+  nd.w2 = make_uint4(qlo[2], qhi[2], 0u, 0u);
+  nd.w3 = make_int4(ref[0], ref[1], ref[2], ref[3]);
+  *out = nd;
+}
+
+__device__ __forceinline__ void kid_of(const GpuBvh& g, int m, int x, bool as_leaf, Kid& k) {
+  const uint32_t slot = (uint32_t)(x >= 0 ? x : (m - 1) + ~x);
+  const float* b = g.box + 6u * slot;
+  for (int a = 0; a < 3; ++a) {
+    k.lo[a] = b[a];
+    k.hi[a] = b[3 + a];
+  }
+  k.empty = false;
+  if (as_leaf) {
+    const uint32_t first = x >= 0 ? g.range[2 * x] : (uint32_t)~x;
+    const uint32_t last = x >= 0 ? g.range[2 * x + 1] : (uint32_t)~x;
+    k.ref = leaf_ref_encode(first, last - first + 1u);
+  } else {
+    k.ref = g.head[x];
+  }
+}
+
+__device__ __forceinline__ bool leaf_sized(const GpuBvh& g, int x) {
+  return x < 0 || g.range[2 * x + 1] - g.range[2 * x] + 1u <= g.max_leaf;
+}
+
+// one four-wide node per head: its two binary children, each opened into
+// its own two children unless it is a leaf
+__global__ void __launch_bounds__(kB) k_emit(GpuBvh g, Node4* nodes, bool count) {
+  const int m = (int)g.misc[7];
+  const int i = (int)(blockIdx.x * kB + threadIdx.x);
+  const float pad = __uint_as_float(g.misc[6]) * (1.0f / 262144.0f);
+  if (m < 2) {
+    // the root must be an inner node: at most one triangle hangs below it
+    if (i == 0) {
+      Kid k[2];
+      int n = 0;
+      if (m == 1) {
+        kid_of(g, m, ~0, true, k[0]);
+        n = 1;
+      }
+      write_node(nodes, k, n, pad);
+      if (count) g.misc[9] = (uint32_t)n;
+    }
+    return;
+  }
+  if (i >= m - 1 || g.head[i] < 0) return;
+  Kid kids[4];
+  int n = 0;
+  uint32_t leaves = 0;
+  for (int s = 0; s < 2; ++s) {
+    const int x = g.child[2 * i + s];
+    if (leaf_sized(g, x)) {
+      kid_of(g, m, x, true, kids[n++]);
+      ++leaves;
+    } else {
+      for (int u = 0; u < 2; ++u) {
+        const int y = g.child[2 * x + u];
+        const bool lf = leaf_sized(g, y);
+        kid_of(g, m, y, lf, kids[n++]);
+        leaves += lf ? 1u : 0u;
+      }
+    }
+  }
+  write_node(nodes + g.head[i], kids, n, pad);
+  if (count) atomicAdd(g.misc + 9, leaves);
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * kB + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+inline dim3 grid_for(uint32_t n) { return dim3(n ? (n + kB - 1) / kB : 1u); }
+
+}  // namespace
+
+hipError_t gpu_bvh_build(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st) {
+  const uint32_t nt = g.nt;
+  hipError_t e;
+#define RR_GB(x)                      \
+  do {                                \
+    if ((e = (x)) != hipSuccess) return e; \
+  } while (0)
+  hipLaunchKernelGGL(k_init_misc, dim3(1), dim3(64), 0, st, g.misc, false);
+  RR_GB(hipGetLastError());
+  float4* cen = reinterpret_cast<float4*>(g.box);  // scratch until the boxes are formed
+  hipLaunchKernelGGL(k_prep, grid_for(nt), dim3(kB), 0, st, g, aux, cen, true);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_morton, grid_for(nt), dim3(kB), 0, st, g, cen);
+  RR_GB(hipGetLastError());
+  size_t bytes = g.temp_bytes;
+  RR_GB(rocprim::radix_sort_pairs(g.temp, bytes, g.keys, g.keys + nt, g.ids, g.sorted, nt, 0u, 32u, st));
+  hipLaunchKernelGGL(k_internal, grid_for(nt), dim3(kB), 0, st, g);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_zero_u32, grid_for(nt), dim3(kB), 0, st, g.flag, nt);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_leaves, grid_for(nt), dim3(kB), 0, st, g, tris);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_heads, grid_for(nt), dim3(kB), 0, st, g);
+  RR_GB(hipGetLastError());
+  // node index of each head: exclusive scan of the head flags into the
+  // first half of the key array (free after the sort)
+  bytes = g.temp_bytes;
+  RR_GB(rocprim::exclusive_scan(g.temp, bytes, g.flag, g.keys, 0u, (size_t)nt, rocprim::plus<uint32_t>(), st));
+  hipLaunchKernelGGL(k_head_index, grid_for(nt), dim3(kB), 0, st, g, g.keys);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_emit, grid_for(nt), dim3(kB), 0, st, g, nodes, true);
+  RR_GB(hipGetLastError());
+  uint32_t h[kMiscWords];
+  RR_GB(hipMemcpyAsync(h, g.misc, sizeof h, hipMemcpyDeviceToHost, st));
+  RR_GB(hipStreamSynchronize(st));
+  g.m = h[7];
+  g.n_nodes = g.m >= 2 ? h[8] : 1u;
+  g.n_leaves = h[9];
+  g.max_depth = g.m >= 2 ? h[10] : 0u;
+  // a node pushes at most three of its children; the path to the deepest
+  // node has max_depth + 1 nodes
+  g.max_stack = 3u * (g.max_depth + 1u);
+  g.pad = __builtin_bit_cast(float, h[6]) * (1.0f / 262144.0f);
+  return hipSuccess;
+}
+
+hipError_t gpu_bvh_refit(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st) {
+  const uint32_t nt = g.nt;
+  hipError_t e;
+  hipLaunchKernelGGL(k_init_misc, dim3(1), dim3(64), 0, st, g.misc, true);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_prep, grid_for(nt), dim3(kB), 0, st, g, aux, nullptr, false);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_zero_u32, grid_for(nt), dim3(kB), 0, st, g.flag, nt);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_leaves, grid_for(nt), dim3(kB), 0, st, g, tris);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_emit, grid_for(nt), dim3(kB), 0, st, g, nodes, false);
+  RR_GB(hipGetLastError());
+#undef RR_GB
+  return hipSuccess;
+}
+
+hipError_t rocprim_sizes(size_t n, size_t* sort_bytes, size_t* scan_bytes) {
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, *sort_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (uint32_t*)nullptr, (uint32_t*)nullptr, n, 0u, 32u);
+  if (e != hipSuccess) return e;
+  return rocprim::exclusive_scan(nullptr, *scan_bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, 0u, n,
+                                 rocprim::plus<uint32_t>());
+}
+
+void gpu_bvh_free(GpuBvh& g) {
+  void* ptrs[] = {g.V, g.F, g.M, g.sorted, g.child, g.parent, g.range, g.head, g.box, g.flag, g.misc, g.temp,
+                  g.keys, g.ids};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  g = GpuBvh();
+}
+
+}  // namespace rr

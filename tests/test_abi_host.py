@@ -129,7 +129,8 @@ def test_host_bvh_wide_and_split(R, width, leaf, split, merge):
 
 def test_bvh_option_validation(R):
     s = W.tiny_room()
-    for bad in (dict(width=6), dict(width=8, max_leaf_size=5), dict(split_pct=201), dict(merge_leaves=3)):
+    for bad in (dict(width=6), dict(width=8, max_leaf_size=5), dict(split_pct=201), dict(merge_leaves=3),
+                dict(builder=2), dict(builder=1), dict(builder=1, width=8, max_leaf_size=2)):
         with pytest.raises(R.RadarError) as e:
             R.Scene(None, s.vertices, s.indices, s.tri_material, **bad)
         assert e.value.status == R.RR_EINVAL

@@ -1,0 +1,203 @@
+"""The BVH built on the GPU (linear BVH, rr_bvh_options.builder = 1) and its
+refit, through the C ABI.
+
+The closest hit is the minimum of (t, original triangle id) over the scene,
+whatever the tree, so a scan over the GPU-built tree must give the same path
+records as the oracle's brute force, and the same fixed-point accumulator,
+bit for bit, as a scan over the host-built SAH tree.  The downloaded tree is
+also checked on the host: host traversal against brute force over its
+leaves, and every hittable triangle in exactly one leaf.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2310_03505_amd as lib
+    lib.load_library()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def scan(R, ctx, sc, s, params=None, pose=None, mask=None):
+    import torch
+    m = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8)).cuda()
+    out = R.rr_radar_scan_records(ctx.handle, sc.handle, pose or s.pose, params or s.params, s.materials,
+                                  primary_mask=m)
+    torch.cuda.synchronize()
+    return dict(image=out["image"].cpu().numpy(), records=out["records"].cpu().numpy(),
+                accum=out["accum"].cpu().numpy(), stats=out["stats"])
+
+
+def deep_mesh():
+    n = 5000
+    xs = np.minimum(np.cumsum(1.05 ** np.arange(n)) * 1e-3, 1e6)
+    V = np.zeros((3 * n, 3), np.float32)
+    V[0::3, 0] = xs
+    V[1::3, 0] = xs + 1e-3
+    V[1::3, 1] = 0.5
+    V[2::3, 0] = xs
+    V[2::3, 2] = 0.5
+    return W.Scene("deep", V, np.arange(3 * n, dtype=np.uint32).reshape(n, 3), np.zeros(n, np.uint16),
+                   [W.material_lambertian(0.5)], W.identity_pose(), W.tiny_room().params)
+
+
+SCENES = {
+    "tiny_room": lambda: W.tiny_room(),
+    "urban_block": lambda: W.urban_block(),
+    "large_scene": lambda: W.large_scene(),
+    "thin_pillars": lambda: W.thin_pillars_scene(),
+    "single": lambda: W.single_triangle_scene((3, -2, -2), (3, 0, 3), (3, 2, -2), W.material_metal()),
+    "deep": deep_mesh,
+}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_gpu_built_tree_selfcheck(R, ctx, name):
+    s = SCENES[name]()
+    log("case: GPU-built tree", name, s.n_tris, "triangles")
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=1)
+    try:
+        info = sc.info()
+        log(f"  nodes {info['n_nodes']}, leaves {info['n_leaves']}, depth {info['max_depth']}, "
+            f"stack bound {info['max_stack']}, build {info['build_ms']:.2f} ms")
+        assert info["n_tris"] == s.n_tris and info["max_stack"] <= 96
+        assert sc.selfcheck(3000 if s.n_tris > 100000 else 20000, 5) == 0
+    finally:
+        sc.release()
+
+
+def test_empty_and_degenerate_only(R, ctx):
+    s = W.tiny_room(n_azimuth=16, rays_per_beam=8)
+    cases = [(s.vertices, s.indices[:0], s.tri_material[:0]),
+             (np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32), np.array([[0, 1, 2]], np.uint32),
+              np.zeros(1, np.uint16))]
+    for V, F, M in cases:
+        sc = R.Scene(ctx, V, F, M, builder=1)
+        try:
+            assert sc.info()["n_hittable"] == 0 and sc.selfcheck(1000, 3) == 0
+            out = scan(R, ctx, sc, W.Scene("x", V, F, M, s.materials[:1], s.pose, s.params))
+            assert not out["image"].any() and (out["records"][:, 0] == -1).all()
+        finally:
+            sc.release()
+
+
+@pytest.mark.parametrize("leaf", [1, 2, 4, 16])
+def test_scan_equals_host_tree_tiny_room(R, ctx, leaf):
+    s = W.tiny_room()
+    a = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    b = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=1, max_leaf_size=leaf)
+    try:
+        ra, rb = scan(R, ctx, a, s), scan(R, ctx, b, s)
+        assert np.array_equal(ra["records"], rb["records"])
+        assert np.array_equal(ra["accum"], rb["accum"])
+        ref = oracle.scan_scene(s, records=True, exempt=True, threads=8)
+        ok = ~ref["exempt"]
+        assert not (rb["records"][ok] != ref["records"][ok]).any()
+    finally:
+        a.release()
+        b.release()
+
+
+@pytest.mark.parametrize("name", ["urban_block", "large_scene"])
+def test_scan_equals_host_tree_full_size(R, ctx, name):
+    """The spec workload and the 2 M-triangle scene: same records and
+    accumulator over the GPU-built tree as over the host SAH tree."""
+    s = SCENES[name]()
+    mask = None
+    if name == "large_scene":
+        rng = np.random.default_rng(7)
+        n = s.params["n_azimuth"] * s.params["rays_per_beam"]
+        mask = (rng.random(n) < 0.05).astype(np.uint8)
+    log("case: full-size scan over both trees", name)
+    a = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    b = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=1)
+    try:
+        ra, rb = scan(R, ctx, a, s, mask=mask), scan(R, ctx, b, s, mask=mask)
+        assert np.array_equal(ra["records"], rb["records"])
+        assert np.array_equal(ra["accum"], rb["accum"])
+        assert ra["stats"]["segments"] == rb["stats"]["segments"]
+    finally:
+        a.release()
+        b.release()
+
+
+def moved(s, t):
+    """Frame t of the tiny room with its cuboids moving: each object (12
+    triangles after the room's 12) turns about its own vertical axis and
+    slides along x."""
+    V = s.vertices.astype(np.float64).copy()
+    obj_vertices = np.unique(s.indices[12:].reshape(-1))
+    n_obj = (s.n_tris - 12) // 12
+    for k in range(n_obj):
+        vid = np.unique(s.indices[12 + 12 * k: 24 + 12 * k].reshape(-1))
+        c = V[vid].mean(axis=0)
+        a = 0.15 * t * (1 + k)
+        rot = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1]])
+        V[vid] = (V[vid] - c) @ rot.T + c + np.array([0.2 * t * (-1) ** k, 0.0, 0.0])
+    assert len(obj_vertices) > 0
+    return V.astype(np.float32)
+
+
+def test_refit_follows_moving_objects(R, ctx):
+    import torch
+    s = W.tiny_room()
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=1)
+    try:
+        for t in (1, 2, 3):
+            Vt = moved(s, t)
+            sc.refit(torch.from_numpy(Vt).cuda())
+            st = W.Scene("moved", Vt, s.indices, s.tri_material, s.materials, s.pose, s.params)
+            got = scan(R, ctx, sc, st)
+            fresh = R.Scene(ctx, Vt, s.indices, s.tri_material)
+            try:
+                want = scan(R, ctx, fresh, st)
+            finally:
+                fresh.release()
+            assert np.array_equal(got["records"], want["records"]), t
+            assert np.array_equal(got["accum"], want["accum"]), t
+            ref = oracle.scan_scene(st, records=True, exempt=True, threads=8)
+            ok = ~ref["exempt"]
+            assert not (got["records"][ok] != ref["records"][ok]).any(), t
+            assert sc.selfcheck(20000, t) == 0
+            log(f"  frame {t}: records equal the oracle on {int(ok.sum())} primaries")
+    finally:
+        sc.release()
+
+
+def test_refit_errors(R, ctx):
+    import torch
+    s = W.tiny_room(n_azimuth=8, rays_per_beam=4)
+    host = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    gpu = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=1)
+    try:
+        V = torch.from_numpy(s.vertices).cuda()
+        with pytest.raises(R.RadarError) as e:
+            host.refit(V)
+        assert e.value.status == R.RR_ESTATE
+        with pytest.raises(R.RadarError) as e:
+            gpu.refit(V[:-1].contiguous())
+        assert e.value.status == R.RR_EINVAL
+    finally:
+        host.release()
+        gpu.release()
