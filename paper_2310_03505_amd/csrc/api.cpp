@@ -646,6 +646,8 @@ rr_status build_on_gpu(rr_context* ctx, rr_scene* sc, uint32_t max_leaf) {
       {reinterpret_cast<void**>(&g.box), 48 * nt},        {reinterpret_cast<void**>(&g.flag), 4 * nt},
       {reinterpret_cast<void**>(&g.misc), 64},            {reinterpret_cast<void**>(&g.keys), 8 * nt},
       {reinterpret_cast<void**>(&g.ids), 4 * nt},         {reinterpret_cast<void**>(&sc->d_nodes), 64 * nt},
+      {reinterpret_cast<void**>(&g.depth), 4 * nt},       {reinterpret_cast<void**>(&g.order), 4 * nt},
+      {reinterpret_cast<void**>(&g.level), 8 * kMaxTreeDepth},
       {reinterpret_cast<void**>(&sc->d_tris), 48 * nt},   {reinterpret_cast<void**>(&sc->d_aux), 16 * nt},
   };
   size_t total = 0;

@@ -5,10 +5,13 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "rr_internal.h"
 
 namespace rr {
+
+constexpr uint32_t kMaxTreeDepth = 128;  // binary depth bound (30-bit keys + index bits)
 
 // Device state of a GPU-built tree, kept for refits (same triangles, moved
 // vertices).  m = hittable (non-degenerate) triangles; the binary radix tree
@@ -24,7 +27,11 @@ struct GpuBvh {
   uint32_t* range = nullptr;   // [m - 1][2] first and last sorted position under inner i
   int32_t* head = nullptr;     // [m - 1] four-wide node index of inner i, or -1
   float* box = nullptr;        // [m - 1 + m][6] boxes of inner nodes, then of single triangles
-  uint32_t* flag = nullptr;    // [m - 1] bottom-up visit counters
+  uint32_t* flag = nullptr;    // [nt] head flags during the build
+  uint32_t* depth = nullptr;   // [m - 1] depth of inner i (root 0)
+  uint32_t* order = nullptr;   // [m - 1] inner nodes grouped by depth
+  uint32_t* level = nullptr;   // [2][kMaxTreeDepth] nodes per depth, then scatter cursors
+  std::vector<uint32_t> level_off, level_cnt;  // host copies: where each depth's nodes start
   uint32_t* misc = nullptr;    // scalars (bounds, counts), see bvh_gpu.hip
   void* temp = nullptr;        // sort / scan scratch
   size_t temp_bytes = 0;
@@ -41,8 +48,10 @@ struct GpuBvh {
 hipError_t gpu_bvh_build(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st);
 
 // Recomputes triangles, normals, boxes and node frames of the existing tree
-// from g.V (updated by the caller); stream-ordered, no allocation.
-hipError_t gpu_bvh_refit(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st);
+// from g.V (updated by the caller): the leaves, then one launch per depth,
+// deepest first, then the four-wide nodes; stream-ordered, no allocation.
+// (refit = false: the tail of a build, normals already written.)
+hipError_t gpu_bvh_refit(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st, bool refit = true);
 
 void gpu_bvh_free(GpuBvh& g);
 

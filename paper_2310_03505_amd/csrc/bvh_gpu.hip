@@ -205,12 +205,7 @@ __global__ void __launch_bounds__(kB) k_internal(GpuBvh g) {
   if (i == 0) g.parent[0] = -1;
 }
 
-__device__ __forceinline__ float ld_acq(const float* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// per sorted position: the leaf-order triangle, its box, then up the tree;
-// the second of two children to arrive at an inner node forms its box
+// per sorted position: the leaf-order triangle and its box
 __global__ void __launch_bounds__(kB) k_leaves(GpuBvh g, float4* tris) {
   const int m = (int)g.misc[7];
   const int p = (int)(blockIdx.x * kB + threadIdx.x);
@@ -228,22 +223,32 @@ __global__ void __launch_bounds__(kB) k_leaves(GpuBvh g, float4* tris) {
     b[k] = lo[k];
     b[3 + k] = hi[k];
   }
-  if (m < 2) return;
-  int node = g.parent[(m - 1) + p];
-  for (int guard = 0; node >= 0 && guard < 128; ++guard) {
-    __threadfence();
-    const uint32_t seen = __hip_atomic_fetch_add(g.flag + node, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (seen == 0u) return;  // the sibling subtree is not done yet
-    const int l = g.child[2 * node], r = g.child[2 * node + 1];
-    const float* bl = g.box + 6u * (uint32_t)(l >= 0 ? l : (m - 1) + ~l);
-    const float* br = g.box + 6u * (uint32_t)(r >= 0 ? r : (m - 1) + ~r);
-    float* bn = g.box + 6u * (uint32_t)node;
-    for (int k = 0; k < 3; ++k) {
-      bn[k] = fminf(ld_acq(bl + k), ld_acq(br + k));
-      bn[3 + k] = fmaxf(ld_acq(bl + 3 + k), ld_acq(br + 3 + k));
-    }
-    node = g.parent[node];
+}
+
+// boxes of the inner nodes of one depth from their children (one launch per
+// depth, deepest first, so the children are complete without any fence)
+__global__ void __launch_bounds__(kB) k_box_level(GpuBvh g, uint32_t first, uint32_t count) {
+  const uint32_t k = blockIdx.x * kB + threadIdx.x;
+  if (k >= count) return;
+  const int m = (int)g.misc[7];
+  const int node = (int)g.order[first + k];
+  const int l = g.child[2 * node], r = g.child[2 * node + 1];
+  const float* bl = g.box + 6u * (uint32_t)(l >= 0 ? l : (m - 1) + ~l);
+  const float* br = g.box + 6u * (uint32_t)(r >= 0 ? r : (m - 1) + ~r);
+  float* bn = g.box + 6u * (uint32_t)node;
+  for (int a = 0; a < 3; ++a) {
+    bn[a] = fminf(bl[a], br[a]);
+    bn[3 + a] = fmaxf(bl[3 + a], br[3 + a]);
   }
+}
+
+// inner nodes into depth buckets (positions from the host's prefix sums)
+__global__ void __launch_bounds__(kB) k_scatter(GpuBvh g) {
+  const int m = (int)g.misc[7];
+  const int i = (int)(blockIdx.x * kB + threadIdx.x);
+  if (i >= m - 1) return;
+  const uint32_t d = g.depth[i];
+  g.order[atomicAdd(g.level + kMaxTreeDepth + d, 1u)] = (uint32_t)i;
 }
 
 // four-wide nodes sit at even binary depths; a subtree of at most max_leaf
@@ -255,7 +260,9 @@ __global__ void __launch_bounds__(kB) k_heads(GpuBvh g) {
   uint32_t is_head = 0;
   if (i < m - 1) {
     int depth = 0;
-    for (int n = g.parent[i]; n >= 0 && depth < 128; n = g.parent[n]) ++depth;
+    for (int n = g.parent[i]; n >= 0 && depth < (int)kMaxTreeDepth - 1; n = g.parent[n]) ++depth;
+    g.depth[i] = (uint32_t)depth;
+    atomicAdd(g.level + depth, 1u);
     const uint32_t count = g.range[2 * i + 1] - g.range[2 * i] + 1u;
     is_head = (i == 0 || ((depth & 1) == 0 && count > g.max_leaf)) ? 1u : 0u;
     atomicMax(g.misc + 11, (uint32_t)depth);
@@ -407,11 +414,13 @@ inline dim3 grid_for(uint32_t n) { return dim3(n ? (n + kB - 1) / kB : 1u); }
 hipError_t gpu_bvh_build(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st) {
   const uint32_t nt = g.nt;
   hipError_t e;
-#define RR_GB(x)                      \
-  do {                                \
+#define RR_GB(x)                           \
+  do {                                     \
     if ((e = (x)) != hipSuccess) return e; \
   } while (0)
   hipLaunchKernelGGL(k_init_misc, dim3(1), dim3(64), 0, st, g.misc, false);
+  RR_GB(hipGetLastError());
+  hipLaunchKernelGGL(k_zero_u32, grid_for(2 * kMaxTreeDepth), dim3(kB), 0, st, g.level, 2 * kMaxTreeDepth);
   RR_GB(hipGetLastError());
   float4* cen = reinterpret_cast<float4*>(g.box);  // scratch until the boxes are formed
   hipLaunchKernelGGL(k_prep, grid_for(nt), dim3(kB), 0, st, g, aux, cen, true);
@@ -422,10 +431,6 @@ hipError_t gpu_bvh_build(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hip
   RR_GB(rocprim::radix_sort_pairs(g.temp, bytes, g.keys, g.keys + nt, g.ids, g.sorted, nt, 0u, 32u, st));
   hipLaunchKernelGGL(k_internal, grid_for(nt), dim3(kB), 0, st, g);
   RR_GB(hipGetLastError());
-  hipLaunchKernelGGL(k_zero_u32, grid_for(nt), dim3(kB), 0, st, g.flag, nt);
-  RR_GB(hipGetLastError());
-  hipLaunchKernelGGL(k_leaves, grid_for(nt), dim3(kB), 0, st, g, tris);
-  RR_GB(hipGetLastError());
   hipLaunchKernelGGL(k_heads, grid_for(nt), dim3(kB), 0, st, g);
   RR_GB(hipGetLastError());
   // node index of each head: exclusive scan of the head flags into the
@@ -434,9 +439,23 @@ hipError_t gpu_bvh_build(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hip
   RR_GB(rocprim::exclusive_scan(g.temp, bytes, g.flag, g.keys, 0u, (size_t)nt, rocprim::plus<uint32_t>(), st));
   hipLaunchKernelGGL(k_head_index, grid_for(nt), dim3(kB), 0, st, g, g.keys);
   RR_GB(hipGetLastError());
-  hipLaunchKernelGGL(k_emit, grid_for(nt), dim3(kB), 0, st, g, nodes, true);
-  RR_GB(hipGetLastError());
+  // depth buckets: counts to the host, prefix sums back as scatter cursors
   uint32_t h[kMiscWords];
+  std::vector<uint32_t> cnt(kMaxTreeDepth), off(kMaxTreeDepth);
+  RR_GB(hipMemcpyAsync(h, g.misc, sizeof h, hipMemcpyDeviceToHost, st));
+  RR_GB(hipMemcpyAsync(cnt.data(), g.level, 4 * kMaxTreeDepth, hipMemcpyDeviceToHost, st));
+  RR_GB(hipStreamSynchronize(st));
+  uint32_t acc = 0;
+  for (uint32_t d = 0; d < kMaxTreeDepth; ++d) {
+    off[d] = acc;
+    acc += cnt[d];
+  }
+  RR_GB(hipMemcpyAsync(g.level + kMaxTreeDepth, off.data(), 4 * kMaxTreeDepth, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_scatter, grid_for(nt), dim3(kB), 0, st, g);
+  RR_GB(hipGetLastError());
+  g.level_cnt = cnt;
+  g.level_off = off;
+  RR_GB(gpu_bvh_refit(g, nodes, tris, aux, st, false));
   RR_GB(hipMemcpyAsync(h, g.misc, sizeof h, hipMemcpyDeviceToHost, st));
   RR_GB(hipStreamSynchronize(st));
   g.m = h[7];
@@ -450,18 +469,24 @@ hipError_t gpu_bvh_build(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hip
   return hipSuccess;
 }
 
-hipError_t gpu_bvh_refit(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st) {
+hipError_t gpu_bvh_refit(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hipStream_t st, bool refit) {
   const uint32_t nt = g.nt;
   hipError_t e;
-  hipLaunchKernelGGL(k_init_misc, dim3(1), dim3(64), 0, st, g.misc, true);
-  RR_GB(hipGetLastError());
-  hipLaunchKernelGGL(k_prep, grid_for(nt), dim3(kB), 0, st, g, aux, nullptr, false);
-  RR_GB(hipGetLastError());
-  hipLaunchKernelGGL(k_zero_u32, grid_for(nt), dim3(kB), 0, st, g.flag, nt);
-  RR_GB(hipGetLastError());
+  if (refit) {
+    hipLaunchKernelGGL(k_init_misc, dim3(1), dim3(64), 0, st, g.misc, true);
+    RR_GB(hipGetLastError());
+    hipLaunchKernelGGL(k_prep, grid_for(nt), dim3(kB), 0, st, g, aux, nullptr, false);
+    RR_GB(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_leaves, grid_for(nt), dim3(kB), 0, st, g, tris);
   RR_GB(hipGetLastError());
-  hipLaunchKernelGGL(k_emit, grid_for(nt), dim3(kB), 0, st, g, nodes, false);
+  for (int d = (int)g.level_cnt.size() - 1; d >= 0; --d) {
+    const uint32_t c = g.level_cnt[(size_t)d];
+    if (!c) continue;
+    hipLaunchKernelGGL(k_box_level, grid_for(c), dim3(kB), 0, st, g, g.level_off[(size_t)d], c);
+    RR_GB(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_emit, grid_for(nt), dim3(kB), 0, st, g, nodes, !refit);
   RR_GB(hipGetLastError());
 #undef RR_GB
   return hipSuccess;
@@ -477,7 +502,7 @@ hipError_t rocprim_sizes(size_t n, size_t* sort_bytes, size_t* scan_bytes) {
 
 void gpu_bvh_free(GpuBvh& g) {
   void* ptrs[] = {g.V, g.F, g.M, g.sorted, g.child, g.parent, g.range, g.head, g.box, g.flag, g.misc, g.temp,
-                  g.keys, g.ids};
+                  g.keys, g.ids, g.depth, g.order, g.level};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   g = GpuBvh();
