@@ -47,7 +47,8 @@ class Params(C.Structure):
                 ("max_bounces", C.c_uint32), ("n_bins", C.c_uint32),
                 ("bin_size_m", C.c_float), ("beam_width_rad", C.c_float),
                 ("beam_prob", C.c_float), ("energy_cutoff", C.c_float),
-                ("seed", C.c_uint64), ("scan_id", C.c_uint32), ("flags", C.c_uint32)]
+                ("seed", C.c_uint64), ("scan_id", C.c_uint32), ("flags", C.c_uint32),
+                ("stretch_az", C.c_float), ("stretch_inc", C.c_float)]
 
 
 class PostParams(C.Structure):
@@ -91,6 +92,8 @@ def _load():
                                      P(C.c_uint32), C.c_uint32, P(C.c_uint8), P(C.c_double),
                                      P(C.c_int32), P(C.c_uint8), P(C.c_double),
                                      P(C.c_uint64), C.c_int]
+            lib.orc_ct_terms.argtypes = [P(Material), P(C.c_double), P(C.c_double), P(C.c_double),
+                                         P(C.c_double)]
             lib.orc_perlin.restype = C.c_double
             lib.orc_perlin.argtypes = [C.c_uint64, C.c_uint32, C.c_double, C.c_double]
             lib.orc_post.argtypes = [P(C.c_float), C.c_uint32, C.c_uint32, P(PostParams),
@@ -114,7 +117,8 @@ def make_pose(pose: dict) -> Pose:
 def make_params(p: dict) -> Params:
     return Params(p["n_azimuth"], p["rays_per_beam"], p["max_bounces"], p["n_bins"],
                   p["bin_size_m"], p["beam_width_rad"], p["beam_prob"], p["energy_cutoff"],
-                  p["seed"], p["scan_id"], p["flags"])
+                  p["seed"], p["scan_id"], p["flags"], p.get("beam_stretch_az", 0.0),
+                  p.get("beam_stretch_inc", 0.0))
 
 
 def make_material(m: dict) -> Material:
@@ -276,3 +280,12 @@ def postprocess(image, post: dict):
     _load().orc_post(_ptr(img, C.c_float), n_az, n_bins, C.byref(pp), _ptr(db, C.c_float),
                      _ptr(u8, C.c_uint8), _ptr(pre, C.c_double))
     return db, u8, pre
+
+
+def ct_terms(material: dict, n, l, v):
+    """Cook-Torrance terms (D, F, G1(n.l) G1(n.v), f) for unit vectors."""
+    m = make_material(material)
+    a = [(C.c_double * 3)(*[float(x) for x in vec]) for vec in (n, l, v)]
+    out = (C.c_double * 4)()
+    _load().orc_ct_terms(C.byref(m), a[0], a[1], a[2], out)
+    return tuple(out[:])

@@ -39,6 +39,7 @@
 #define ORC_DIELECTRIC 0u
 #define ORC_METAL 1u
 #define ORC_LAMBERTIAN 2u
+#define ORC_COOK_TORRANCE 3u
 
 typedef struct {
   float position[3];
@@ -50,6 +51,7 @@ typedef struct {
   float bin_size_m, beam_width_rad, beam_prob, energy_cutoff;
   uint64_t seed;
   uint32_t scan_id, flags;
+  float stretch_az, stretch_inc; /* elliptic beam: scale of the cone offsets (0 = 1) */
 } orc_params;
 
 typedef struct {
@@ -148,12 +150,83 @@ double orc_lobe_integral(double C) {
  * a = A*b/Z, beta = 2B*sin(b/2)/Z, s = S*b/Z (the S term integrated over the
  * window with the one-point midpoint rule, the A and B terms exactly). */
 void orc_window_coeffs(const orc_material* m, double b, double out[4]) {
+  if (m->kind == ORC_COOK_TORRANCE) {
+    /* a three-dimensional BRDF: the window is the solid angle of the cone
+     * of opening angle b around the return direction */
+    out[0] = 2.0 * M_PI * (1.0 - cos(b / 2.0));
+    out[1] = out[2] = out[3] = 0.0;
+    return;
+  }
   double A = m->A, B = m->B, S = 1.0 - A - B;
   double Z = A * M_PI + 2.0 * B + S * orc_lobe_integral(m->C);
   out[0] = Z;
   out[1] = A * b / Z;
   out[2] = 2.0 * B * sin(b / 2.0) / Z;
   out[3] = S * b / Z;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cook-Torrance microfacet BRDF as a second material kind (the user-defined */
+/* BRDF of the experiments, Sec. IV): Cook & Torrance (1982) with the GGX     */
+/* normal distribution and the separable Smith masking of Walter et al.      */
+/* (2007).  Material fields: A = diffuse amount k_d, B = roughness alpha,    */
+/* n = index of refraction of the Fresnel factor, reflectance = reflected    */
+/* share (1 - transmittance).  For unit vectors n (surface, towards the      */
+/* incoming side), l (towards where the ray came from) and v (return):       */
+/*   f = k_d / pi + (1 - k_d) D(h) F(v.h) G1(n.l) G1(n.v) / (4 (n.l)(n.v)),   */
+/*   h = (l + v) / |l + v|, D = a^2 / (pi ((n.h)^2 (a^2 - 1) + 1)^2),        */
+/*   G1(x) = 2x / (x + sqrt(a^2 + (1 - a^2) x^2)), F the unpolarised         */
+/*   Fresnel reflectance from index 1 into n at cos = v.h;                   */
+/* out = {D, F, G1(n.l) G1(n.v), f}; f = 0 unless n.l > 0 and n.v > 0.       */
+/* ------------------------------------------------------------------------ */
+static double fresnel_unpolarised(double N1, double N2, double ci) {
+  double e = N1 / N2;
+  double k64 = 1.0 - e * e * (1.0 - ci * ci);
+  if (k64 < 0.0) return 1.0;
+  double ct = sqrt(k64);
+  double ds = N1 * ci + N2 * ct, dp = N2 * ci + N1 * ct;
+  if (ds == 0.0 || dp == 0.0) return 1.0;
+  double rs = (N1 * ci - N2 * ct) / ds;
+  double rp = (N2 * ci - N1 * ct) / dp;
+  return 0.5 * (rs * rs + rp * rp);
+}
+
+void orc_ct_terms(const orc_material* m, const double n[3], const double l[3], const double v[3],
+                  double out[4]) {
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  double nl = n[0] * l[0] + n[1] * l[1] + n[2] * l[2];
+  double nv = n[0] * v[0] + n[1] * v[1] + n[2] * v[2];
+  if (!(nl > 0.0 && nv > 0.0)) return;
+  double h[3] = {l[0] + v[0], l[1] + v[1], l[2] + v[2]};
+  double hl = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  h[0] = h[0] / hl;
+  h[1] = h[1] / hl;
+  h[2] = h[2] / hl;
+  double nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+  double vh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
+  double a = m->B, a2 = a * a;
+  double q = nh * nh * (a2 - 1.0) + 1.0;
+  double D = a2 / (M_PI * q * q);
+  double g1l = 2.0 * nl / (nl + sqrt(a2 + (1.0 - a2) * nl * nl));
+  double g1v = 2.0 * nv / (nv + sqrt(a2 + (1.0 - a2) * nv * nv));
+  double F = fresnel_unpolarised(1.0, (double)m->n, vh);
+  double kd = m->A;
+  out[0] = D;
+  out[1] = F;
+  out[2] = g1l * g1v;
+  out[3] = kd / M_PI + (1.0 - kd) * D * F * g1l * g1v / (4.0 * nl * nv);
+}
+
+/* share of the reflected energy returned into the beam window around v:
+ * f(l, v) (n.v) Omega, clamped to [0, 1] */
+static double ct_return(const orc_material* m, const float nf[3], const float d[3], const float v[3],
+                        double omega) {
+  double n[3] = {nf[0], nf[1], nf[2]}, l[3] = {-(double)d[0], -(double)d[1], -(double)d[2]};
+  double vv[3] = {v[0], v[1], v[2]}, t[4];
+  orc_ct_terms(m, n, l, vv, t);
+  double nv = n[0] * vv[0] + n[1] * vv[1] + n[2] * vv[2];
+  double w = t[3] * nv * omega;
+  return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -287,6 +360,9 @@ static void primary(const orc_params* prm, const orc_pose* pose, const prim_cons
   double omega = -M_PI + 2.0 * M_PI * u3;
   double r = zz * pc->sigma_r;
   double az_off = r * cos(omega), inc_off = r * sin(omega);
+  /* elliptic beam (Sec. III-A): the cone stretched along the two axes */
+  if (prm->stretch_az > 0.0f) az_off = az_off * (double)prm->stretch_az;
+  if (prm->stretch_inc > 0.0f) inc_off = inc_off * (double)prm->stretch_inc;
   if ((prm->flags & ORC_MIRROR_PAIRS) && (i & 1u)) az_off = -az_off;
   double phi = 2.0 * M_PI * (double)k / (double)prm->n_azimuth + az_off;
   double theta = inc_off;
@@ -336,7 +412,7 @@ static void interact(const float d[3], const float ng[3], const orc_material* m,
   it->kappa = 0.0f;
   it->n2 = n_cur;
   double ci = (double)cosi;
-  if (m->kind == ORC_DIELECTRIC) {
+  if (m->kind == ORC_DIELECTRIC || m->kind == ORC_COOK_TORRANCE) {
     float n1 = n_cur, n2 = it->entering ? m->n : 1.0f;
     float eta = n1 / n2;
     float kappa = 1.0f - (eta * eta) * (1.0f - cosi * cosi);
@@ -355,6 +431,12 @@ static void interact(const float d[3], const float ng[3], const orc_material* m,
       }
       normalizef(it->refr_dir);
       it->has_refract = 1;
+      if (m->kind == ORC_COOK_TORRANCE) {
+        /* a fixed reflected share; the transmitted rest refracts */
+        it->R = m->reflectance;
+        it->T = 1.0 - it->R;
+        goto returned;
+      }
       /* unpolarised Fresnel reflectance, float64 */
       double N1 = n1, N2 = n2;
       double e = N1 / N2;
@@ -374,8 +456,13 @@ static void interact(const float d[3], const float ng[3], const orc_material* m,
     it->R = m->reflectance;
     it->T = 0.0;
   }
+returned:
   if (flags & ORC_RETURN_ALL) {
     it->w = 1.0;
+  } else if (m->kind == ORC_COOK_TORRANCE) {
+    /* retrace: the return direction is the way back, -d */
+    float back[3] = {-d[0], -d[1], -d[2]};
+    it->w = ct_return(m, it->nf, d, back, win[0]);
   } else {
     /* angle between mean reflection and the way back is twice the incidence
      * angle: cos(omega) = 2 cos^2(theta0) - 1, clamped at 0 */
@@ -521,7 +608,7 @@ static void trace_ray(const scan_ctx* c, const oray* r, prim_state* ps) {
   const orc_material* m = &c->mats[c->mat[j]];
   interaction it;
   interact(r->d, c->ng + 3 * j, m, c->win[c->mat[j]], r->n_cur, prm->flags, &it);
-  if (m->kind == ORC_DIELECTRIC && fabs((double)it.kappa) < 1e-6) ps->exempt = 1;
+  if ((m->kind == ORC_DIELECTRIC || m->kind == ORC_COOK_TORRANCE) && fabs((double)it.kappa) < 1e-6) ps->exempt = 1;
 
   /* return along the travelled path, binned by one-way optical range */
   double e_ret = r->E * it.R * it.w;
@@ -568,6 +655,8 @@ static void trace_ray(const scan_ctx* c, const oray* r, prim_state* ps) {
       double w_air;
       if (prm->flags & ORC_RETURN_ALL) {
         w_air = 1.0;
+      } else if (m->kind == ORC_COOK_TORRANCE) {
+        w_air = ct_return(m, it.nf, r->d, s, c->win[c->mat[j]][0]);
       } else {
         double ca = (double)it.refl_dir[0] * s[0] + (double)it.refl_dir[1] * s[1] + (double)it.refl_dir[2] * s[2];
         if (ca < 0.0) ca = 0.0;

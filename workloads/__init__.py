@@ -9,8 +9,8 @@ code of the method.
 """
 from .scenes import (  # noqa: F401
     FLAG_BEAM_GAIN, FLAG_FIXED_PATTERN, FLAG_MIRROR_PAIRS, FLAG_RETURN_ALL, FLAG_AIR_PATH,
-    KIND_DIELECTRIC, KIND_METAL, KIND_LAMBERTIAN,
-    Scene, material_dielectric, material_metal, material_lambertian,
+    KIND_DIELECTRIC, KIND_METAL, KIND_LAMBERTIAN, KIND_COOK_TORRANCE,
+    Scene, material_dielectric, material_metal, material_lambertian, material_cook_torrance,
     sensor_params, identity_pose, yaw_pose,
     tiny_room, urban_block, large_scene, empty_room, plane_scene, slab_scene,
     mirror_scene, single_triangle_scene, thin_pillars_scene,

@@ -33,6 +33,7 @@ FLAG_AIR_PATH = 16
 KIND_DIELECTRIC = 0
 KIND_METAL = 1
 KIND_LAMBERTIAN = 2
+KIND_COOK_TORRANCE = 3
 
 
 # --------------------------------------------------------------------------
@@ -41,6 +42,13 @@ KIND_LAMBERTIAN = 2
 def material_metal(reflectance: float = 0.95, C: float = 2000.0) -> dict:
     return dict(kind=KIND_METAL, n=1.0, reflectance=float(reflectance),
                 A=0.0, B=0.0, C=float(C))
+
+
+def material_cook_torrance(diffuse: float, roughness: float, n: float, transmittance: float) -> dict:
+    """Cook-Torrance microfacet material: diffuse amount k_d (A), GGX
+    roughness (B), Fresnel index n, reflected share 1 - transmittance."""
+    return dict(kind=KIND_COOK_TORRANCE, n=float(n), reflectance=float(1.0 - transmittance),
+                A=float(diffuse), B=float(roughness), C=0.0)
 
 
 def material_dielectric(n: float, roughness: float = 0.0) -> dict:
@@ -73,13 +81,15 @@ def sensor_params(n_azimuth: int, rays_per_beam: int, max_bounces: int,
                   beam_width_deg: float = 2.0, beam_prob: float = 0.9,
                   energy_cutoff: float = 1e-12, seed: int = 0x5EED,
                   scan_id: int = 0, flags: int = FLAG_BEAM_GAIN,
-                  beam_width_rad: float | None = None) -> dict:
+                  beam_width_rad: float | None = None, beam_stretch_az: float = 0.0,
+                  beam_stretch_inc: float = 0.0) -> dict:
     b = math.radians(beam_width_deg) if beam_width_rad is None else beam_width_rad
     return dict(n_azimuth=int(n_azimuth), rays_per_beam=int(rays_per_beam),
                 max_bounces=int(max_bounces), n_bins=int(n_bins),
                 bin_size_m=float(bin_size_m), beam_width_rad=float(b),
                 beam_prob=float(beam_prob), energy_cutoff=float(energy_cutoff),
-                seed=int(seed), scan_id=int(scan_id), flags=int(flags))
+                seed=int(seed), scan_id=int(scan_id), flags=int(flags),
+                beam_stretch_az=float(beam_stretch_az), beam_stretch_inc=float(beam_stretch_inc))
 
 
 @dataclass
