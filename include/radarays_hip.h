@@ -64,7 +64,8 @@ typedef int32_t rr_status;
 /* material kinds */
 #define RR_DIELECTRIC 0u /* Fresnel reflection + Snell refraction, lossless */
 #define RR_METAL 1u      /* reflects `reflectance`, absorbs the rest */
-#define RR_LAMBERTIAN 2u /* reflects `reflectance` (albedo), absorbs the rest */
+#define RR_LAMBERTIAN 2u
+#define RR_COOK_TORRANCE 3u /* reflects `reflectance` (albedo), absorbs the rest */
 
 /* limits */
 #define RR_MAX_BOUNCES 8u
@@ -100,19 +101,34 @@ typedef struct {
  *  beam_prob      P in (0, 1): probability of a ray inside b/2 (Eq. 2)
  *  energy_cutoff  children whose energy is <= this are not traced (>= 0)
  *  seed, scan_id  key of the counter-based generator of the ray samples
- *  flags          RR_* sensor flags */
+ *  flags          RR_* sensor flags
+ *  beam_stretch_az, beam_stretch_inc
+ *                 elliptic beam (Sec. III-A): the drawn cone offsets are
+ *                 scaled by these factors along azimuth and inclination,
+ *                 0..100 (0 = 1, the circular cone); the receive gain keeps
+ *                 the drawn radius */
 typedef struct {
   uint32_t n_azimuth, rays_per_beam, max_bounces, n_bins;
   float bin_size_m, beam_width_rad, beam_prob, energy_cutoff;
   uint64_t seed;
   uint32_t scan_id, flags;
+  float beam_stretch_az, beam_stretch_inc;
 } rr_sensor_params;
 
 /* Material (Sec. III-A; Eq. 5 parameters, S = 1 - A - B).
- *  kind        RR_DIELECTRIC / RR_METAL / RR_LAMBERTIAN
+ *  kind        RR_DIELECTRIC / RR_METAL / RR_LAMBERTIAN / RR_COOK_TORRANCE
  *  n           refractive index of a dielectric (> 0), ignored otherwise
  *  reflectance reflected share for metal and Lambertian, in [0, 1]
- *  A, B, C     lobe parameters: A, B in [0, 1], A + B <= 1, C >= 0 */
+ *  A, B, C     lobe parameters: A, B in [0, 1], A + B <= 1, C >= 0
+ * RR_COOK_TORRANCE (a user-defined BRDF as in Sec. IV): Cook-Torrance with
+ * the GGX distribution and separable Smith masking (Walter et al. 2007),
+ *   f = A / pi + (1 - A) D(h) F(v.h) G1(n.l) G1(n.v) / (4 (n.l)(n.v)),
+ * A = diffuse amount in [0, 1], B = roughness alpha in [1e-4, 1], n = index
+ * of the Fresnel factor (> 0, also the index of refraction of the
+ * transmitted share), reflectance = reflected share (1 - transmittance), C
+ * ignored.  The share returned into the beam window around a return
+ * direction v is f (n.v) 2 pi (1 - cos(b/2)), at most 1; the transmitted
+ * share refracts by Snell's law. */
 typedef struct {
   uint32_t kind;
   float n, reflectance, A, B, C;

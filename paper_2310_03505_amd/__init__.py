@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libradarays_hip.so")
 
 RR_OK, RR_EINVAL, RR_ENOMEM, RR_EDEVICE, RR_ESTATE, RR_EOVERFLOW = 0, -1, -2, -3, -4, -5
 RR_BEAM_GAIN, RR_FIXED_PATTERN, RR_MIRROR_PAIRS, RR_RETURN_ALL, RR_AIR_PATH = 1, 2, 4, 8, 16
-RR_DIELECTRIC, RR_METAL, RR_LAMBERTIAN = 0, 1, 2
+RR_DIELECTRIC, RR_METAL, RR_LAMBERTIAN, RR_COOK_TORRANCE = 0, 1, 2, 3
 RR_MAX_BOUNCES = 8
 
 
@@ -35,7 +35,8 @@ class rr_sensor_params(C.Structure):
                 ("max_bounces", C.c_uint32), ("n_bins", C.c_uint32),
                 ("bin_size_m", C.c_float), ("beam_width_rad", C.c_float),
                 ("beam_prob", C.c_float), ("energy_cutoff", C.c_float),
-                ("seed", C.c_uint64), ("scan_id", C.c_uint32), ("flags", C.c_uint32)]
+                ("seed", C.c_uint64), ("scan_id", C.c_uint32), ("flags", C.c_uint32),
+                ("beam_stretch_az", C.c_float), ("beam_stretch_inc", C.c_float)]
 
 
 class rr_material(C.Structure):
@@ -198,7 +199,8 @@ def make_pose(pose: dict) -> rr_pose:
 def make_params(p: dict) -> rr_sensor_params:
     return rr_sensor_params(p["n_azimuth"], p["rays_per_beam"], p["max_bounces"], p["n_bins"],
                             p["bin_size_m"], p["beam_width_rad"], p["beam_prob"],
-                            p["energy_cutoff"], p["seed"], p["scan_id"], p["flags"])
+                            p["energy_cutoff"], p["seed"], p["scan_id"], p["flags"],
+                            p.get("beam_stretch_az", 0.0), p.get("beam_stretch_inc", 0.0))
 
 
 def make_materials(mats):

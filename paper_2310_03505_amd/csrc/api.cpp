@@ -65,6 +65,9 @@ rr_status check_params(rr_context* ctx, const rr_sensor_params* p) {
   if (!std::isfinite((float)p->n_bins * p->bin_size_m))
     return fail(ctx, RR_EINVAL, "n_bins * bin_size_m overflows");
   if (p->flags & ~31u) return fail(ctx, RR_EINVAL, "unknown flag bits 0x%x", p->flags);
+  if (!(p->beam_stretch_az >= 0.0f && p->beam_stretch_az <= 100.0f && p->beam_stretch_inc >= 0.0f &&
+        p->beam_stretch_inc <= 100.0f))
+    return fail(ctx, RR_EINVAL, "beam stretch factors must be in [0, 100]");
   return RR_OK;
 }
 
@@ -84,9 +87,15 @@ rr_status check_materials(rr_context* ctx, const rr_material* m, uint32_t n, con
   if (n < 1 || n > RR_MAX_MATERIALS || !m) return fail(ctx, RR_EINVAL, "need 1..255 materials");
   for (uint32_t i = 0; i < n; ++i) {
     const rr_material& q = m[i];
-    if (q.kind > RR_LAMBERTIAN) return fail(ctx, RR_EINVAL, "material %u: unknown kind", i);
-    if (q.kind == RR_DIELECTRIC && !(std::isfinite(q.n) && q.n > 0.0f))
+    if (q.kind > RR_COOK_TORRANCE) return fail(ctx, RR_EINVAL, "material %u: unknown kind", i);
+    if ((q.kind == RR_DIELECTRIC || q.kind == RR_COOK_TORRANCE) && !(std::isfinite(q.n) && q.n > 0.0f))
       return fail(ctx, RR_EINVAL, "material %u: n must be > 0", i);
+    if (q.kind == RR_COOK_TORRANCE) {
+      if (!(q.reflectance >= 0.0f && q.reflectance <= 1.0f && q.A >= 0.0f && q.A <= 1.0f && q.B >= 1e-4f &&
+            q.B <= 1.0f))
+        return fail(ctx, RR_EINVAL, "material %u: Cook-Torrance needs A in [0,1], B in [1e-4,1]", i);
+      continue;
+    }
     if (!(q.reflectance >= 0.0f && q.reflectance <= 1.0f))
       return fail(ctx, RR_EINVAL, "material %u: reflectance out of [0,1]", i);
     if (!(q.A >= 0.0f && q.A <= 1.0f && q.B >= 0.0f && q.B <= 1.0f && q.A + q.B <= 1.0f + 1e-6f))
@@ -152,6 +161,8 @@ void make_scan(const rr_pose& pose, const rr_sensor_params& p, DevScan& s) {
   s.flags = p.flags;
   s.scan_id = p.scan_id;
   s.seed = p.seed;
+  s.stretch_az = p.beam_stretch_az > 0.0f ? p.beam_stretch_az : 1.0f;
+  s.stretch_inc = p.beam_stretch_inc > 0.0f ? p.beam_stretch_inc : 1.0f;
   s.n_prim = p.n_azimuth * p.rays_per_beam;
 }
 
@@ -170,6 +181,13 @@ void make_materials(const rr_material* m, uint32_t n, float beam_width, std::vec
     d.n = m[i].n;
     d.refl = m[i].reflectance;
     d.C = m[i].C;
+    if (m[i].kind == RR_COOK_TORRANCE) {
+      // diffuse amount, roughness, and the solid angle of the beam cone
+      d.a = m[i].A;
+      d.beta = m[i].B;
+      d.s = 2.0 * M_PI * (1.0 - std::cos(b / 2.0));
+      continue;
+    }
     d.a = A * b / Z;
     d.beta = 2.0 * B * std::sin(b / 2.0) / Z;
     d.s = S * b / Z;

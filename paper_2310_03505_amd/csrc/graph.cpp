@@ -156,9 +156,10 @@ rr_status rr_graph_launch(rr_graph* g, const rr_scan_desc* descs, void* stream) 
     for (uint32_t i = 0; i < n; ++i) {
       const rr_sensor_params &a = descs[i].params, &b = g->params[i];
       if (a.n_azimuth != b.n_azimuth || a.rays_per_beam != b.rays_per_beam || a.n_bins != b.n_bins ||
-          a.max_bounces != b.max_bounces)
+          a.max_bounces != b.max_bounces || (a.flags & RR_AIR_PATH) != (b.flags & RR_AIR_PATH))
         return fail(ctx, RR_EINVAL,
-                    "scan %u: azimuths, rays per beam, bins and bounces must match the captured scans", i);
+                    "scan %u: azimuths, rays per beam, bins, bounces and the air-path flag must match the "
+                    "captured scans", i);
     }
     if ((s = graph_upload(g, descs, st))) return s;
   }

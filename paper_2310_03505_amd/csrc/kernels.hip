@@ -45,6 +45,9 @@ __device__ __forceinline__ void gen_primary(const DevScan& s, uint32_t k, uint32
   double omega = -M_PI + 2.0 * M_PI * u3;
   double r = zz * s.sigma_r;
   double az_off = r * cos(omega), inc_off = r * sin(omega);
+  // elliptic beam (Sec. III-A): the cone stretched along the two axes
+  if (s.stretch_az != 1.0f) az_off = az_off * (double)s.stretch_az;
+  if (s.stretch_inc != 1.0f) inc_off = inc_off * (double)s.stretch_inc;
   if ((s.flags & 4u) && (i & 1u)) az_off = -az_off;
   double phi = 2.0 * M_PI * (double)k / (double)s.n_az + az_off;
   double theta = inc_off;
@@ -58,6 +61,55 @@ __device__ __forceinline__ void gen_primary(const DevScan& s, uint32_t k, uint32
   dy = (float)(w1 / len);
   dz = (float)(w2 / len);
   g = (s.flags & 1u) ? (float)exp(-0.5 * zz * zz) : 1.0f;
+}
+
+// Unpolarised Fresnel reflectance from index N1 into N2 at incidence cosine
+// ci (float64); 1 beyond the critical angle.
+__device__ __forceinline__ double fresnel_unpolarised(double N1, double N2, double ci) {
+  const double e = N1 / N2;
+  const double k64 = 1.0 - e * e * (1.0 - ci * ci);
+  if (k64 < 0.0) return 1.0;
+  const double ct = sqrt(k64);
+  const double ds = N1 * ci + N2 * ct, dp = N2 * ci + N1 * ct;
+  if (ds == 0.0 || dp == 0.0) return 1.0;
+  const double rs = (N1 * ci - N2 * ct) / ds;
+  const double rp = (N2 * ci - N1 * ct) / dp;
+  return 0.5 * (rs * rs + rp * rp);
+}
+
+// Share of the reflected energy a Cook-Torrance surface returns into the
+// beam cone around unit direction v, for a ray of direction d meeting it
+// with facing normal nf: f(l, v) (n.v) Omega with l = -d, clamped to [0, 1];
+// f = k_d / pi + (1 - k_d) D F G1 G1 / (4 (n.l)(n.v)) with the GGX
+// distribution, separable Smith masking and the unpolarised Fresnel factor
+// (Walter et al., EGSR 2007).  Float64 in a fixed order.
+__device__ __forceinline__ double ct_return(const DevMaterial& M, float nfx, float nfy, float nfz, float dx,
+                                            float dy, float dz, float vx, float vy, float vz) {
+  const double n0 = nfx, n1 = nfy, n2 = nfz;
+  const double l0 = -(double)dx, l1 = -(double)dy, l2 = -(double)dz;
+  const double v0 = vx, v1 = vy, v2 = vz;
+  const double nl = n0 * l0 + n1 * l1 + n2 * l2;
+  const double nv = n0 * v0 + n1 * v1 + n2 * v2;
+  double f = 0.0;
+  if (nl > 0.0 && nv > 0.0) {
+    double h0 = l0 + v0, h1 = l1 + v1, h2 = l2 + v2;
+    const double hl = sqrt(h0 * h0 + h1 * h1 + h2 * h2);
+    h0 = h0 / hl;
+    h1 = h1 / hl;
+    h2 = h2 / hl;
+    const double nh = n0 * h0 + n1 * h1 + n2 * h2;
+    const double vh = v0 * h0 + v1 * h1 + v2 * h2;
+    const double a = M.beta, a2 = a * a;
+    const double q = nh * nh * (a2 - 1.0) + 1.0;
+    const double D = a2 / (M_PI * q * q);
+    const double g1l = 2.0 * nl / (nl + sqrt(a2 + (1.0 - a2) * nl * nl));
+    const double g1v = 2.0 * nv / (nv + sqrt(a2 + (1.0 - a2) * nv * nv));
+    const double F = fresnel_unpolarised(1.0, (double)M.n, vh);
+    const double kd = M.a;
+    f = kd / M_PI + (1.0 - kd) * D * F * g1l * g1v / (4.0 * nl * nv);
+  }
+  const double w = f * nv * M.s;
+  return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
 }
 
 // Origin offset of Waechter & Binder (Ray Tracing Gems, 2019, ch. 6).
@@ -762,7 +814,7 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
   const double ci = (double)cosi;
   bool refract = false;
   uint32_t t_medium = kAir;
-  if (M.kind == 0u) {
+  if (M.kind == 0u || M.kind == 3u) {
     const float n1 = n_cur, n2 = entering ? M.n : 1.0f;
     const float eta = n1 / n2;
     const float kappa = 1.0f - (eta * eta) * (1.0f - cosi * cosi);
@@ -779,17 +831,22 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
       normalize3(o.tdx, o.tdy, o.tdz);
       refract = true;
       t_medium = entering ? mat : kAir;
-      const double N1 = n1, N2 = n2;
-      const double e = N1 / N2;
-      const double k64 = 1.0 - e * e * (1.0 - ci * ci);
-      const double ct = sqrt(k64 > 0.0 ? k64 : 0.0);
-      const double dsum = N1 * ci + N2 * ct, psum = N2 * ci + N1 * ct;
-      if (dsum == 0.0 || psum == 0.0) {
-        R = 1.0;
+      if (M.kind == 3u) {
+        // Cook-Torrance: a fixed reflected share, the rest refracts
+        R = (double)M.refl;
       } else {
-        const double rs = (N1 * ci - N2 * ct) / dsum;
-        const double rp = (N2 * ci - N1 * ct) / psum;
-        R = 0.5 * (rs * rs + rp * rp);
+        const double N1 = n1, N2 = n2;
+        const double e = N1 / N2;
+        const double k64 = 1.0 - e * e * (1.0 - ci * ci);
+        const double ct = sqrt(k64 > 0.0 ? k64 : 0.0);
+        const double dsum = N1 * ci + N2 * ct, psum = N2 * ci + N1 * ct;
+        if (dsum == 0.0 || psum == 0.0) {
+          R = 1.0;
+        } else {
+          const double rs = (N1 * ci - N2 * ct) / dsum;
+          const double rp = (N2 * ci - N1 * ct) / psum;
+          R = 0.5 * (rs * rs + rp * rp);
+        }
       }
       T = 1.0 - R;
     }
@@ -800,6 +857,8 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
   double w;
   if (S->flags & 8u) {
     w = 1.0;
+  } else if (M.kind == 3u) {
+    w = ct_return(M, nfx, nfy, nfz, dx, dy, dz, -dx, -dy, -dz);
   } else {
     double cw = 2.0 * ci * ci - 1.0;
     if (cw < 0.0) cw = 0.0;
@@ -836,6 +895,8 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
         double w_air;
         if (S->flags & 8u) {
           w_air = 1.0;
+        } else if (M.kind == 3u) {
+          w_air = ct_return(M, nfx, nfy, nfz, dx, dy, dz, sx, sy, sz);
         } else {
           double ca = (double)o.rdx * sx + (double)o.rdy * sy + (double)o.rdz * sz;
           ca = ca < 0.0 ? 0.0 : (ca > 1.0 ? 1.0 : ca);

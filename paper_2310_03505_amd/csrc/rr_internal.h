@@ -55,7 +55,9 @@ RR_HD uint32_t leaf_count(int32_t ref) { return (((uint32_t)ref >> 27) & 15u) + 
 // A second 16-byte array holds (geometric unit normal, material id bits).
 
 // Material table entry on the device.  a, beta, s: beam-window coefficients
-// of the normalised standard BRDF (Eq. 3-5), see api.cpp.
+// of the normalised standard BRDF (Eq. 3-5), see api.cpp; for the
+// Cook-Torrance kind: diffuse amount, roughness and the beam cone's solid
+// angle.
 struct DevMaterial {
   uint32_t kind;
   float n;
@@ -77,6 +79,7 @@ struct DevScan {
   float e_cut;
   uint32_t n_az, n_s, max_b, n_bins, flags, scan_id;
   uint64_t seed;
+  float stretch_az, stretch_inc;  // elliptic beam: factors of the cone offsets (1 = circular)
   uint32_t prim_base;  // first global primary of this scan
   uint32_t n_prim;     // n_az * n_s
   uint64_t acc_base;   // first accumulator cell of this scan
