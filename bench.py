@@ -37,9 +37,12 @@ HBM_PEAK_GBS = 8000.0
 # timed-variant dispatches), scaled by what the same counters read for a
 # plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
 # all of them).  Valid only for the kernel sources it was taken on.
-TRACE_HBM = dict(workload="urban_block_200k", fetch_kib=55205.9, write_kib=20226.5,
-                 fetch_scale=2.0, write_scale=1.0,
-                 sources_sha256="236aece52e48d02abfa5ec76b1e34f1eb688b3313ec16b6c0e9e0d9965cbf3d6")
+TRACE_HBM = {
+    "urban_block_200k": dict(fetch_kib=55214.8, write_kib=20213.8),
+    "urban_block_200k_air": dict(fetch_kib=53436.1, write_kib=19776.6),
+}
+TRACE_HBM_SCALE = dict(fetch_scale=2.0, write_scale=1.0,
+                       sources_sha256="0e12a53b7432c7384e678ad5c2df8ebb0200a402185a1bdceee818d3b6810f6e")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
@@ -67,10 +70,10 @@ def post_traffic(wname: str):
 def trace_traffic(wname: str):
     """Measured HBM bytes per k_trace launch, or None when the counters were
     taken on another workload or on other kernel sources."""
-    t = TRACE_HBM
-    if wname != t["workload"] or trace_sources_sha256() != t["sources_sha256"]:
+    t, c = TRACE_HBM.get(wname), TRACE_HBM_SCALE
+    if t is None or trace_sources_sha256() != c["sources_sha256"]:
         return None
-    return int(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+    return int(1024 * (t["fetch_kib"] * c["fetch_scale"] + t["write_kib"] * c["write_scale"]))
 
 
 def log(*a):
@@ -209,9 +212,9 @@ def bench_trajectory(args):
 POST_BYTES_PER_PIXEL = 9   # float32 energy read, float32 dB and 8-bit pixel written
 # HBM traffic of one k_post launch over the 64 x 400 x 3776 images, from the
 # same two rocprofv3 --pmc passes and copy-kernel scale as the trace kernel's
-POST_HBM = dict(workload="polar_epilogue_64x400x3776", fetch_kib=198518.0, write_kib=472000.0,
+POST_HBM = dict(workload="polar_epilogue_64x400x3776", fetch_kib=198520.1, write_kib=472000.0,
                 fetch_scale=2.0, write_scale=1.0,
-                sources_sha256="a22ae2b26b20bc7f289793c9856f5f050258215f7ee641484f8f1ac7d9c6f0f7")
+                sources_sha256="f1b4d1b309689b6062387408831c57132e67e0128da69f3c5e5685a17ae3ec0c")
 POST_SOURCES = ("post.hip", "post.h", "philox.h", "rr_internal.h")
 POST_FULL = dict(blur_sigma_bins=2.0, uniform_amp=1e-7, perlin_amp=1e-6, perlin_cell_az=16.0,
                  perlin_cell_bins=64.0, seed=12345, scan_id=0)
@@ -439,6 +442,8 @@ def main():
                     help="serve one request per launch on one stream (baseline)")
     ap.add_argument("--air", action="store_true",
                     help="also return along the air path (one visibility ray per hit at depth >= 1)")
+    ap.add_argument("--cook-torrance", action="store_true",
+                    help="every material of the scene as the Cook-Torrance BRDF with the paper's parameters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -475,6 +480,11 @@ def main():
     if args.air:
         scene.params = dict(scene.params, flags=scene.params["flags"] | R.RR_AIR_PATH)
         wname += "_air"
+    if args.cook_torrance:
+        import workloads as W
+        # diffuse amount 0.2, roughness 0.5, n 100, transmittance 0.1 (Sec. IV)
+        scene.materials = [W.material_cook_torrance(0.2, 0.5, 100.0, 0.1) for _ in scene.materials]
+        wname += "_cook_torrance"
     p = scene.params
     log(f"bench: {wname}, {scene.n_tris} tris, {p['n_azimuth']}x{p['rays_per_beam']}, "
         f"B={p['max_bounces']}, bins={p['n_bins']}")

@@ -242,33 +242,50 @@ __global__ void __launch_bounds__(kB) k_box_level(GpuBvh g, uint32_t first, uint
   }
 }
 
-// inner nodes into depth buckets (positions from the host's prefix sums)
+// inner nodes into depth buckets (positions from the host's prefix sums):
+// ranks within the workgroup from LDS, one global reservation per
+// workgroup and depth
 __global__ void __launch_bounds__(kB) k_scatter(GpuBvh g) {
+  __shared__ uint32_t s_cnt[kMaxTreeDepth], s_base[kMaxTreeDepth];
+  for (uint32_t d = threadIdx.x; d < kMaxTreeDepth; d += kB) s_cnt[d] = 0u;
+  __syncthreads();
   const int m = (int)g.misc[7];
   const int i = (int)(blockIdx.x * kB + threadIdx.x);
-  if (i >= m - 1) return;
-  const uint32_t d = g.depth[i];
-  g.order[atomicAdd(g.level + kMaxTreeDepth + d, 1u)] = (uint32_t)i;
+  const bool live = i < m - 1;
+  const uint32_t d = live ? g.depth[i] : 0u;
+  const uint32_t rank = live ? atomicAdd(&s_cnt[d], 1u) : 0u;
+  __syncthreads();
+  for (uint32_t e = threadIdx.x; e < kMaxTreeDepth; e += kB)
+    s_base[e] = s_cnt[e] ? atomicAdd(g.level + kMaxTreeDepth + e, s_cnt[e]) : 0u;
+  __syncthreads();
+  if (live) g.order[s_base[d] + rank] = (uint32_t)i;
 }
 
 // four-wide nodes sit at even binary depths; a subtree of at most max_leaf
 // triangles is a leaf and is not opened
+// (the per-depth counts are summed in LDS first: one global atomic per
+// workgroup and depth instead of one per node on a few dozen addresses)
 __global__ void __launch_bounds__(kB) k_heads(GpuBvh g) {
+  __shared__ uint32_t s_cnt[kMaxTreeDepth];
+  for (uint32_t d = threadIdx.x; d < kMaxTreeDepth; d += kB) s_cnt[d] = 0u;
+  __syncthreads();
   const int m = (int)g.misc[7];
   const int i = (int)(blockIdx.x * kB + threadIdx.x);
-  if (i >= (int)g.nt) return;
   uint32_t is_head = 0;
   if (i < m - 1) {
     int depth = 0;
     for (int n = g.parent[i]; n >= 0 && depth < (int)kMaxTreeDepth - 1; n = g.parent[n]) ++depth;
     g.depth[i] = (uint32_t)depth;
-    atomicAdd(g.level + depth, 1u);
+    atomicAdd(&s_cnt[depth], 1u);
     const uint32_t count = g.range[2 * i + 1] - g.range[2 * i] + 1u;
     is_head = (i == 0 || ((depth & 1) == 0 && count > g.max_leaf)) ? 1u : 0u;
     atomicMax(g.misc + 11, (uint32_t)depth);
     if (is_head) atomicMax(g.misc + 10, (uint32_t)depth / 2u);
   }
-  g.flag[i] = is_head;
+  if (i < (int)g.nt) g.flag[i] = is_head;
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < kMaxTreeDepth; d += kB)
+    if (s_cnt[d]) atomicAdd(g.level + d, s_cnt[d]);
 }
 
 __global__ void __launch_bounds__(kB) k_head_index(GpuBvh g, const uint32_t* scanned) {
