@@ -378,19 +378,25 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           if (++visits > A.n_nodes) trav_done = true;
         }
       }
-      // hit leaves into the ring, child slot by child slot (all lanes take
-      // part, so the ring head stays the same in every lane)
+      // hit leaves into the ring, lane by lane: the lane's position is the
+      // exclusive prefix sum of the leaf counts (at most 4, three bits, one
+      // ballot each); most steps hit no leaf and skip it after one ballot.
+      // All lanes take part, so the ring head stays the same in every lane.
+      const uint32_t nleaf = (uint32_t)__popc(leaves);
+      if (__ballot(nleaf != 0u)) {
+        const uint64_t c0 = __ballot(nleaf & 1u), c1 = __ballot(nleaf & 2u), c2 = __ballot(nleaf & 4u);
+        uint32_t p = ring_head + (uint32_t)__popcll(c0 & lanes_below) + 2u * (uint32_t)__popcll(c1 & lanes_below) +
+                     4u * (uint32_t)__popcll(c2 & lanes_below);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bool want = (leaves >> j) & 1u;
-        const uint64_t m = __ballot(want);
-        if (want) {
-          const uint32_t p = ring_head + (uint32_t)__popcll(m & lanes_below);
-          lds_leaf[wib][p & (kLeafRing - 1u)] = (uint32_t)lref[j];
-          lds_own[wib][p & (kLeafRing - 1u)] = (uint8_t)lane;
-          last_pos = p + 1u;
+        for (int j = 0; j < 4; ++j) {
+          if ((leaves >> j) & 1u) {
+            lds_leaf[wib][p & (kLeafRing - 1u)] = (uint32_t)lref[j];
+            lds_own[wib][p & (kLeafRing - 1u)] = (uint8_t)lane;
+            ++p;
+          }
         }
-        ring_head += (uint32_t)__popcll(m);
+        if (nleaf) last_pos = p;
+        ring_head += (uint32_t)__popcll(c0) + 2u * (uint32_t)__popcll(c1) + 4u * (uint32_t)__popcll(c2);
       }
     }
     __builtin_amdgcn_wave_barrier();
