@@ -125,15 +125,23 @@ def cpu_baseline(scene, threads: int, n_cols: int):
 
 def bench_trajectory(args):
     """64 poses along a spline through the 2M-triangle scene, each with its
-    own azimuth count and rays per beam (B = 5).  The launch parameters are
-    autotuned on the first pose; the scans are then run as batched launches
-    (groups bounded by the workspace budget), as HIP graphs of those groups
-    replayed with the same tables, and one rr_radar_scan at a time."""
+    own azimuth count and rays per beam (B = 5), or (``--trajectory-scene
+    tiny``) 64 seeded poses in the 60-triangle room at its own sensor settings
+    (400 x 64 rays, B = 3).  The launch parameters are autotuned on the first
+    pose; the scans are then run as batched launches (groups bounded by the
+    workspace budget), as HIP graphs of those groups replayed with the same
+    tables, and one rr_radar_scan at a time."""
     import torch
     import paper_2310_03505_amd as R
     import workloads as W
-    scene = W.large_scene()
-    scans = W.spline_poses()
+    if args.trajectory_scene == "tiny":
+        scene = W.tiny_room()
+        scans = W.room_poses(scene)
+        wname = "trajectory_64_poses_tiny_room_60"
+    else:
+        scene = W.large_scene()
+        scans = W.spline_poses()
+        wname = "trajectory_64_poses_large_scene_2m"
     log(f"bench: trajectory, {len(scans)} scans on {scene.n_tris} tris")
     ctx = R.Context(0)
     sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
@@ -192,7 +200,7 @@ def bench_trajectory(args):
         "unit": "Mray-segments/s", "n_gpus": 1, "steps": steps, "warmup": 1,
         "ms_per_step": round(batch_ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "trajectory_64_poses_large_scene_2m", "n_tris": scene.n_tris,
+        "config": {"workload": wname, "n_tris": scene.n_tris,
                    "n_scans": len(scans), "primaries": sum(p["n_azimuth"] * p["rays_per_beam"]
                                                             for _, p in scans),
                    "segments_per_step": segs, "scans_per_s": round(len(scans) / (batch_ms / 1e3), 2),
@@ -434,6 +442,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="urban", choices=["urban", "tiny", "large", "trajectory", "serve", "post", "build"])
+    ap.add_argument("--trajectory-scene", default="large", choices=["large", "tiny"],
+                    help="trajectory workload: 64 poses on the 2M-triangle scene or in the tiny room")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed request stream (serve workload)")
     ap.add_argument("--serve-rate-scale", type=float, default=1.0,
@@ -460,7 +470,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py runs on one GPU only; more than one GPU is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

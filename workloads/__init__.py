@@ -16,5 +16,5 @@ from .scenes import (  # noqa: F401
     mirror_scene, single_triangle_scene, thin_pillars_scene,
     transform_scene,
 )
-from .poses import spline_poses, request_stream, street_points  # noqa: F401
+from .poses import spline_poses, room_poses, request_stream, street_points  # noqa: F401
 from .images import polar_images  # noqa: F401

@@ -1,11 +1,12 @@
-"""Seeded sensor trajectories and scan-request streams on the large scene."""
+"""Seeded sensor trajectories and scan-request streams on the large scene,
+and seeded poses inside the tiny room."""
 from __future__ import annotations
 
 import math
 
 import numpy as np
 
-from .scenes import BLOCK, PITCH, N_LOTS, sensor_params, yaw_pose
+from .scenes import BLOCK, PITCH, N_LOTS, ROOM_LO, ROOM_HI, sensor_params, yaw_pose
 
 
 def street_points(rng, n: int, tiles: int = 3):
@@ -64,6 +65,28 @@ def spline_poses(seed: int = 4, n_poses: int = 64, n_knots: int = 8,
                                int(rng.choice([256, 1024, 4096])),
                                max_bounces, n_bins, scan_id=i, **kw)
         out.append((pose, params))
+    return out
+
+
+def room_poses(room, seed: int = 6, n_poses: int = 64, n_azimuth: int = 400,
+               rays_per_beam: int = 64, max_bounces: int = 3, n_bins: int = 1024, **kw):
+    """``n_poses`` seeded poses inside the tiny room ``room`` (a Scene from
+    ``tiny_room``): x, y uniform at least 0.5 m from the walls and 0.2 m clear
+    of every cuboid's bounding circle, z = 0 (1 m above the floor), yaw
+    uniform; every scan has the room's own sensor settings.  Returns a list
+    of (pose, params)."""
+    rng = np.random.default_rng(seed)
+    circles = room.meta["cuboids"]
+    out = []
+    while len(out) < n_poses:
+        x = rng.uniform(ROOM_LO[0] + 0.5, ROOM_HI[0] - 0.5)
+        y = rng.uniform(ROOM_LO[1] + 0.5, ROOM_HI[1] - 0.5)
+        yaw = rng.uniform(-math.pi, math.pi)
+        if any(math.hypot(x - cx, y - cy) < r + 0.2 for cx, cy, r in circles):
+            continue
+        params = sensor_params(n_azimuth, rays_per_beam, max_bounces, n_bins,
+                               scan_id=len(out), **kw)
+        out.append((yaw_pose((x, y, 0.0), yaw), params))
     return out
 
 
