@@ -155,7 +155,14 @@ typedef struct {
                              and split_pct 0 only) -- about ten times faster to
                              build, slower to trace, and refittable
                              (rr_bvh_refit) */
-  uint32_t reserved[1];
+  uint32_t collapse;      /* host builder, width 4: how the binary SAH tree is
+                             collapsed into four-wide nodes.  0: default (2);
+                             1: greedy, each node opens its largest-area inner
+                             child until it has four; 2: cost-optimal, a
+                             dynamic program over the binary tree minimises
+                             the expected surface-area cost of node steps and
+                             triangle tests.  Ignored by the GPU builder and
+                             for width 8. */
 } rr_bvh_options;
 
 typedef struct {

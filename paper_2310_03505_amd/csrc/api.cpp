@@ -730,6 +730,8 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
     o.width = opt->width ? opt->width : 4u;
     if (opt->merge_leaves > 2) return fail(ctx, RR_EINVAL, "merge_leaves out of [0, 2]");
     o.merge_leaves = opt->merge_leaves != 2;
+    if (opt->collapse > 2) return fail(ctx, RR_EINVAL, "collapse out of [0, 2]");
+    o.collapse = opt->collapse == 1 ? 1u : 0u;
   }
   if (o.width != 4 && o.width != 8) return fail(ctx, RR_EINVAL, "width must be 4 or 8");
   if (o.width == 8 && o.max_leaf > 4) return fail(ctx, RR_EINVAL, "an eight-wide BVH takes leaves of at most 4 triangles");

@@ -111,6 +111,16 @@ struct BNode {
   std::unique_ptr<BNode> l, r;
   uint32_t begin = 0, count = 0;  // leaf range in the ref array
   uint32_t span = 0;              // references below an inner node (from begin)
+  // four-wide collapse plan (cost-optimal mode): cover[j] is the least
+  // expected cost of the subtree as at most j entries of a wide node; the
+  // subtree is one entry if cl[j] == 0, else its left child takes cl[j]
+  // entries and its right child cr[j].  As a wide node of its own, the left
+  // child takes wide_l of the four entries; as one entry it is a leaf if
+  // as_leaf.
+  double cover[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  uint8_t cl[5] = {0, 0, 0, 0, 0}, cr[5] = {0, 0, 0, 0, 0};
+  uint8_t wide_l = 2;
+  bool as_leaf = false;
   bool leaf() const { return !l; }
 };
 
@@ -229,11 +239,23 @@ struct Builder {
   }
 };
 
-// Collapses the two-wide build tree into four-wide quantised nodes: each
-// output node takes the two children of a build node and repeatedly opens
-// its largest-area inner child until it has four children.  Children are
-// emitted after their parent (preorder), so child indices exceed parents'.
+// Collapses the two-wide build tree into four-wide quantised nodes.  Which
+// build nodes become wide nodes, leaves or opened entries is chosen either
+// greedily (each output node takes the two children of a build node and
+// repeatedly opens its largest-area inner child until it has four children)
+// or, by default, by the dynamic program of the surface-area cost over the
+// build tree (as in Ylitie, Karras and Laine, HPG 2017, for eight-wide
+// trees): the expected cost of a wide node is kWideNodeCost times its area,
+// that of a leaf kLeafRefCost times its area per reference, and every build
+// node's cheapest cover by one to four entries is found bottom-up.  Children
+// are emitted after their parent (preorder), so child indices exceed
+// parents'.
 struct Flattener4 {
+  // relative cost of one node step (four box tests, the sort and the stack)
+  // and of one triangle test, per unit of box area
+  static constexpr double kWideNodeCost = 1.0;
+  static constexpr double kLeafRefCost = 0.3;
+
   const std::vector<Ref>& refs;
   const std::vector<float4>& tri3;
   const std::vector<float4>& aux0;
@@ -241,9 +263,68 @@ struct Flattener4 {
   float pad;
   double root_area;
   uint32_t leaf_max = 0;  // > 0: a subtree with at most this many references becomes one leaf
+  bool optimal = true;    // cost-optimal collapse (else greedy)
 
   static uint32_t refs_of(const BNode* k) { return k->leaf() ? k->count : k->span; }
-  bool is_leaf(const BNode* k) const { return k->leaf() || (leaf_max && k->span <= leaf_max); }
+  bool is_leaf(const BNode* k) const {
+    if (optimal) return k->leaf() || k->as_leaf;
+    return k->leaf() || (leaf_max && k->span <= leaf_max);
+  }
+
+  // bottom-up cover costs of the cost-optimal collapse
+  void plan(BNode* n) {
+    const double area = n->box.empty() ? 0.0 : n->box.area();
+    if (n->leaf()) {
+      const double c = kLeafRefCost * (double)n->count * area;
+      for (int j = 1; j <= 4; ++j) {
+        n->cover[j] = c;
+        n->cl[j] = n->cr[j] = 0;
+      }
+      n->as_leaf = true;
+      return;
+    }
+    BNode* l = n->l.get();
+    BNode* r = n->r.get();
+    plan(l);
+    plan(r);
+    // as a wide node: the two children share its four entries
+    double wide = INFINITY;
+    for (int k = 1; k <= 3; ++k) {
+      const double c = l->cover[k] + r->cover[4 - k];
+      if (c < wide) {
+        wide = c;
+        n->wide_l = (uint8_t)k;
+      }
+    }
+    wide += kWideNodeCost * area;
+    const double as_leaf = (leaf_max && n->span <= leaf_max) ? kLeafRefCost * (double)n->span * area : INFINITY;
+    n->as_leaf = as_leaf <= wide;
+    n->cover[1] = std::min(as_leaf, wide);
+    n->cl[1] = n->cr[1] = 0;
+    for (int j = 2; j <= 4; ++j) {
+      n->cover[j] = n->cover[j - 1];
+      n->cl[j] = n->cl[j - 1];
+      n->cr[j] = n->cr[j - 1];
+      for (int k = 1; k < j; ++k) {
+        const double c = l->cover[k] + r->cover[j - k];
+        if (c < n->cover[j]) {
+          n->cover[j] = c;
+          n->cl[j] = (uint8_t)k;
+          n->cr[j] = (uint8_t)(j - k);
+        }
+      }
+    }
+  }
+
+  // the entries of a subtree covered by at most j entries, in order
+  static void gather(const BNode* n, int j, std::vector<const BNode*>& kids) {
+    if (n->cl[j] == 0) {
+      kids.push_back(n);
+      return;
+    }
+    gather(n->l.get(), n->cl[j], kids);
+    gather(n->r.get(), n->cr[j], kids);
+  }
 
   static void quantise_axis(float lo, float hi, float& origin, uint32_t& ebyte) {
     origin = lo;
@@ -286,8 +367,14 @@ struct Flattener4 {
 
   // returns the worst-case stack need of the subtree
   uint32_t emit(const BNode* b, uint32_t depth, int32_t* ref_out) {
-    std::vector<const BNode*> kids{b->l.get(), b->r.get()};
-    while (kids.size() < 4) {
+    std::vector<const BNode*> kids;
+    if (optimal) {
+      gather(b->l.get(), b->wide_l, kids);
+      gather(b->r.get(), 4 - b->wide_l, kids);
+    } else {
+      kids = {b->l.get(), b->r.get()};
+    }
+    while (!optimal && kids.size() < 4) {
       // open the largest child that has children, those too big for a leaf first
       int best = -1;
       double ba = -1.0;
@@ -693,7 +780,8 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
     out.max_stack = fl.fill(root.get(), 0, 0);
   } else {
     Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area(),
-                  merge ? std::max(1u, opt.max_leaf) : 0u};
+                  merge ? std::max(1u, opt.max_leaf) : 0u, opt.collapse != 1};
+    if (fl.optimal) fl.plan(root.get());
     int32_t root_ref;
     out.max_stack = fl.emit(root.get(), 0, &root_ref);
   }

@@ -25,6 +25,12 @@
 
 namespace rr {
 
+// Set bits of a wave-wide mask in the lanes below this one (the exclusive
+// prefix count of a ballot): v_mbcnt_lo over lanes 0-31, v_mbcnt_hi over 32-63.
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 constexpr uint32_t kHashBits = 11;     // shade: LDS table of 2048 accumulator cells
 constexpr uint32_t kHashSlots = 1u << kHashBits;
 constexpr uint32_t kHashEmpty = 0xffffffffu;
@@ -160,7 +166,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
-  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
   const uint32_t n_in = kShadow ? min(A.counters[kCtrShadow], A.shq_cap) : min(A.counters[kCtrCount + A.depth], A.cap);
   uint32_t* cursor = kShadow ? A.counters + kCtrShadowWork : A.counters + kCtrWork + A.depth;
   const Node4* __restrict__ nodes = A.nodes;
@@ -201,7 +206,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           }
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
-        const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+        const uint32_t rank = lane_prefix(idle);
         const bool mine = !valid && rank < take;
         if (mine) {
           const uint32_t my = pool_next + rank;
@@ -390,8 +395,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         const uint32_t nleaf = (uint32_t)__popc(leaves);
         if (__ballot(nleaf != 0u)) {
           const uint64_t c0 = __ballot(nleaf & 1u), c1 = __ballot(nleaf & 2u), c2 = __ballot(nleaf & 4u);
-          uint32_t p = ring_head + (uint32_t)__popcll(c0 & lanes_below) + 2u * (uint32_t)__popcll(c1 & lanes_below) +
-                       4u * (uint32_t)__popcll(c2 & lanes_below);
+          uint32_t p = ring_head + lane_prefix(c0) + 2u * lane_prefix(c1) +
+                       4u * lane_prefix(c2);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if ((leaves >> j) & 1u) {
@@ -464,7 +469,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
-  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
   const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
   uint32_t* cursor = A.counters + kCtrWork + A.depth;
   const Node8* __restrict__ nodes = A.nodes8;
@@ -505,7 +509,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
           }
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
-        const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+        const uint32_t rank = lane_prefix(idle);
         if (!valid && rank < take) {
           const uint32_t my = pool_next + rank;
           const float4 a = A.in.a[my];
@@ -652,7 +656,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const uint64_t m = __ballot((cnt >> b) & 1u);
-        prefix += (uint32_t)__popcll(m & lanes_below) << b;
+        prefix += lane_prefix(m) << b;
         total += (uint32_t)__popcll(m) << b;
       }
       uint32_t p = ring_head + prefix;
@@ -691,7 +695,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
 // Wave-aggregated append of up to one ray per lane into a queue: one atomic
 // per wave.  Returns the slot of this lane (valid only if `want`).
 __device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter, uint32_t lane,
-                                                uint64_t lanes_below, uint64_t& mask) {
+                                                uint64_t& mask) {
   mask = __ballot(want);
   const uint32_t total = (uint32_t)__popcll(mask);
   uint32_t base = 0;
@@ -699,7 +703,7 @@ __device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter, ui
     if (lane == 0) base = atomicAdd(counter, total);
     base = __shfl(base, 0);
   }
-  return base + (uint32_t)__popcll(mask & lanes_below);
+  return base + lane_prefix(mask);
 }
 
 __device__ __forceinline__ void put_ray(const QueueView& q, uint32_t slot, float ox, float oy, float oz,
@@ -715,7 +719,6 @@ __device__ __forceinline__ void put_ray(const QueueView& q, uint32_t slot, float
 // indices; masked primaries are skipped; the rest are appended to queue 0.
 __global__ void __launch_bounds__(kBlock) k_raygen(LevelArgs A) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
   for (uint32_t base = wave * 64u; base < A.n_first; base += n_waves * 64u) {
@@ -750,7 +753,7 @@ __global__ void __launch_bounds__(kBlock) k_raygen(LevelArgs A) {
     uint32_t slot = gp;  // no mask: primary gp sits at slot gp (count preset)
     if (A.masked) {
       uint64_t mask;
-      slot = wave_append(active, A.counters + kCtrCount, lane, lanes_below, mask);
+      slot = wave_append(active, A.counters + kCtrCount, lane, mask);
     }
     if (active && slot < A.cap)
       put_ray(A.out, slot, ox, oy, oz, 0.0f, dx, dy, dz, g, E, pid, 0xffffffffu,
@@ -1001,7 +1004,6 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
   __shared__ uint32_t s_base, s_abase;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wid = threadIdx.x >> 6;
-  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
   const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
   for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
     h_key[i] = kHashEmpty;
@@ -1072,7 +1074,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
     }
     __syncthreads();  // s_cnt / s_base are rewritten by the next iteration
     if (kAirPath && o.has_air) {
-      const uint32_t slot = oa + (uint32_t)__popcll(ma & lanes_below);
+      const uint32_t slot = oa + lane_prefix(ma);
       if (slot < A.shq_cap) {
         A.shq.a[slot] = make_float4(o.aox, o.aoy, o.aoz, o.adist);
         A.shq.b[slot] = make_float4(o.asx, o.asy, o.asz, __uint_as_float(o.aslot));
@@ -1082,7 +1084,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
       }
     }
     if (has_r) {
-      const uint32_t slot = ob + (uint32_t)__popcll(mr & lanes_below);
+      const uint32_t slot = ob + lane_prefix(mr);
       if (slot < A.cap)
         put_ray(A.out, slot, o.rox, o.roy, o.roz, o.range, o.rdx, o.rdy, o.rdz, o.g, o.e_refl, o.pid,
                 (uint32_t)o.hit, o.r_meta);
@@ -1090,7 +1092,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
         atomicOr(A.counters + kCtrOverflow, 1u);
     }
     if (has_t) {
-      const uint32_t slot = ob + nr + (uint32_t)__popcll(mt & lanes_below);
+      const uint32_t slot = ob + nr + lane_prefix(mt);
       if (slot < A.cap)
         put_ray(A.out, slot, o.tox, o.toy, o.toz, o.range, o.tdx, o.tdy, o.tdz, o.g, o.e_refr, o.pid,
                 (uint32_t)o.hit, o.t_meta);
@@ -1131,7 +1133,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
-  const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
   const uint32_t n_in = min(A.counters[kCtrCount], A.cap);
   uint32_t* cursor = A.counters + kCtrWork;
   const Node4* __restrict__ nodes = A.nodes;
@@ -1194,7 +1195,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
     uint64_t idle = __ballot(!valid);
     if (pool_n > 0 && idle) {
       const uint32_t take = min((uint32_t)__popcll(idle), pool_n);
-      const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+      const uint32_t rank = lane_prefix(idle);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       if (!valid && rank < take) {
         const float4* e = pool + (size_t)(pool_n - 1u - rank) * 4u;
@@ -1221,7 +1222,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
           }
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
-        const uint32_t rank = (uint32_t)__popcll(idle & lanes_below);
+        const uint32_t rank = lane_prefix(idle);
         if (!valid && rank < take) {
           const uint32_t my = pool_next + rank;
           start_ray(A.in.a[my], A.in.b[my], A.in.c[my], A.in.m[my]);
@@ -1265,7 +1266,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
       const uint32_t nr = (uint32_t)__popcll(mr), nt = (uint32_t)__popcll(mt);
       if (pool_n + nr + nt <= A.wq_pool) {
         if (take && o.has_r) {
-          float4* e = pool + (size_t)(pool_n + (uint32_t)__popcll(mr & lanes_below)) * 4u;
+          float4* e = pool + (size_t)(pool_n + lane_prefix(mr)) * 4u;
           e[0] = make_float4(o.rox, o.roy, o.roz, o.range);
           e[1] = make_float4(o.rdx, o.rdy, o.rdz, o.g);
           reinterpret_cast<uint4*>(e)[2] = make_uint4((uint32_t)__double2loint(o.e_refl),
@@ -1273,7 +1274,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
           reinterpret_cast<uint4*>(e)[3] = make_uint4(o.r_meta, 0u, 0u, 0u);
         }
         if (take && o.has_t) {
-          float4* e = pool + (size_t)(pool_n + nr + (uint32_t)__popcll(mt & lanes_below)) * 4u;
+          float4* e = pool + (size_t)(pool_n + nr + lane_prefix(mt)) * 4u;
           e[0] = make_float4(o.tox, o.toy, o.toz, o.range);
           e[1] = make_float4(o.tdx, o.tdy, o.tdz, o.g);
           reinterpret_cast<uint4*>(e)[2] = make_uint4((uint32_t)__double2loint(o.e_refr),
@@ -1399,7 +1400,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
         const bool want = (leaves >> j) & 1u;
         const uint64_t m = __ballot(want);
         if (want) {
-          const uint32_t p = ring_head + (uint32_t)__popcll(m & lanes_below);
+          const uint32_t p = ring_head + lane_prefix(m);
           lds_leaf[wib][p & (kLeafRing - 1u)] = (uint32_t)lref[j];
           lds_own[wib][p & (kLeafRing - 1u)] = (uint8_t)lane;
           last_pos = p + 1u;
@@ -1414,7 +1415,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
     const uint64_t fm = __ballot(fin);
     if (fin) {
       const unsigned long long bst = lds_best[threadIdx.x];
-      float4* e = hring + (size_t)((hit_head + (uint32_t)__popcll(fm & lanes_below)) & (A.wq_hits - 1u)) * 4u;
+      float4* e = hring + (size_t)((hit_head + lane_prefix(fm)) & (A.wq_hits - 1u)) * 4u;
       e[0] = make_float4(ox, oy, oz, ray_L);
       e[1] = make_float4(dx, dy, dz, ray_g);
       reinterpret_cast<uint4*>(e)[2] = ray_c;

@@ -127,9 +127,34 @@ def test_host_bvh_wide_and_split(R, width, leaf, split, merge):
         sc.release()
 
 
+@pytest.mark.parametrize("collapse,leaf,split,merge", [(1, 2, 0, 1), (2, 2, 0, 1), (2, 1, 0, 1), (2, 4, 0, 1),
+                                                       (2, 2, 50, 1), (2, 4, 0, 2), (1, 4, 0, 2)])
+def test_host_bvh_collapse(R, collapse, leaf, split, merge):
+    """Greedy (1) and cost-optimal (2) four-wide collapses, with leaves formed
+    by the collapse or by the binary build, with and without split
+    references, find the brute-force closest hit; the default is the
+    cost-optimal tree."""
+    for s, n in ((W.tiny_room(), 4000), (W.thin_pillars_scene(), 4000), (W.urban_block(), 1000)):
+        sc = R.Scene(None, s.vertices, s.indices, s.tri_material, max_leaf_size=leaf, split_pct=split,
+                     merge_leaves=merge, collapse=collapse)
+        info = sc.info()
+        assert info["n_tris"] == s.n_tris and info["n_nodes"] > 0 and info["max_stack"] <= 96
+        assert sc.selfcheck(n, 17) == 0
+        sc.release()
+    s = W.urban_block()
+    infos = []
+    for c in (0, 2):
+        sc = R.Scene(None, s.vertices, s.indices, s.tri_material, max_leaf_size=leaf, split_pct=split,
+                     merge_leaves=merge, collapse=c)
+        infos.append(sc.info())
+        sc.release()
+    assert infos[0]["n_nodes"] == infos[1]["n_nodes"] and infos[0]["sah_cost"] == infos[1]["sah_cost"]
+
+
 def test_bvh_option_validation(R):
     s = W.tiny_room()
     for bad in (dict(width=6), dict(width=8, max_leaf_size=5), dict(split_pct=201), dict(merge_leaves=3),
+                dict(collapse=3),
                 dict(builder=2), dict(builder=1), dict(builder=1, width=8, max_leaf_size=2)):
         with pytest.raises(R.RadarError) as e:
             R.Scene(None, s.vertices, s.indices, s.tri_material, **bad)
@@ -150,8 +175,8 @@ def test_deep_median_fallback_bounds_depth(R):
     V[2::3, 0] = xs
     V[2::3, 2] = 0.5
     F = np.arange(3 * n, dtype=np.uint32).reshape(n, 3)
-    for width in (4, 8):
-        sc = R.Scene(None, V, F, np.zeros(n, np.uint16), max_leaf_size=1, width=width)
+    for width, collapse in ((4, 1), (4, 2), (8, 0)):
+        sc = R.Scene(None, V, F, np.zeros(n, np.uint16), max_leaf_size=1, width=width, collapse=collapse)
         assert sc.info()["max_stack"] <= (96 if width == 4 else 44)
         assert sc.selfcheck(3000, 11) == 0
         sc.release()

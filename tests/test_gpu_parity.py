@@ -275,8 +275,10 @@ def test_fused_launch_equals_levels(R, ctx):
 
 
 def test_eight_wide_equals_four_wide(R, ctx):
-    """The eight-wide tree (octant-ordered node groups) finds the same closest
-    hits as the four-wide one: records, accumulator and image bit for bit."""
+    """The eight-wide tree (octant-ordered node groups) and the four-wide tree
+    of the greedy collapse find the same closest hits as the default
+    four-wide tree (cost-optimal collapse): records, accumulator and image
+    bit for bit."""
     import torch
     s, u = W.tiny_room(), W.urban_block()
     cases = [(s, s.params, s.pose),
@@ -284,19 +286,20 @@ def test_eight_wide_equals_four_wide(R, ctx):
              (u, dict(u.params, n_azimuth=40), u.pose)]
     for scene, p, pose in cases:
         outs = []
-        for width in (4, 8):
-            sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material, width=width)
+        for opts in (dict(width=4), dict(width=8), dict(width=4, collapse=1)):
+            sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material, **opts)
             try:
                 o = R.rr_radar_scan_records(ctx.handle, sc.handle, pose, p, scene.materials)
                 torch.cuda.synchronize()
                 outs.append(o)
             finally:
                 sc.release()
-        a, b = outs
-        assert torch.equal(a["records"], b["records"])
-        assert torch.equal(a["accum"], b["accum"])
-        assert torch.equal(a["image"], b["image"])
-        assert a["stats"]["rays_per_depth"] == b["stats"]["rays_per_depth"]
+        a = outs[0]
+        for b in outs[1:]:
+            assert torch.equal(a["records"], b["records"])
+            assert torch.equal(a["accum"], b["accum"])
+            assert torch.equal(a["image"], b["image"])
+            assert a["stats"]["rays_per_depth"] == b["stats"]["rays_per_depth"]
 
 
 def test_workspace_variant_matches(R, ctx):
