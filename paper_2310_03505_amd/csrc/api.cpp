@@ -410,8 +410,9 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     uint64_t tblocks = (level_bound + kTraceBlock - 1) / kTraceBlock;
     uint32_t tgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
     if ((rs = timed_launch(1, d, [&] { return launch_trace(a, tgrid, st); }))) return rs;
-    uint64_t sblocks = (level_bound + kBlock - 1) / kBlock;
-    uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), (uint64_t)ctx->n_cu * 12u);
+    const uint32_t sb = (uint32_t)shade_block(a.air);
+    uint64_t sblocks = (level_bound + sb - 1) / sb;
+    uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), (uint64_t)ctx->n_cu * (12u * 256u / sb));
     if ((rs = timed_launch(2, d, [&] { return launch_shade(a, sgrid, st); }))) return rs;
     level_bound = std::min<uint64_t>(level_bound * 2, L.cap);
   }

@@ -89,6 +89,11 @@ constexpr int kProfMaxVisits = kProfTailActive + 8;
 constexpr int kProfPoolMax = kProfMaxVisits + 8;  // fused scan: largest child pool of a wave
 constexpr int kProfWords = kProfPoolMax + 1;
 constexpr int kBlock = 256;
+// shade: lanes per block (one queue reservation per block step); the air-path
+// variant holds twice the registers and keeps two blocks per CU with 256
+constexpr int kShadeBlock = 512;
+constexpr int kShadeBlockAir = 256;
+constexpr int shade_block(bool air) { return air ? kShadeBlockAir : kShadeBlock; }
 constexpr uint32_t kMaxLevels = 8;   // bounce levels (interactions per path) at most
 constexpr uint32_t kLeafRing = 512;
 constexpr uint32_t kNodeSteps = 4;   // four-wide trace: node steps per refill/triangle decision at most

@@ -993,36 +993,42 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
 // Fresnel split, the retrace return through the beam window of the standard
 // BRDF, range binning (Sec. III-B) and the two children.
 template <bool kCount, bool kAirPath>
-__global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
+__global__ void __launch_bounds__(shade_block(kAirPath)) k_shade(LevelArgs A) {
+  constexpr int kShadeLanes = shade_block(kAirPath);
   // returns of the block's rays are summed in an LDS hash table keyed by
   // accumulator cell and flushed with one global atomic per cell at the end;
   // the block works on a contiguous range of the level, whose rays mostly
   // share azimuths and so few cells
   __shared__ uint32_t h_key[kHashSlots];
   __shared__ unsigned long long h_val[kHashSlots];
-  __shared__ uint32_t s_cnt[kBlock / 64][3];
-  __shared__ uint32_t s_base, s_abase;
+  // per-wave child counts and the block's queue bases, double-buffered by
+  // block step so that one step's readers never race the next step's writers
+  __shared__ uint32_t s_cnt[2][kShadeLanes / 64][3];
+  __shared__ uint32_t s_base[2], s_abase[2];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wid = threadIdx.x >> 6;
   const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
-  for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock) {
+  for (uint32_t i = threadIdx.x; i < kHashSlots; i += kShadeLanes) {
     h_key[i] = kHashEmpty;
     h_val[i] = 0ull;
   }
   __syncthreads();
-  const uint32_t per_block = ((n_in + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+  const uint32_t per_block = ((n_in + gridDim.x - 1) / gridDim.x + kShadeLanes - 1) / kShadeLanes * kShadeLanes;
   const uint32_t begin = min(blockIdx.x * per_block, n_in);
   const uint32_t end = min(begin + per_block, n_in);
   uint32_t cnt_hits = 0;
-  for (uint32_t base = begin; base < end; base += kBlock) {
+  uint32_t par = 0;
+  for (uint32_t base = begin; base < end; base += kShadeLanes, par ^= 1u) {
     const uint32_t idx = base + threadIdx.x;
     const bool active = idx < end;
     Shaded o;
     if (active) {
       const uint2 h = A.hits[idx];
       const int32_t hit = (int32_t)h.y;
-      const float4 a = hit >= 0 ? A.in.a[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      const float4 b = hit >= 0 ? A.in.b[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      // loaded whether or not the ray hit, so these loads do not wait for the
+      // hit record
+      const float4 a = A.in.a[idx];
+      const float4 b = A.in.b[idx];
       shade_hit<kAirPath>(A, a, b, A.in.c[idx], A.in.m[idx], h.x, hit, o);
       if (kCount && hit >= 0) ++cnt_hits;
     }
@@ -1052,27 +1058,28 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
     const uint32_t nr = (uint32_t)__popcll(mr);
     const uint32_t nt = (uint32_t)__popcll(mt);
     if (lane == 0) {
-      s_cnt[wid][0] = nr;
-      s_cnt[wid][1] = nt;
-      s_cnt[wid][2] = (uint32_t)__popcll(ma);
+      s_cnt[par][wid][0] = nr;
+      s_cnt[par][wid][1] = nt;
+      s_cnt[par][wid][2] = (uint32_t)__popcll(ma);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t total = 0, total_a = 0;
-      for (uint32_t w = 0; w < kBlock / 64; ++w) {
-        total += s_cnt[w][0] + s_cnt[w][1];
-        total_a += s_cnt[w][2];
+      for (uint32_t w = 0; w < kShadeLanes / 64; ++w) {
+        total += s_cnt[par][w][0] + s_cnt[par][w][1];
+        total_a += s_cnt[par][w][2];
       }
-      s_base = total ? atomicAdd(A.counters + kCtrCount + A.depth + 1, total) : 0u;
-      if (kAirPath) s_abase = total_a ? atomicAdd(A.counters + kCtrShadow, total_a) : 0u;
+      s_base[par] = total ? atomicAdd(A.counters + kCtrCount + A.depth + 1, total) : 0u;
+      if (kAirPath) s_abase[par] = total_a ? atomicAdd(A.counters + kCtrShadow, total_a) : 0u;
     }
     __syncthreads();
-    uint32_t ob = s_base, oa = kAirPath ? s_abase : 0u;
+    // buffer `par` is written again two steps on, after every wave has passed
+    // the next step's first barrier, so no third barrier is needed here
+    uint32_t ob = s_base[par], oa = kAirPath ? s_abase[par] : 0u;
     for (uint32_t w = 0; w < wid; ++w) {
-      ob += s_cnt[w][0] + s_cnt[w][1];
-      if (kAirPath) oa += s_cnt[w][2];
+      ob += s_cnt[par][w][0] + s_cnt[par][w][1];
+      if (kAirPath) oa += s_cnt[par][w][2];
     }
-    __syncthreads();  // s_cnt / s_base are rewritten by the next iteration
     if (kAirPath && o.has_air) {
       const uint32_t slot = oa + lane_prefix(ma);
       if (slot < A.shq_cap) {
@@ -1102,7 +1109,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(LevelArgs A) {
   }
   // ---- flush the table
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < kHashSlots; i += kBlock)
+  for (uint32_t i = threadIdx.x; i < kHashSlots; i += kShadeLanes)
     if (h_key[i] != kHashEmpty) atomicAdd(A.acc + h_key[i], h_val[i]);
   if (kCount) atomicAdd(A.prof + 3, (unsigned long long)cnt_hits);
 }
@@ -1565,7 +1572,7 @@ hipError_t launch_scan(const LevelArgs& a, uint32_t grid, hipStream_t st) {
 }
 
 hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st) {
-  const dim3 g(grid ? grid : 1), b(kBlock);
+  const dim3 g(grid ? grid : 1), b(shade_block(a.air));
   if (a.air) {
     if (a.prof)
       hipLaunchKernelGGL((k_shade<true, true>), g, b, 0, st, a);
