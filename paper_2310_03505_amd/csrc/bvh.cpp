@@ -111,17 +111,21 @@ struct BNode {
   std::unique_ptr<BNode> l, r;
   uint32_t begin = 0, count = 0;  // leaf range in the ref array
   uint32_t span = 0;              // references below an inner node (from begin)
-  // four-wide collapse plan (cost-optimal mode): cover[j] is the least
-  // expected cost of the subtree as at most j entries of a wide node; the
-  // subtree is one entry if cl[j] == 0, else its left child takes cl[j]
-  // entries and its right child cr[j].  As a wide node of its own, the left
-  // child takes wide_l of the four entries; as one entry it is a leaf if
-  // as_leaf.
-  double cover[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  uint8_t cl[5] = {0, 0, 0, 0, 0}, cr[5] = {0, 0, 0, 0, 0};
+  uint32_t plan = 0;              // cost-optimal collapse: index of the node's Plan
+  bool leaf() const { return !l; }
+};
+
+// Four-wide collapse plan of one build node (cost-optimal mode): cover[j-1]
+// is the least expected cost of the subtree as at most j entries of a wide
+// node; the subtree is one entry if cl[j-1] == 0, else its left child takes
+// cl[j-1] entries and its right child cr[j-1].  As a wide node of its own,
+// the left child takes wide_l of the four entries; as one entry it is a leaf
+// if as_leaf.
+struct Plan {
+  float cover[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  uint8_t cl[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0};
   uint8_t wide_l = 2;
   bool as_leaf = false;
-  bool leaf() const { return !l; }
 };
 
 struct Builder {
@@ -264,66 +268,73 @@ struct Flattener4 {
   double root_area;
   uint32_t leaf_max = 0;  // > 0: a subtree with at most this many references becomes one leaf
   bool optimal = true;    // cost-optimal collapse (else greedy)
+  std::vector<Plan> plans;  // cost-optimal collapse: one per build node
 
   static uint32_t refs_of(const BNode* k) { return k->leaf() ? k->count : k->span; }
   bool is_leaf(const BNode* k) const {
-    if (optimal) return k->leaf() || k->as_leaf;
+    if (optimal) return k->leaf() || plans[k->plan].as_leaf;
     return k->leaf() || (leaf_max && k->span <= leaf_max);
   }
 
-  // bottom-up cover costs of the cost-optimal collapse
+  // bottom-up cover costs of the cost-optimal collapse (costs in float: only
+  // their order matters)
   void plan(BNode* n) {
-    const double area = n->box.empty() ? 0.0 : n->box.area();
+    n->plan = (uint32_t)plans.size();
+    plans.emplace_back();
+    const float area = n->box.empty() ? 0.0f : n->box.area();
     if (n->leaf()) {
-      const double c = kLeafRefCost * (double)n->count * area;
-      for (int j = 1; j <= 4; ++j) {
-        n->cover[j] = c;
-        n->cl[j] = n->cr[j] = 0;
-      }
-      n->as_leaf = true;
+      Plan& P = plans[n->plan];
+      const float c = (float)kLeafRefCost * (float)n->count * area;
+      for (int j = 0; j < 4; ++j) P.cover[j] = c;
+      P.as_leaf = true;
       return;
     }
     BNode* l = n->l.get();
     BNode* r = n->r.get();
     plan(l);
     plan(r);
+    const Plan& L = plans[l->plan];
+    const Plan& Rr = plans[r->plan];
+    Plan P;
     // as a wide node: the two children share its four entries
-    double wide = INFINITY;
+    float wide = INFINITY;
     for (int k = 1; k <= 3; ++k) {
-      const double c = l->cover[k] + r->cover[4 - k];
+      const float c = L.cover[k - 1] + Rr.cover[4 - k - 1];
       if (c < wide) {
         wide = c;
-        n->wide_l = (uint8_t)k;
+        P.wide_l = (uint8_t)k;
       }
     }
-    wide += kWideNodeCost * area;
-    const double as_leaf = (leaf_max && n->span <= leaf_max) ? kLeafRefCost * (double)n->span * area : INFINITY;
-    n->as_leaf = as_leaf <= wide;
-    n->cover[1] = std::min(as_leaf, wide);
-    n->cl[1] = n->cr[1] = 0;
+    wide += (float)kWideNodeCost * area;
+    const float as_leaf =
+        (leaf_max && n->span <= leaf_max) ? (float)kLeafRefCost * (float)n->span * area : INFINITY;
+    P.as_leaf = as_leaf <= wide;
+    P.cover[0] = std::min(as_leaf, wide);
     for (int j = 2; j <= 4; ++j) {
-      n->cover[j] = n->cover[j - 1];
-      n->cl[j] = n->cl[j - 1];
-      n->cr[j] = n->cr[j - 1];
+      P.cover[j - 1] = P.cover[j - 2];
+      P.cl[j - 1] = P.cl[j - 2];
+      P.cr[j - 1] = P.cr[j - 2];
       for (int k = 1; k < j; ++k) {
-        const double c = l->cover[k] + r->cover[j - k];
-        if (c < n->cover[j]) {
-          n->cover[j] = c;
-          n->cl[j] = (uint8_t)k;
-          n->cr[j] = (uint8_t)(j - k);
+        const float c = L.cover[k - 1] + Rr.cover[j - k - 1];
+        if (c < P.cover[j - 1]) {
+          P.cover[j - 1] = c;
+          P.cl[j - 1] = (uint8_t)k;
+          P.cr[j - 1] = (uint8_t)(j - k);
         }
       }
     }
+    plans[n->plan] = P;
   }
 
   // the entries of a subtree covered by at most j entries, in order
-  static void gather(const BNode* n, int j, std::vector<const BNode*>& kids) {
-    if (n->cl[j] == 0) {
+  void gather(const BNode* n, int j, std::vector<const BNode*>& kids) const {
+    const Plan& P = plans[n->plan];
+    if (P.cl[j - 1] == 0) {
       kids.push_back(n);
       return;
     }
-    gather(n->l.get(), n->cl[j], kids);
-    gather(n->r.get(), n->cr[j], kids);
+    gather(n->l.get(), P.cl[j - 1], kids);
+    gather(n->r.get(), P.cr[j - 1], kids);
   }
 
   static void quantise_axis(float lo, float hi, float& origin, uint32_t& ebyte) {
@@ -369,8 +380,9 @@ struct Flattener4 {
   uint32_t emit(const BNode* b, uint32_t depth, int32_t* ref_out) {
     std::vector<const BNode*> kids;
     if (optimal) {
-      gather(b->l.get(), b->wide_l, kids);
-      gather(b->r.get(), 4 - b->wide_l, kids);
+      const uint8_t wl = plans[b->plan].wide_l;
+      gather(b->l.get(), wl, kids);
+      gather(b->r.get(), 4 - wl, kids);
     } else {
       kids = {b->l.get(), b->r.get()};
     }
@@ -781,7 +793,10 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
   } else {
     Flattener4 fl{refs, tri3, aux0, out, out.pad, root->box.empty() ? 0.0 : root->box.area(),
                   merge ? std::max(1u, opt.max_leaf) : 0u, opt.collapse != 1};
-    if (fl.optimal) fl.plan(root.get());
+    if (fl.optimal) {
+      fl.plans.reserve(2 * (size_t)n + 2);
+      fl.plan(root.get());
+    }
     int32_t root_ref;
     out.max_stack = fl.emit(root.get(), 0, &root_ref);
   }
