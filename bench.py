@@ -38,11 +38,11 @@ HBM_PEAK_GBS = 8000.0
 # plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
 # all of them).  Valid only for the kernel sources it was taken on.
 TRACE_HBM = {
-    "urban_block_200k": dict(fetch_kib=56134.2, write_kib=21515.0),
-    "urban_block_200k_air": dict(fetch_kib=54308.9, write_kib=21010.4),
+    "urban_block_200k": dict(fetch_kib=56040.1, write_kib=22138.9),
+    "urban_block_200k_air": dict(fetch_kib=54479.5, write_kib=21652.1),
 }
 TRACE_HBM_SCALE = dict(fetch_scale=2.0, write_scale=1.0,
-                       sources_sha256="f9fb2023895897da09804884c4cc96f8c95eff0eedb6ea5314ea46ec1273850a")
+                       sources_sha256="e63cbe0d762176cc04310a042b4cf2a4ecb6b203be7bc2fea1bda6988aef3a20")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
