@@ -38,11 +38,11 @@ HBM_PEAK_GBS = 8000.0
 # plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
 # all of them).  Valid only for the kernel sources it was taken on.
 TRACE_HBM = {
-    "urban_block_200k": dict(fetch_kib=56040.1, write_kib=22138.9),
-    "urban_block_200k_air": dict(fetch_kib=54479.5, write_kib=21652.1),
+    "urban_block_200k": dict(fetch_kib=55138.8, write_kib=24516.2),
+    "urban_block_200k_air": dict(fetch_kib=55674.3, write_kib=24796.6),
 }
 TRACE_HBM_SCALE = dict(fetch_scale=2.0, write_scale=1.0,
-                       sources_sha256="e63cbe0d762176cc04310a042b4cf2a4ecb6b203be7bc2fea1bda6988aef3a20")
+                       sources_sha256="5160a3fa39e886a41535e005882e4ca4e2e995211140933a63d8bec9e9951bfd")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
@@ -222,7 +222,7 @@ POST_BYTES_PER_PIXEL = 9   # float32 energy read, float32 dB and 8-bit pixel wri
 # same two rocprofv3 --pmc passes and copy-kernel scale as the trace kernel's
 POST_HBM = dict(workload="polar_epilogue_64x400x3776", fetch_kib=198520.1, write_kib=472000.0,
                 fetch_scale=2.0, write_scale=1.0,
-                sources_sha256="f1b4d1b309689b6062387408831c57132e67e0128da69f3c5e5685a17ae3ec0c")
+                sources_sha256="2525117f83383f7ff623215308e43a43db333af84faddc5aaa3590b3688fd44c")
 POST_SOURCES = ("post.hip", "post.h", "philox.h", "rr_internal.h")
 POST_FULL = dict(blur_sigma_bins=2.0, uniform_amp=1e-7, perlin_amp=1e-6, perlin_cell_az=16.0,
                  perlin_cell_bins=64.0, seed=12345, scan_id=0)

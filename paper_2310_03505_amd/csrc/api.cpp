@@ -439,9 +439,9 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   if (accum_out)
     HIP_TRY(ctx, hipMemcpyAsync(accum_out, d_acc, 8 * L.acc_cells, hipMemcpyDeviceToDevice, st));
   if (counters_host)
-    HIP_TRY(ctx, hipMemcpyAsync(counters_host, d_ctr, 4 * kCtrWords, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(counters_host, d_ctr, 4 * kCtrHostWords, hipMemcpyDeviceToHost, st));
   if (stats) {
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctr, d_ctr, 4 * kCtrWords, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctr, d_ctr, 4 * kCtrHostWords, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     std::memset(stats, 0, sizeof *stats);
     for (uint32_t d = 0; d < RR_MAX_BOUNCES; ++d) {
@@ -567,7 +567,7 @@ rr_status rr_create(int device, rr_context** out) {
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
     c->n_cu = cu;
   void* p = nullptr;
-  e = hipHostMalloc(&p, 4 * kCtrWords, hipHostMallocDefault);
+  e = hipHostMalloc(&p, 4 * kCtrHostWords, hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
     return fail(nullptr, RR_ENOMEM, "pinned host buffer: %s", hipGetErrorString(e));

@@ -176,6 +176,11 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
 
   bool valid = false, exhausted = false;
   uint32_t pool_next = 0, pool_end = 0;  // wave-uniform: claimed, not yet started rays
+  // closest-hit levels: the queue is claimed in kCtrSegs segments, each with
+  // its own cursor (one cursor serialised every wave's claims); a wave starts
+  // at its block's segment and moves on to the next once that one is used up
+  uint32_t seg = blockIdx.x & (kCtrSegs - 1u), seg_tries = 0;
+  uint32_t* const seg_cur = A.counters + kCtrCursor + A.depth * kCtrSegs * kCtrCursorStride;
   uint32_t ring_head = 0, ring_tail = 0;  // wave-uniform: appended / tested ring entries
   uint32_t ridx = 0, visits = 0, excl = 0xffffffffu, last_pos = 0;
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0;
@@ -195,14 +200,36 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
 #pragma unroll 1
       for (int pass = 0; pass < 2 && idle; ++pass) {
         if (pool_next >= pool_end) {
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(cursor, A.pool);
-          base = __shfl(base, 0);
-          pool_next = base;
-          pool_end = min(base + A.pool, n_in);
-          if (base >= n_in) {
-            exhausted = true;
-            break;
+          if constexpr (kShadow) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(cursor, A.pool);
+            base = __shfl(base, 0);
+            pool_next = base;
+            pool_end = min(base + A.pool, n_in);
+            if (base >= n_in) {
+              exhausted = true;
+              break;
+            }
+          } else {
+#pragma unroll 1
+            for (;;) {
+              const uint32_t s0 = (uint32_t)((uint64_t)n_in * seg / kCtrSegs);
+              const uint32_t s1 = (uint32_t)((uint64_t)n_in * (seg + 1u) / kCtrSegs);
+              uint32_t base = 0;
+              if (lane == 0) base = atomicAdd(seg_cur + seg * kCtrCursorStride, A.pool);
+              base = __shfl(base, 0);
+              if (base < s1 - s0) {
+                pool_next = s0 + base;
+                pool_end = min(pool_next + A.pool, s1);
+                break;
+              }
+              if (++seg_tries >= kCtrSegs) {
+                exhausted = true;
+                break;
+              }
+              seg = (seg + 1u) & (kCtrSegs - 1u);
+            }
+            if (exhausted) break;
           }
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
@@ -244,7 +271,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         }
         pool_next += take;
         idle = __ballot(!valid);
-        if (pool_next >= pool_end && pool_end >= n_in) exhausted = true;
+        if (kShadow && pool_next >= pool_end && pool_end >= n_in) exhausted = true;
       }
     }
     const uint64_t live = __ballot(valid);
@@ -1522,7 +1549,7 @@ hipError_t put_blob(void* dst, const void* src, size_t bytes, hipStream_t st) {
 hipError_t launch_clear(unsigned long long* acc, size_t n_acc, uint32_t* counters, uint32_t count0,
                         hipStream_t st) {
   size_t blocks = (n_acc + 255) / 256;
-  if (blocks < 1) blocks = 1;
+  if (blocks < (size_t)(kCtrWords + 255) / 256) blocks = (size_t)(kCtrWords + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, acc, n_acc, counters, count0);
   return hipGetLastError();

@@ -216,7 +216,7 @@ rr_status rr_server_create(rr_context* ctx, const rr_scene* scene, const rr_mate
     sl.srv = s;
     void* p = nullptr;
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc(&p, 4 * kCtrWords, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&p, 4 * kCtrHostWords, hipHostMallocDefault) != hipSuccess) {
       for (auto& q : s->slots) {
         if (q.stream) (void)hipStreamDestroy(q.stream);
         if (q.h_ctr) (void)hipHostFree(q.h_ctr);
@@ -225,7 +225,7 @@ rr_status rr_server_create(rr_context* ctx, const rr_scene* scene, const rr_mate
       return fail(ctx, RR_EDEVICE, "server streams / pinned buffers");
     }
     sl.h_ctr = static_cast<uint32_t*>(p);
-    std::memset(sl.h_ctr, 0, 4 * kCtrWords);
+    std::memset(sl.h_ctr, 0, 4 * kCtrHostWords);
   }
   s->worker = std::thread(dispatcher, s);
   *out = s;
