@@ -167,7 +167,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
   const uint32_t n_in = kShadow ? min(A.counters[kCtrShadow], A.shq_cap) : min(A.counters[kCtrCount + A.depth], A.cap);
-  uint32_t* cursor = kShadow ? A.counters + kCtrShadowWork : A.counters + kCtrWork + A.depth;
   const Node4* __restrict__ nodes = A.nodes;
   const float4* __restrict__ tris = A.tris;
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,11 +175,14 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
 
   bool valid = false, exhausted = false;
   uint32_t pool_next = 0, pool_end = 0;  // wave-uniform: claimed, not yet started rays
-  // closest-hit levels: the queue is claimed in kCtrSegs segments, each with
-  // its own cursor (one cursor serialised every wave's claims); a wave starts
-  // at its block's segment and moves on to the next once that one is used up
+  // the queue is claimed in kCtrSegs segments, each with its own cursor (one
+  // cursor serialised every wave's claims); a wave starts at its block's
+  // segment and moves on to the next once that one is used up.  Closest-hit
+  // levels use cursor set `depth`, the visibility launch the set after the
+  // last level's.
   uint32_t seg = blockIdx.x & (kCtrSegs - 1u), seg_tries = 0;
-  uint32_t* const seg_cur = A.counters + kCtrCursor + A.depth * kCtrSegs * kCtrCursorStride;
+  uint32_t* const seg_cur =
+      A.counters + kCtrCursor + (kShadow ? kMaxLevels : A.depth) * kCtrSegs * kCtrCursorStride;
   uint32_t ring_head = 0, ring_tail = 0;  // wave-uniform: appended / tested ring entries
   uint32_t ridx = 0, visits = 0, excl = 0xffffffffu, last_pos = 0;
   float ox = 0, oy = 0, oz = 0, dx = 0, dy = 0, dz = 0, best_t = 0;
@@ -195,42 +197,31 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   for (;;) {
     // ---- refill idle lanes (wave-uniform decision) from the wave's pool of
     // claimed rays; the pool is refilled A.pool rays at a time with one atomic
+    // on a segment cursor
     uint64_t idle = __ballot(!valid);
     if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
 #pragma unroll 1
       for (int pass = 0; pass < 2 && idle; ++pass) {
         if (pool_next >= pool_end) {
-          if constexpr (kShadow) {
+#pragma unroll 1
+          for (;;) {
+            const uint32_t s0 = (uint32_t)((uint64_t)n_in * seg / kCtrSegs);
+            const uint32_t s1 = (uint32_t)((uint64_t)n_in * (seg + 1u) / kCtrSegs);
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(cursor, A.pool);
+            if (lane == 0) base = atomicAdd(seg_cur + seg * kCtrCursorStride, A.pool);
             base = __shfl(base, 0);
-            pool_next = base;
-            pool_end = min(base + A.pool, n_in);
-            if (base >= n_in) {
+            if (base < s1 - s0) {
+              pool_next = s0 + base;
+              pool_end = min(pool_next + A.pool, s1);
+              break;
+            }
+            if (++seg_tries >= kCtrSegs) {
               exhausted = true;
               break;
             }
-          } else {
-#pragma unroll 1
-            for (;;) {
-              const uint32_t s0 = (uint32_t)((uint64_t)n_in * seg / kCtrSegs);
-              const uint32_t s1 = (uint32_t)((uint64_t)n_in * (seg + 1u) / kCtrSegs);
-              uint32_t base = 0;
-              if (lane == 0) base = atomicAdd(seg_cur + seg * kCtrCursorStride, A.pool);
-              base = __shfl(base, 0);
-              if (base < s1 - s0) {
-                pool_next = s0 + base;
-                pool_end = min(pool_next + A.pool, s1);
-                break;
-              }
-              if (++seg_tries >= kCtrSegs) {
-                exhausted = true;
-                break;
-              }
-              seg = (seg + 1u) & (kCtrSegs - 1u);
-            }
-            if (exhausted) break;
+            seg = (seg + 1u) & (kCtrSegs - 1u);
           }
+          if (exhausted) break;
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
         const uint32_t rank = lane_prefix(idle);
@@ -271,7 +262,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         }
         pool_next += take;
         idle = __ballot(!valid);
-        if (kShadow && pool_next >= pool_end && pool_end >= n_in) exhausted = true;
       }
     }
     const uint64_t live = __ballot(valid);

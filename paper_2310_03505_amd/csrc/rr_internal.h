@@ -99,21 +99,20 @@ constexpr size_t kRayBytes = 16 + 16 + 16 + 4;
 
 // counters block (uint32): [0..8] rays per depth, [16..24] work cursors (the
 // eight-wide and one-launch traversals), [32] overflow flag, [40] air-path
-// visibility rays of the scan, [48] their work cursor, [64..) the claim
-// cursors of the four-wide traversal's levels; only the first 64 words are
-// read back to the host
+// visibility rays of the scan, [64..) the claim cursors of the four-wide
+// traversal's levels and of the visibility launch; only the first 64 words
+// are read back to the host
 constexpr int kCtrCount = 0;
 constexpr int kCtrWork = 16;
 constexpr int kCtrOverflow = 32;
 constexpr int kCtrShadow = 40;
-constexpr int kCtrShadowWork = 48;
 constexpr int kCtrHostWords = 64;   // the part of the block read back to the host
 // per level, sixteen claim cursors (one per segment of the level's queue),
 // each on its own 128-byte line
 constexpr int kCtrCursor = 64;
 constexpr int kCtrSegs = 16;
 constexpr int kCtrCursorStride = 32;
-constexpr int kCtrWords = kCtrCursor + 8 * kCtrSegs * kCtrCursorStride;  // eight levels at most
+constexpr int kCtrWords = kCtrCursor + 9 * kCtrSegs * kCtrCursorStride;  // eight levels at most, then visibility
 
 // Air-path visibility ray (one per air-path return to test), three arrays:
 //   a = (o.x, o.y, o.z, dist)   offset origin, distance to the sensor
