@@ -1067,7 +1067,7 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   if (!ctx || !t) return fail(ctx, RR_EINVAL, "NULL argument");
-  uint32_t rl = t->refill_lanes ? t->refill_lanes : 16u;
+  uint32_t rl = t->refill_lanes ? t->refill_lanes : 8u;
   uint32_t wc = t->trace_waves_per_cu ? t->trace_waves_per_cu : 20u;
   uint32_t pr = t->pool_rays ? t->pool_rays : 64u;
   if (rl > 64) return fail(ctx, RR_EINVAL, "refill_lanes out of [1, 64]");
@@ -1083,7 +1083,7 @@ rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   if (t->shade_batch > 64) return fail(ctx, RR_EINVAL, "shade_batch out of [1, 64]");
   ctx->fused = t->fused == 1 ? 1u : 0u;
   ctx->shade_batch = t->shade_batch ? t->shade_batch : 64u;
-  ctx->tri_batch = t->tri_batch ? t->tri_batch : 32u;
+  ctx->tri_batch = t->tri_batch ? t->tri_batch : 16u;
   return RR_OK;
 }
 

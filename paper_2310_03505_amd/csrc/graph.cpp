@@ -216,7 +216,7 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   static const uint32_t kRefill[] = {4, 8, 12, 16, 24, 32, 48};
   static const uint32_t kWaves[] = {8, 12, 16, 20, 24, 32};
   static const uint32_t kPool[] = {64, 128, 256};
-  static const uint32_t kTriBatch[] = {16, 32, 48, 64};
+  static const uint32_t kTriBatch[] = {8, 16, 32, 48, 64};
   static const uint32_t kFused[] = {1, 2};  // one launch per scan, one per level
   static const uint32_t kShadeBatch[] = {16, 32, 64};
   struct Axis {
@@ -226,7 +226,7 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   } axes[] = {{kRefill, 7, &rr_tuning::refill_lanes},
               {kWaves, 6, &rr_tuning::trace_waves_per_cu},
               {kPool, 3, &rr_tuning::pool_rays},
-              {kTriBatch, 4, &rr_tuning::tri_batch},
+              {kTriBatch, 5, &rr_tuning::tri_batch},
               {kFused, 2, &rr_tuning::fused},
               {kShadeBatch, 3, &rr_tuning::shade_batch}};
   double inc = 0.0;
