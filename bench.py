@@ -23,7 +23,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic bytes per unit of work of the trace kernel (see DESIGN.md)
+# algorithmic bytes per unit of work of the trace kernel
 NODE_BYTES = 64        # one four-wide node: quantised child boxes, box frame, child refs
 TRI_BYTES = 48         # v0 | e1 | e2 of a leaf triangle
 TRACE_RAY_BYTES = 52   # origin, L, direction, excluded leaf, medium/scan of a queued ray
