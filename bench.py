@@ -38,11 +38,11 @@ HBM_PEAK_GBS = 8000.0
 # plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
 # all of them).  Valid only for the kernel sources it was taken on.
 TRACE_HBM = {
-    "urban_block_200k": dict(fetch_kib=53043.0, write_kib=24611.9),
-    "urban_block_200k_air": dict(fetch_kib=53734.4, write_kib=24961.1),
+    "urban_block_200k": dict(fetch_kib=53657.9, write_kib=25961.1),
+    "urban_block_200k_air": dict(fetch_kib=54018.5, write_kib=26238.7),
 }
 TRACE_HBM_SCALE = dict(fetch_scale=2.0, write_scale=1.0,
-                       sources_sha256="ef4b9055d45c5f6a4ed0b61fd131baf6380e50cd438940703eb4cf6e3bc26a47")
+                       sources_sha256="4fd10ad32f0b20966c1af19df8238209832ece6d8f71baf73634adb5a7c76f9a")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
@@ -222,7 +222,7 @@ POST_BYTES_PER_PIXEL = 9   # float32 energy read, float32 dB and 8-bit pixel wri
 # same two rocprofv3 --pmc passes and copy-kernel scale as the trace kernel's
 POST_HBM = dict(workload="polar_epilogue_64x400x3776", fetch_kib=198520.1, write_kib=472000.0,
                 fetch_scale=2.0, write_scale=1.0,
-                sources_sha256="d70b40c6872b4ca97c08b45a8f441316718b3b4d85792e29372e5f0059dcc6fa")
+                sources_sha256="f15c1b6e87a34b8e82c2f7f6468493ad0ffe19c7c7ad577d9849c45e29339dcd")
 POST_SOURCES = ("post.hip", "post.h", "philox.h", "rr_internal.h")
 POST_FULL = dict(blur_sigma_bins=2.0, uniform_amp=1e-7, perlin_amp=1e-6, perlin_cell_az=16.0,
                  perlin_cell_bins=64.0, seed=12345, scan_id=0)

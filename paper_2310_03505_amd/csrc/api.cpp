@@ -1068,7 +1068,7 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   if (!ctx || !t) return fail(ctx, RR_EINVAL, "NULL argument");
   uint32_t rl = t->refill_lanes ? t->refill_lanes : 8u;
-  uint32_t wc = t->trace_waves_per_cu ? t->trace_waves_per_cu : 20u;
+  uint32_t wc = t->trace_waves_per_cu ? t->trace_waves_per_cu : 24u;
   uint32_t pr = t->pool_rays ? t->pool_rays : 64u;
   if (rl > 64) return fail(ctx, RR_EINVAL, "refill_lanes out of [1, 64]");
   if (wc > 32) return fail(ctx, RR_EINVAL, "trace_waves_per_cu out of [1, 32]");

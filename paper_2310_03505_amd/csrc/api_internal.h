@@ -32,7 +32,7 @@ struct rr_context {
   unsigned long long* d_prof = nullptr;
   // tuning
   uint32_t refill_lanes = 8;
-  uint32_t trace_waves_per_cu = 20;
+  uint32_t trace_waves_per_cu = 24;
   uint32_t pool_rays = 64;
   uint32_t tri_batch = 16;  // queued leaves that start a triangle phase
   uint32_t fused = 0;       // 1: all bounce levels in one persistent launch

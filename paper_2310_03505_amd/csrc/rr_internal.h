@@ -25,8 +25,8 @@ struct alignas(16) uint4 {
 namespace rr {
 
 constexpr int kMaxDepth = 32;  // two-wide build: inner-node depth bound
-constexpr int kStack = 20;     // traversal stack entries per lane held in LDS
-constexpr int kSpill = 76;     // further entries per lane in workspace memory
+constexpr int kStack = 16;     // traversal stack entries per lane held in LDS
+constexpr int kSpill = 80;     // further entries per lane in workspace memory
 
 // Four-wide node with quantised child boxes, 64 bytes (four 16-byte loads):
 //   w0 = (origin.x, origin.y, origin.z, exponent bytes ex | ey << 8 | ez << 16)

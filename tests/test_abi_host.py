@@ -53,9 +53,9 @@ def test_workspace_query_and_validation(R):
     n = R.rr_workspace_query(p)
     # two queues of N_p * 2^(B-1) rays of 52 bytes, one 8-byte hit per ray
     # of a level, the accumulator, and the traversal-stack spill area
-    # (76 entries x 256 CUs x 32 waves x 64 lanes)
+    # (80 entries x 256 CUs x 32 waves x 64 lanes)
     cap = 400 * 1024 * 8
-    want = 2 * cap * 52 + cap * 8 + 400 * 3776 * 8 + 4 * 76 * 256 * 32 * 64
+    want = 2 * cap * 52 + cap * 8 + 400 * 3776 * 8 + 4 * 80 * 256 * 32 * 64
     assert want <= n < want + (1 << 20)
     for bad in [dict(p, max_bounces=9), dict(p, n_azimuth=0), dict(p, beam_prob=0.0),
                 dict(p, beam_width_rad=4.0), dict(p, rays_per_beam=(1 << 20) + 1),
