@@ -42,7 +42,7 @@ TRACE_HBM = {
     "urban_block_200k_air": dict(fetch_kib=54018.5, write_kib=26238.7),
 }
 TRACE_HBM_SCALE = dict(fetch_scale=2.0, write_scale=1.0,
-                       sources_sha256="4fd10ad32f0b20966c1af19df8238209832ece6d8f71baf73634adb5a7c76f9a")
+                       sources_sha256="45120ef71ebd1eeae5e857b7c1581bc661586b2aea5cbe3b1276a15ae4ac7cad")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 

@@ -414,12 +414,17 @@ rr_status rr_server_destroy(rr_server* srv);
 /* Launch parameters of the traversal kernel (all zero = defaults).  They
  * change speed only, never results. */
 typedef struct {
-  uint32_t refill_lanes;   /* a wave takes new rays once this many lanes are idle (1..64) */
-  uint32_t trace_waves_per_cu; /* persistent trace waves per compute unit (1..32) */
-  uint32_t pool_rays;      /* rays a trace wave claims per atomic (64..4096) */
-  uint32_t batch_budget_mb; /* workspace budget of one batch group, MiB (>= 64) */
+  uint32_t refill_lanes;   /* a wave takes new rays once this many lanes are
+                              idle (1..64, default 8) */
+  uint32_t trace_waves_per_cu; /* persistent trace waves per compute unit in
+                              the grid (1..32, default 24) */
+  uint32_t pool_rays;      /* rays a trace wave claims per atomic (64..4096,
+                              default 64) */
+  uint32_t batch_budget_mb; /* workspace budget of one batch group, MiB (>= 64,
+                              default 24 GiB) */
   uint32_t tri_batch;      /* leaves a trace wave queues before it tests their
-                             triangles in one step, one leaf per lane (1..64) */
+                             triangles in one step, one leaf per lane (1..64,
+                             default 16) */
   uint32_t fused;          /* 0: default (2); 1: every bounce level in one
                              persistent launch, each wave tracing and shading
                              its own rays' children; 2: one trace and one shade

@@ -5,11 +5,14 @@
 //             (Sec. III-A, Eq. 2), appended to ray queue 0;
 //   k_trace   (per bounce level) closest hit of every queued ray through the
 //             BVH: persistent lanes that take a new ray as soon as theirs is
-//             done, leaf tests batched wave-wide;
+//             done (rays claimed 64 at a time from per-segment cursors), up
+//             to kNodeSteps node steps between two scheduling decisions,
+//             leaf tests batched wave-wide;
 //   k_shade   (per bounce level) the interaction at each hit (Snell,
 //             Fresnel, standard BRDF return, Sec. III-A), the return binned
 //             into the polar image with a 64-bit fixed-point atomic
-//             (Sec. III-B), and up to two children appended to the next queue;
+//             (Sec. III-B), and up to two children appended to the next queue
+//             (one reservation per 512-lane block step);
 //   k_scan    the optional one-launch form of k_trace + k_shade over every
 //             level, each wave keeping its own rays' children.
 //
