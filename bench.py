@@ -422,7 +422,8 @@ def bench_serve(args):
         "ms_per_step": round(st["wall_s"] * 1e3 / max(st["completed"], 1), 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "serve_poisson_200hz_large_scene_2m" + ("_one_per_launch" if one else ""),
+        "config": {"workload": "serve_poisson_%dhz_large_scene_2m" % round(200.0 * args.serve_rate_scale)
+                               + ("_one_per_launch" if one else ""),
                    "requests": len(reqs), "stream_seconds": args.serve_seconds,
                    "arrival_rate_hz": round(200.0 * args.serve_rate_scale, 1),
                    "completed": st["completed"], "rejected": st["rejected"], "batches": st["batches"],
