@@ -419,6 +419,41 @@ def test_autotune_keeps_images(R, ctx):
         sc.release()
 
 
+@pytest.mark.parametrize("tuning", [
+    dict(refill_lanes=1), dict(refill_lanes=64), dict(trace_waves_per_cu=1), dict(trace_waves_per_cu=32),
+    dict(pool_rays=4096), dict(tri_batch=1), dict(tri_batch=64),
+    dict(refill_lanes=64, trace_waves_per_cu=1, pool_rays=4096, tri_batch=64)])
+def test_extreme_tunings_keep_images(R, ctx, tuning):
+    """Launch parameters at the ends of their ranges (one lane or a whole wave
+    idle before a refill, one wave per CU or 32, claims of 4,096 rays -- more
+    than a claim segment holds -- and triangle phases after 1 or 64 queued
+    leaves) change the schedule of the trace kernel only: hit records,
+    accumulator and image equal those of the default parameters, bit for
+    bit, on the tiny room at four bounces and on 24 columns of the urban
+    block."""
+    import torch
+    before = R.rr_get_tuning(ctx.handle)
+    t, u = W.tiny_room(), W.urban_block()
+    cases = [(t, dict(t.params, max_bounces=4), t.pose), (u, dict(u.params, n_azimuth=24), u.pose)]
+    try:
+        for scene, p, pose in cases:
+            sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+            try:
+                R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
+                ref = R.rr_radar_scan_records(ctx.handle, sc.handle, pose, p, scene.materials)
+                R.rr_set_tuning(ctx.handle, **dict({k: before[k] for k in R.TUNING_KEYS}, **tuning))
+                got = R.rr_radar_scan_records(ctx.handle, sc.handle, pose, p, scene.materials)
+                torch.cuda.synchronize()
+                log(f"tuning {tuning}: {scene.name} {got['stats']['rays_per_depth']}")
+                assert torch.equal(ref["records"], got["records"])
+                assert torch.equal(ref["accum"], got["accum"])
+                assert torch.equal(ref["image"], got["image"])
+            finally:
+                sc.release()
+    finally:
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
+
+
 # ---------------------------------------------------------------- serving
 def test_server_mix_equals_alone(R, ctx):
     """Requests served in overlapping batches produce the same images, bit for
