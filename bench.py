@@ -38,11 +38,11 @@ HBM_PEAK_GBS = 8000.0
 # plain 1 GiB device copy (FETCH_SIZE reads half the bytes moved, WRITE_SIZE
 # all of them).  Valid only for the kernel sources it was taken on.
 TRACE_HBM = {
-    "urban_block_200k": dict(fetch_kib=53657.9, write_kib=25961.1),
-    "urban_block_200k_air": dict(fetch_kib=54018.5, write_kib=26238.7),
+    "urban_block_200k": dict(fetch_kib=53071.3, write_kib=25856.9),
+    "urban_block_200k_air": dict(fetch_kib=54245.0, write_kib=26292.8),
 }
 TRACE_HBM_SCALE = dict(fetch_scale=2.0, write_scale=1.0,
-                       sources_sha256="45120ef71ebd1eeae5e857b7c1581bc661586b2aea5cbe3b1276a15ae4ac7cad")
+                       sources_sha256="779e26bbe36c14781e5442f47420e01a920a4958334b39289da184894ba77412")
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h")
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
@@ -222,7 +222,7 @@ POST_BYTES_PER_PIXEL = 9   # float32 energy read, float32 dB and 8-bit pixel wri
 # same two rocprofv3 --pmc passes and copy-kernel scale as the trace kernel's
 POST_HBM = dict(workload="polar_epilogue_64x400x3776", fetch_kib=198520.1, write_kib=472000.0,
                 fetch_scale=2.0, write_scale=1.0,
-                sources_sha256="f15c1b6e87a34b8e82c2f7f6468493ad0ffe19c7c7ad577d9849c45e29339dcd")
+                sources_sha256="25aca0723d84e536dcba3a684e466421b9eda9a926da7bc8e08d0d1a6823a1d7")
 POST_SOURCES = ("post.hip", "post.h", "philox.h", "rr_internal.h")
 POST_FULL = dict(blur_sigma_bins=2.0, uniform_amp=1e-7, perlin_amp=1e-6, perlin_cell_az=16.0,
                  perlin_cell_bins=64.0, seed=12345, scan_id=0)

@@ -34,6 +34,32 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Claims this wave's next `pool` rays of a queue of n_in rays.  The queue is
+// split into kCtrSegs segments, each with its own cursor (`cur`, one cursor
+// per kCtrCursorStride words, so on its own cache line): one cursor
+// serialised every wave's claims.  A wave starts at segment `seg` and moves
+// on cyclically once that one is used up; `tries` counts the segments found
+// used up.  On success the rays are [next, end); false once every segment is
+// used up.  Wave-uniform; lane 0 does the atomics.
+__device__ __forceinline__ bool claim_rays(uint32_t* cur, uint32_t n_in, uint32_t pool, uint32_t lane,
+                                           uint32_t& seg, uint32_t& tries, uint32_t& next, uint32_t& end) {
+#pragma unroll 1
+  for (;;) {
+    const uint32_t s0 = (uint32_t)((uint64_t)n_in * seg / kCtrSegs);
+    const uint32_t s1 = (uint32_t)((uint64_t)n_in * (seg + 1u) / kCtrSegs);
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(cur + seg * kCtrCursorStride, pool);
+    base = __shfl(base, 0);
+    if (base < s1 - s0) {
+      next = s0 + base;
+      end = min(next + pool, s1);
+      return true;
+    }
+    if (++tries >= kCtrSegs) return false;
+    seg = (seg + 1u) & (kCtrSegs - 1u);
+  }
+}
+
 constexpr uint32_t kHashBits = 11;     // shade: LDS table of 2048 accumulator cells
 constexpr uint32_t kHashSlots = 1u << kHashBits;
 constexpr uint32_t kHashEmpty = 0xffffffffu;
@@ -139,7 +165,7 @@ __device__ __forceinline__ void normalize3(float& x, float& y, float& z) {
 // Closest-hit traversal, persistent and replenishing (after Aila & Laine,
 // "Understanding the efficiency of ray traversal on GPUs", HPG 2009): every
 // lane owns one ray at a time; lanes whose ray has finished take new rays
-// from the level's cursor (one atomic per wave) as soon as A.refill lanes are
+// (claim_rays, one atomic per wave and claim) as soon as A.refill lanes are
 // idle.
 //
 // Each loop iteration is either a node step or a triangle phase, decided for
@@ -178,11 +204,9 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
 
   bool valid = false, exhausted = false;
   uint32_t pool_next = 0, pool_end = 0;  // wave-uniform: claimed, not yet started rays
-  // the queue is claimed in kCtrSegs segments, each with its own cursor (one
-  // cursor serialised every wave's claims); a wave starts at its block's
-  // segment and moves on to the next once that one is used up.  Closest-hit
-  // levels use cursor set `depth`, the visibility launch the set after the
-  // last level's.
+  // rays are claimed from segment cursors (claim_rays), starting at the
+  // block's segment; closest-hit levels use cursor set `depth`, the
+  // visibility launch the set after the last level's
   uint32_t seg = blockIdx.x & (kCtrSegs - 1u), seg_tries = 0;
   uint32_t* const seg_cur =
       A.counters + kCtrCursor + (kShadow ? kMaxLevels : A.depth) * kCtrSegs * kCtrCursorStride;
@@ -205,26 +229,10 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
     if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
 #pragma unroll 1
       for (int pass = 0; pass < 2 && idle; ++pass) {
-        if (pool_next >= pool_end) {
-#pragma unroll 1
-          for (;;) {
-            const uint32_t s0 = (uint32_t)((uint64_t)n_in * seg / kCtrSegs);
-            const uint32_t s1 = (uint32_t)((uint64_t)n_in * (seg + 1u) / kCtrSegs);
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(seg_cur + seg * kCtrCursorStride, A.pool);
-            base = __shfl(base, 0);
-            if (base < s1 - s0) {
-              pool_next = s0 + base;
-              pool_end = min(pool_next + A.pool, s1);
-              break;
-            }
-            if (++seg_tries >= kCtrSegs) {
-              exhausted = true;
-              break;
-            }
-            seg = (seg + 1u) & (kCtrSegs - 1u);
-          }
-          if (exhausted) break;
+        if (pool_next >= pool_end &&
+            !claim_rays(seg_cur, n_in, A.pool, lane, seg, seg_tries, pool_next, pool_end)) {
+          exhausted = true;
+          break;
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
         const uint32_t rank = lane_prefix(idle);
@@ -490,7 +498,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
   const uint32_t n_in = min(A.counters[kCtrCount + A.depth], A.cap);
-  uint32_t* cursor = A.counters + kCtrWork + A.depth;
+  uint32_t seg = blockIdx.x & (kCtrSegs - 1u), seg_tries = 0;  // claim_rays state
+  uint32_t* const seg_cur = A.counters + kCtrCursor + A.depth * kCtrSegs * kCtrCursorStride;
   const Node8* __restrict__ nodes = A.nodes8;
   const float4* __restrict__ tris = A.tris;
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -517,16 +526,10 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
     if (!exhausted && (uint32_t)__popcll(idle) >= A.refill) {
 #pragma unroll 1
       for (int pass = 0; pass < 2 && idle; ++pass) {
-        if (pool_next >= pool_end) {
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(cursor, A.pool);
-          base = __shfl(base, 0);
-          pool_next = base;
-          pool_end = min(base + A.pool, n_in);
-          if (base >= n_in) {
-            exhausted = true;
-            break;
-          }
+        if (pool_next >= pool_end &&
+            !claim_rays(seg_cur, n_in, A.pool, lane, seg, seg_tries, pool_next, pool_end)) {
+          exhausted = true;
+          break;
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
         const uint32_t rank = lane_prefix(idle);
@@ -560,7 +563,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace8(LevelArgs A) {
         }
         pool_next += take;
         idle = __ballot(!valid);
-        if (pool_next >= pool_end && pool_end >= n_in) exhausted = true;
       }
     }
     const uint64_t live = __ballot(valid);
@@ -1161,7 +1163,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
   const uint32_t wib = threadIdx.x >> 6;
   const uint32_t wave_base = threadIdx.x - lane;
   const uint32_t n_in = min(A.counters[kCtrCount], A.cap);
-  uint32_t* cursor = A.counters + kCtrWork;
+  uint32_t seg = blockIdx.x & (kCtrSegs - 1u), seg_tries = 0;  // claim_rays state (level 0's cursors)
+  uint32_t* const seg_cur = A.counters + kCtrCursor;
   const Node4* __restrict__ nodes = A.nodes;
   const float4* __restrict__ tris = A.tris;
   const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1237,16 +1240,10 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
     if (!exhausted && pool_n == 0 && (uint32_t)__popcll(idle) >= A.refill) {
 #pragma unroll 1
       for (int pass = 0; pass < 2 && idle; ++pass) {
-        if (pool_next >= pool_end) {
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(cursor, A.pool);
-          base = __shfl(base, 0);
-          pool_next = base;
-          pool_end = min(base + A.pool, n_in);
-          if (base >= n_in) {
-            exhausted = true;
-            break;
-          }
+        if (pool_next >= pool_end &&
+            !claim_rays(seg_cur, n_in, A.pool, lane, seg, seg_tries, pool_next, pool_end)) {
+          exhausted = true;
+          break;
         }
         const uint32_t take = min((uint32_t)__popcll(idle), pool_end - pool_next);
         const uint32_t rank = lane_prefix(idle);
@@ -1256,7 +1253,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_scan(LevelArgs A) {
         }
         pool_next += take;
         idle = __ballot(!valid);
-        if (pool_next >= pool_end && pool_end >= n_in) exhausted = true;
       }
     }
     const uint64_t live = __ballot(valid);

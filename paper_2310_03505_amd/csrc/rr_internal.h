@@ -97,13 +97,11 @@ struct DevScan {
 constexpr uint32_t kAir = 255u;
 constexpr size_t kRayBytes = 16 + 16 + 16 + 4;
 
-// counters block (uint32): [0..8] rays per depth, [16..24] work cursors (the
-// eight-wide and one-launch traversals), [32] overflow flag, [40] air-path
-// visibility rays of the scan, [64..) the claim cursors of the four-wide
-// traversal's levels and of the visibility launch; only the first 64 words
-// are read back to the host
+// counters block (uint32): [0..8] rays per depth, [32] overflow flag, [40]
+// air-path visibility rays of the scan, [64..) the claim cursors of the
+// traversal levels and of the visibility launch; only the first 64 words are
+// read back to the host
 constexpr int kCtrCount = 0;
-constexpr int kCtrWork = 16;
 constexpr int kCtrOverflow = 32;
 constexpr int kCtrShadow = 40;
 constexpr int kCtrHostWords = 64;   // the part of the block read back to the host
