@@ -8,8 +8,9 @@ image, all in the HIP library.  The scene and its BVH are resident before
 the timed region.
 
 Prints one JSON line: Mray-segments/s (closest-hit queries per second) and
-scans/s, the roofline of the dominant kernel (the bounce kernel) from live
-HIP-event timings and a counting pass, and the CPU oracle timed on a bounded
+scans/s, the roofline of the dominant kernel (k_trace, the closest-hit
+traversal) from live HIP-event timings, a counting pass and the HBM traffic
+measured for these kernel sources, and the CPU oracle timed on a bounded
 sample of the same workload.
 """
 from __future__ import annotations
