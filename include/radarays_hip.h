@@ -224,16 +224,24 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* scene, const rr_bvh_options* o
 
 rr_status rr_bvh_get_info(const rr_scene* scene, rr_bvh_info* out);
 
-/* Moves the vertices of a scene whose BVH was built on the GPU (builder 1):
+/* Moves the vertices of a scene with a four-wide BVH on the device:
  * vertices_dev holds nv x 3 floats in device memory, nv equal to the count
  * uploaded, indices and materials unchanged (for moving objects).  The tree
- * keeps its structure; triangles, normals, boxes and node frames are
- * recomputed on the GPU, stream-ordered on `stream` with no allocation, so
- * scans issued after it on that stream see the new geometry.  Triangles
- * that were degenerate at build time stay out of the tree.  ESTATE if the
- * BVH was built on the host; EINVAL for a NULL pointer or a vertex count
- * other than the uploaded one (coordinates in device memory are not
- * checked). */
+ * keeps its structure and leaf order; triangles, normals, child boxes and
+ * node frames are recomputed on the GPU, one launch per tree depth, deepest
+ * first, stream-ordered on `stream`, so scans issued after it on that stream
+ * see the new geometry.  Either builder's tree can be refitted (a host SAH
+ * tree keeps its better structure while objects move a little).  A tree
+ * built on the GPU refits with no allocation; the first refit of a
+ * host-built tree sets up its refit state synchronously (device copies of
+ * indices and materials, the nodes grouped by depth and a box per node: 14
+ * bytes per triangle and 28 per node), later ones allocate nothing.  Triangles that were degenerate at
+ * build time stay out of the tree; child boxes of split references grow to
+ * whole triangles.  The host copy of the mesh is not changed, so
+ * rr_bvh_build afterwards builds from the uploaded vertices.  ESTATE
+ * without a device BVH; EINVAL for a NULL pointer, an eight-wide tree or a
+ * vertex count other than the uploaded one (coordinates in device memory
+ * are not checked). */
 rr_status rr_bvh_refit(rr_context* ctx, rr_scene* scene, const float* vertices_dev, uint32_t nv,
                        void* stream);
 

@@ -260,8 +260,9 @@ def rr_bvh_build(ctx, scene, max_leaf_size: int = 0, sah_bins: int = 0, n_thread
 
 
 def rr_bvh_refit(ctx, scene, vertices, stream=None):
-    """New vertex positions (a float32 CUDA tensor [nv, 3]) for a scene whose
-    BVH was built on the GPU; the tree is refitted on the GPU."""
+    """New vertex positions (a float32 CUDA tensor [nv, 3]) for a scene with
+    a four-wide BVH (either builder); the tree is refitted on the GPU,
+    stream-ordered."""
     import torch
     if vertices.dtype != torch.float32 or not vertices.is_contiguous() or vertices.dim() != 2:
         raise ValueError("vertices must be a contiguous float32 tensor [nv, 3]")

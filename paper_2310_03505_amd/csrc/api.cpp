@@ -640,6 +640,12 @@ void free_scene_device(rr_scene* sc) {
     delete sc->gb;
     sc->gb = nullptr;
   }
+  if (sc->hr) {
+    rr::host_refit_free(*sc->hr);
+    delete sc->hr;
+    sc->hr = nullptr;
+  }
+  sc->refitted = false;
 }
 
 // Linear BVH built on the GPU from the scene's mesh (uploaded here).
@@ -797,8 +803,44 @@ rr_status rr_bvh_get_info(const rr_scene* sc, rr_bvh_info* out) {
 rr_status rr_bvh_selfcheck(const rr_scene* sc, uint32_t n_rays, uint64_t seed, uint64_t* mismatches) {
   if (!sc || !mismatches) return fail(nullptr, RR_EINVAL, "NULL argument");
   if (!sc->built) return fail(nullptr, RR_ESTATE, "scene has no BVH");
-  if (!sc->gb) {
+  if (!sc->gb && !sc->refitted) {
     *mismatches = bvh_selfcheck(sc->bvh, n_rays, seed);
+    return RR_OK;
+  }
+  if (!sc->gb) {
+    // a refitted host tree: check the device copy (same structure, moved
+    // triangles) against brute force over its own leaf triangles
+    DeviceGuard dg(sc->ctx->device);
+    rr::BuiltBvh b;
+    b.width = 4;
+    b.n_tris = sc->bvh.n_tris;
+    b.nodes.resize(sc->bvh.nodes.size());
+    b.tris.resize(sc->bvh.tris.size());
+    b.aux.resize(sc->bvh.aux.size());
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(b.nodes.data(), sc->d_nodes, sizeof(rr::Node4) * b.nodes.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+        (!b.tris.empty() &&
+         hipMemcpy(b.tris.data(), sc->d_tris, sizeof(float4) * b.tris.size(), hipMemcpyDeviceToHost) != hipSuccess) ||
+        (!b.aux.empty() &&
+         hipMemcpy(b.aux.data(), sc->d_aux, sizeof(float4) * b.aux.size(), hipMemcpyDeviceToHost) != hipSuccess))
+      return fail(sc->ctx, RR_EDEVICE, "download of the refitted tree failed");
+    for (int k = 0; k < 3; ++k) {
+      b.lo[k] = INFINITY;
+      b.hi[k] = -INFINITY;
+    }
+    for (size_t p = 0; p < b.tris.size() / 3; ++p) {
+      const float4* t = &b.tris[3 * p];
+      for (int k = 0; k < 3; ++k) {
+        const float v0 = (&t[0].x)[k];
+        for (float x : {v0, v0 + (&t[1].x)[k], v0 + (&t[2].x)[k]}) {
+          b.lo[k] = std::min(b.lo[k], x);
+          b.hi[k] = std::max(b.hi[k], x);
+        }
+      }
+    }
+    for (int k = 0; k < 3; ++k)
+      if (!(b.lo[k] <= b.hi[k])) b.lo[k] = b.hi[k] = 0.0f;
+    *mismatches = rr::bvh_selfcheck(b, n_rays, seed);
     return RR_OK;
   }
   // a tree built on the GPU: download it and check it on the host, plus
@@ -860,12 +902,32 @@ rr_status rr_bvh_selfcheck(const rr_scene* sc, uint32_t n_rays, uint64_t seed, u
 rr_status rr_bvh_refit(rr_context* ctx, rr_scene* sc, const float* vertices_dev, uint32_t nv, void* stream) {
   if (!sc || !vertices_dev) return fail(ctx, RR_EINVAL, "NULL argument");
   if (sc->ctx != ctx || !ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
-  if (!sc->built || !sc->gb) return fail(ctx, RR_ESTATE, "refit needs a BVH built on the GPU (builder 1)");
-  if (nv != sc->gb->nv) return fail(ctx, RR_EINVAL, "refit takes %u vertices, got %u", sc->gb->nv, nv);
+  if (!sc->built || !sc->d_nodes) return fail(ctx, RR_ESTATE, "scene has no BVH on the device");
+  if (nv != sc->nv) return fail(ctx, RR_EINVAL, "refit takes %u vertices, got %u", sc->nv, nv);
   DeviceGuard dg(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (nv) HIP_TRY(ctx, hipMemcpyAsync(sc->gb->V, vertices_dev, 12 * (size_t)nv, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(ctx, rr::gpu_bvh_refit(*sc->gb, static_cast<rr::Node4*>(sc->d_nodes), sc->d_tris, sc->d_aux, st));
+  if (sc->gb) {
+    if (nv) HIP_TRY(ctx, hipMemcpyAsync(sc->gb->V, vertices_dev, 12 * (size_t)nv, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, rr::gpu_bvh_refit(*sc->gb, static_cast<rr::Node4*>(sc->d_nodes), sc->d_tris, sc->d_aux, st));
+    return RR_OK;
+  }
+  if (sc->bvh.width != 4) return fail(ctx, RR_EINVAL, "refit of an eight-wide BVH is not supported");
+  if (!sc->hr) {
+    // first refit of this tree: its depth order, indices and materials
+    sc->hr = new rr::HostRefit();
+    const hipError_t e = rr::host_refit_setup(*sc->hr, sc->bvh.nodes.data(), (uint32_t)sc->bvh.nodes.size(),
+                                              (uint32_t)(sc->bvh.tris.size() / 3), sc->F.data(), sc->M.data(),
+                                              sc->nt);
+    if (e != hipSuccess) {
+      rr::host_refit_free(*sc->hr);
+      delete sc->hr;
+      sc->hr = nullptr;
+      return fail(ctx, e == hipErrorOutOfMemory ? RR_ENOMEM : RR_EDEVICE, "refit set-up: %s", hipGetErrorString(e));
+    }
+  }
+  sc->refitted = true;
+  HIP_TRY(ctx, rr::host_refit(*sc->hr, vertices_dev, nv, static_cast<rr::Node4*>(sc->d_nodes), sc->d_tris,
+                              sc->d_aux, st));
   return RR_OK;
 }
 

@@ -52,6 +52,8 @@ struct rr_scene {
   void* d_nodes = nullptr;  // rr::Node4 or rr::Node8 array, as bvh.width says
   uint32_t n_nodes = 0;     // nodes in d_nodes
   rr::GpuBvh* gb = nullptr; // state of a tree built on the GPU (kept for refits)
+  rr::HostRefit* hr = nullptr;  // refit state of a host-built tree (first refit on)
+  bool refitted = false;        // device nodes and triangles differ from `bvh`
   float4* d_tris = nullptr;
   float4* d_aux = nullptr;
   uint64_t dev_bytes = 0;

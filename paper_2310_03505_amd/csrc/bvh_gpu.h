@@ -55,6 +55,35 @@ hipError_t gpu_bvh_refit(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hip
 
 void gpu_bvh_free(GpuBvh& g);
 
+// Device state for refitting a four-wide tree built on the host: its nodes
+// and the order of its leaf triangles stay, moved vertices give new
+// triangles, normals, child boxes and node frames.  Holds the mesh's indices
+// and materials and the nodes grouped by depth (set up once per tree).
+struct HostRefit {
+  uint32_t nt = 0, n_nodes = 0, n_leaf_tris = 0;
+  uint32_t* F = nullptr;      // [nt][3]
+  uint16_t* M = nullptr;      // [nt] material ids
+  uint32_t* order = nullptr;  // [n_nodes] node indices grouped by depth
+  float* nbox = nullptr;      // [n_nodes][6] refitted box of each node
+  uint32_t* misc = nullptr;   // [16]; [6] the largest coordinate magnitude
+  std::vector<uint32_t> level_off, level_cnt;
+};
+
+// Allocates r and uploads the indices, materials and the depth order of the
+// host tree `nodes` (root 0, children after their parents); synchronous.
+hipError_t host_refit_setup(HostRefit& r, const Node4* nodes, uint32_t n_nodes, uint32_t n_leaf_tris,
+                            const uint32_t* F, const uint16_t* M, uint32_t nt);
+
+// Refits the tree in place from V (device, nv x 3): normals and the padding
+// magnitude, the leaf triangles, then the nodes one depth at a time, deepest
+// first, with the conservative quantisation of a build; stream-ordered, no
+// allocation.  A refit with the build's vertices reproduces the build's
+// nodes (for trees without split references).
+hipError_t host_refit(HostRefit& r, const float* V, uint32_t nv, Node4* nodes, float4* tris, float4* aux,
+                      hipStream_t st);
+
+void host_refit_free(HostRefit& r);
+
 // Scratch bytes of the sort and the scan of a build over n triangles.
 hipError_t rocprim_sizes(size_t n, size_t* sort_bytes, size_t* scan_bytes);
 

@@ -9,6 +9,7 @@
 // normals, boxes and node frames from moved vertices.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -507,6 +508,169 @@ hipError_t gpu_bvh_refit(GpuBvh& g, Node4* nodes, float4* tris, float4* aux, hip
   RR_GB(hipGetLastError());
 #undef RR_GB
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------- refit of a host-built tree
+namespace {
+
+// leaf-order triangle li: vertex and edges from the moved vertices of its
+// original triangle (the original id stays in the first word's w)
+__global__ void __launch_bounds__(kB) k_hr_tris(GpuBvh g, float4* tris, uint32_t n) {
+  const uint32_t li = blockIdx.x * kB + threadIdx.x;
+  if (li >= n) return;
+  const uint32_t orig = __float_as_uint(tris[3u * li].w);
+  if (orig >= g.nt) return;
+  Tri t;
+  load_tri(g, orig, t);
+  tris[3u * li + 0u] = make_float4(t.p0[0], t.p0[1], t.p0[2], __uint_as_float(orig));
+  tris[3u * li + 1u] = make_float4(t.e1[0], t.e1[1], t.e1[2], 0.0f);
+  tris[3u * li + 2u] = make_float4(t.e2[0], t.e2[1], t.e2[2], 0.0f);
+}
+
+// the nodes of one depth: child boxes (inner children from the deeper level
+// just refitted, leaves from their triangles), the quantised node and its
+// own box for its parent.  A slot counts as written by the build if it holds
+// a child or nonzero box bytes (an empty leaf the build quantised as the
+// point 0), so a refit with unmoved vertices rewrites every byte as built.
+__global__ void __launch_bounds__(kB) k_hr_level(GpuBvh g, Node4* nodes, const float4* tris, float* nbox,
+                                                 const uint32_t* order, uint32_t first, uint32_t count,
+                                                 uint32_t n_nodes, uint32_t n_leaf_tris) {
+  const uint32_t k = blockIdx.x * kB + threadIdx.x;
+  if (k >= count) return;
+  const uint32_t id = order[first + k];
+  if (id >= n_nodes) return;
+  const float pad = __uint_as_float(g.misc[6]) * (1.0f / 262144.0f);
+  const Node4 nd = nodes[id];
+  const int32_t refs[4] = {nd.w3.x, nd.w3.y, nd.w3.z, nd.w3.w};
+  const uint32_t qb = nd.w1.x | nd.w1.y | nd.w1.z | nd.w1.w | nd.w2.x | nd.w2.y;
+  Kid kids[4];
+  int n_kids = 0;
+  float nlo[3] = {INFINITY, INFINITY, INFINITY}, nhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int j = 0; j < 4; ++j) {
+    Kid& kd = kids[j];
+    kd.ref = refs[j];
+    kd.empty = true;
+    for (int a = 0; a < 3; ++a) {
+      kd.lo[a] = INFINITY;
+      kd.hi[a] = -INFINITY;
+    }
+    if (refs[j] != kEmpty || ((qb >> (8 * j)) & 255u) != 0u) n_kids = j + 1;
+    if (refs[j] == kEmpty) continue;
+    if (refs[j] >= 0) {
+      if ((uint32_t)refs[j] < n_nodes) {
+        const float* b = nbox + 6u * (uint32_t)refs[j];
+        for (int a = 0; a < 3; ++a) {
+          kd.lo[a] = b[a];
+          kd.hi[a] = b[3 + a];
+        }
+      }
+    } else {
+      const uint32_t start = leaf_start(refs[j]), cnt = leaf_count(refs[j]);
+      for (uint32_t u = 0; u < cnt; ++u) {
+        const uint32_t li = start + u;
+        if (li >= n_leaf_tris) break;
+        const uint32_t orig = __float_as_uint(tris[3u * li].w);
+        if (orig >= g.nt) continue;
+        Tri t;
+        load_tri(g, orig, t);
+        float lo[3], hi[3];
+        tri_box(t, lo, hi);
+        for (int a = 0; a < 3; ++a) {
+          kd.lo[a] = fminf(kd.lo[a], lo[a]);
+          kd.hi[a] = fmaxf(kd.hi[a], hi[a]);
+        }
+      }
+    }
+    kd.empty = !(kd.lo[0] <= kd.hi[0] && kd.lo[1] <= kd.hi[1] && kd.lo[2] <= kd.hi[2]);
+    if (!kd.empty)
+      for (int a = 0; a < 3; ++a) {
+        nlo[a] = fminf(nlo[a], kd.lo[a]);
+        nhi[a] = fmaxf(nhi[a], kd.hi[a]);
+      }
+  }
+  write_node(nodes + id, kids, n_kids, pad);
+  for (int a = 0; a < 3; ++a) {
+    nbox[6u * id + (uint32_t)a] = nlo[a];
+    nbox[6u * id + 3u + (uint32_t)a] = nhi[a];
+  }
+}
+
+}  // namespace
+
+hipError_t host_refit_setup(HostRefit& r, const Node4* nodes, uint32_t n_nodes, uint32_t n_leaf_tris,
+                            const uint32_t* F, const uint16_t* M, uint32_t nt) {
+  hipError_t e;
+  host_refit_free(r);
+  r.nt = nt;
+  r.n_nodes = n_nodes;
+  r.n_leaf_tris = n_leaf_tris;
+  // depth of every node from the root (children are emitted after parents)
+  std::vector<uint32_t> depth(n_nodes, 0u);
+  uint32_t max_d = 0;
+  for (uint32_t i = 0; i < n_nodes; ++i) {
+    const int32_t refs[4] = {nodes[i].w3.x, nodes[i].w3.y, nodes[i].w3.z, nodes[i].w3.w};
+    for (int j = 0; j < 4; ++j) {
+      if (refs[j] == kEmpty || refs[j] < 0) continue;
+      if ((uint32_t)refs[j] >= n_nodes || (uint32_t)refs[j] <= i) return hipErrorInvalidValue;
+      depth[(uint32_t)refs[j]] = depth[i] + 1u;
+      max_d = std::max(max_d, depth[i] + 1u);
+    }
+  }
+  r.level_cnt.assign(max_d + 1u, 0u);
+  r.level_off.assign(max_d + 1u, 0u);
+  for (uint32_t i = 0; i < n_nodes; ++i) ++r.level_cnt[depth[i]];
+  for (uint32_t d = 1; d <= max_d; ++d) r.level_off[d] = r.level_off[d - 1] + r.level_cnt[d - 1];
+  std::vector<uint32_t> order(std::max<uint32_t>(n_nodes, 1u)), cur = r.level_off;
+  for (uint32_t i = 0; i < n_nodes; ++i) order[cur[depth[i]]++] = i;
+  if ((e = hipMalloc(&r.F, 12 * (size_t)std::max<uint32_t>(nt, 1u))) != hipSuccess) return e;
+  if ((e = hipMalloc(&r.M, 2 * (size_t)std::max<uint32_t>(nt, 1u))) != hipSuccess) return e;
+  if ((e = hipMalloc(&r.order, 4 * order.size())) != hipSuccess) return e;
+  if ((e = hipMalloc(&r.nbox, 24 * (size_t)std::max<uint32_t>(n_nodes, 1u))) != hipSuccess) return e;
+  if ((e = hipMalloc(&r.misc, 4 * (size_t)kMiscWords)) != hipSuccess) return e;
+  if (nt) {
+    if ((e = hipMemcpy(r.F, F, 12 * (size_t)nt, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(r.M, M, 2 * (size_t)nt, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  }
+  return hipMemcpy(r.order, order.data(), 4 * order.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t host_refit(HostRefit& r, const float* V, uint32_t nv, Node4* nodes, float4* tris, float4* aux,
+                      hipStream_t st) {
+  GpuBvh g;  // a view: the mesh and the scalars only
+  g.nv = nv;
+  g.nt = r.nt;
+  g.V = const_cast<float*>(V);
+  g.F = r.F;
+  g.M = r.M;
+  g.misc = r.misc;
+  hipError_t e;
+  hipLaunchKernelGGL(k_init_misc, dim3(1), dim3(64), 0, st, r.misc, true);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prep, grid_for(r.nt), dim3(kB), 0, st, g, aux, nullptr, false);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hr_tris, grid_for(r.n_leaf_tris), dim3(kB), 0, st, g, tris, r.n_leaf_tris);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int d = (int)r.level_cnt.size() - 1; d >= 0; --d) {
+    const uint32_t c = r.level_cnt[(size_t)d];
+    if (!c) continue;
+    hipLaunchKernelGGL(k_hr_level, grid_for(c), dim3(kB), 0, st, g, nodes, tris, r.nbox, r.order,
+                       r.level_off[(size_t)d], c, r.n_nodes, r.n_leaf_tris);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void host_refit_free(HostRefit& r) {
+  if (r.F) (void)hipFree(r.F);
+  if (r.M) (void)hipFree(r.M);
+  if (r.order) (void)hipFree(r.order);
+  if (r.nbox) (void)hipFree(r.nbox);
+  if (r.misc) (void)hipFree(r.misc);
+  r.F = nullptr;
+  r.M = nullptr;
+  r.order = nullptr;
+  r.nbox = nullptr;
+  r.misc = nullptr;
 }
 
 hipError_t rocprim_sizes(size_t n, size_t* sort_bytes, size_t* scan_bytes) {

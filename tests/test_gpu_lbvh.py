@@ -185,19 +185,84 @@ def test_refit_follows_moving_objects(R, ctx):
         sc.release()
 
 
+@pytest.mark.parametrize("opts", [dict(), dict(collapse=1), dict(merge_leaves=2, max_leaf_size=4),
+                                  dict(split_pct=50)], ids=["optimal", "greedy", "binary-leaves", "split"])
+def test_host_tree_refit_follows_moving_objects(R, ctx, opts):
+    """A host-built SAH tree refitted on the GPU: scans over it give the
+    records and accumulator of a fresh host build over the moved vertices
+    (the closest hit does not depend on the tree) and the oracle's records;
+    a refit back to the build's vertices gives the first scan again."""
+    import torch
+    s = W.tiny_room()
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material, **opts)
+    try:
+        first = scan(R, ctx, sc, s)
+        for t in (1, 3):
+            Vt = moved(s, t)
+            sc.refit(torch.from_numpy(Vt).cuda())
+            st = W.Scene("moved", Vt, s.indices, s.tri_material, s.materials, s.pose, s.params)
+            got = scan(R, ctx, sc, st)
+            fresh = R.Scene(ctx, Vt, s.indices, s.tri_material, **opts)
+            try:
+                want = scan(R, ctx, fresh, st)
+            finally:
+                fresh.release()
+            assert np.array_equal(got["records"], want["records"]), t
+            assert np.array_equal(got["accum"], want["accum"]), t
+            ref = oracle.scan_scene(st, records=True, exempt=True, threads=8)
+            ok = ~ref["exempt"]
+            assert not (got["records"][ok] != ref["records"][ok]).any(), t
+            assert sc.selfcheck(20000, t) == 0
+            log(f"  {opts} frame {t}: records equal a fresh build and the oracle")
+        sc.refit(torch.from_numpy(s.vertices).cuda())
+        again = scan(R, ctx, sc, s)
+        for k in ("records", "accum", "image"):
+            assert np.array_equal(again[k], first[k]), k
+    finally:
+        sc.release()
+
+
+def test_host_tree_refit_urban_block(R, ctx):
+    """The urban block (about 200k triangles) moved by a small scale and
+    shift, refitted on the GPU: the scan equals one over a fresh host build,
+    bit for bit."""
+    import torch
+    s = W.urban_block(n_azimuth=64)
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    try:
+        Vt = (s.vertices.astype(np.float64) * 1.01 + np.array([0.3, -0.2, 0.05])).astype(np.float32)
+        sc.refit(torch.from_numpy(Vt).cuda())
+        st = W.Scene("moved", Vt, s.indices, s.tri_material, s.materials, s.pose, s.params)
+        got = scan(R, ctx, sc, st)
+        fresh = R.Scene(ctx, Vt, s.indices, s.tri_material)
+        try:
+            want = scan(R, ctx, fresh, st)
+        finally:
+            fresh.release()
+        for k in ("records", "accum", "image"):
+            assert np.array_equal(got[k], want[k]), k
+        assert got["stats"]["segments"] == want["stats"]["segments"]
+        assert sc.selfcheck(3000, 5) == 0
+    finally:
+        sc.release()
+
+
 def test_refit_errors(R, ctx):
     import torch
     s = W.tiny_room(n_azimuth=8, rays_per_beam=4)
     host = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    wide = R.Scene(ctx, s.vertices, s.indices, s.tri_material, width=8, max_leaf_size=2)
     gpu = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=1)
     try:
         V = torch.from_numpy(s.vertices).cuda()
         with pytest.raises(R.RadarError) as e:
-            host.refit(V)
-        assert e.value.status == R.RR_ESTATE
-        with pytest.raises(R.RadarError) as e:
-            gpu.refit(V[:-1].contiguous())
+            wide.refit(V)
         assert e.value.status == R.RR_EINVAL
+        for sc in (host, gpu):
+            with pytest.raises(R.RadarError) as e:
+                sc.refit(V[:-1].contiguous())
+            assert e.value.status == R.RR_EINVAL
     finally:
         host.release()
+        wide.release()
         gpu.release()
