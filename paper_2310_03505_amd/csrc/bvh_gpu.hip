@@ -6,7 +6,8 @@
 // traversal kernels read.  Every inner node covers a contiguous range of the
 // sorted triangles, so a subtree of at most max_leaf triangles becomes one
 // leaf without copying.  A refit keeps the tree and recomputes triangles,
-// normals, boxes and node frames from moved vertices.
+// normals, boxes and node frames from moved vertices; a four-wide tree built
+// on the host is refitted the same way, one launch per depth of its nodes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
