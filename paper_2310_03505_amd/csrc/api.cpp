@@ -892,8 +892,10 @@ rr_status rr_bvh_selfcheck(const rr_scene* sc, uint32_t n_rays, uint64_t seed, u
     }
     const float n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2];
     const float n2 = e1[0] * e2[1] - e1[1] * e2[0];
+    // every hittable triangle sits in exactly one leaf; a triangle that a
+    // refit made degenerate stays in its leaf (zero edges, never hit)
     const bool hittable = rr::dot3(n0, n1, n2, n0, n1, n2) > 0.0f;
-    if (hittable != (seen[j] == 1)) ++bad;
+    if (hittable ? seen[j] != 1 : seen[j] > 1) ++bad;
   }
   *mismatches = bad;
   return RR_OK;

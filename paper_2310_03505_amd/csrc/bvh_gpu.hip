@@ -74,6 +74,16 @@ __device__ __forceinline__ float4 aux_of(const GpuBvh& g, uint32_t j, const Tri&
   return make_float4(t.n[0] / len, t.n[1] / len, t.n[2] / len, __uint_as_float((uint32_t)g.M[j]));
 }
 
+// leaf record of triangle `orig`: first vertex and id, the two edges.  A
+// triangle that a refit made degenerate keeps zero edges, so the ray test's
+// determinant is exactly zero and it is never hit (a build leaves it out).
+__device__ __forceinline__ void store_tri(float4* rec, uint32_t orig, const Tri& t) {
+  const float k = t.nn > 0.0f ? 1.0f : 0.0f;
+  rec[0] = make_float4(t.p0[0], t.p0[1], t.p0[2], __uint_as_float(orig));
+  rec[1] = make_float4(k * t.e1[0], k * t.e1[1], k * t.e1[2], 0.0f);
+  rec[2] = make_float4(k * t.e2[0], k * t.e2[1], k * t.e2[2], 0.0f);
+}
+
 __global__ void k_init_misc(uint32_t* misc, bool refit) {
   const uint32_t i = threadIdx.x;
   if (i >= (uint32_t)kMiscWords) return;
@@ -215,9 +225,7 @@ __global__ void __launch_bounds__(kB) k_leaves(GpuBvh g, float4* tris) {
   const uint32_t orig = g.sorted[p];
   Tri t;
   load_tri(g, orig, t);
-  tris[3 * p + 0] = make_float4(t.p0[0], t.p0[1], t.p0[2], __uint_as_float(orig));
-  tris[3 * p + 1] = make_float4(t.e1[0], t.e1[1], t.e1[2], 0.0f);
-  tris[3 * p + 2] = make_float4(t.e2[0], t.e2[1], t.e2[2], 0.0f);
+  store_tri(tris + 3 * p, orig, t);
   float lo[3], hi[3];
   tri_box(t, lo, hi);
   float* b = g.box + 6u * (uint32_t)((m - 1) + p);
@@ -523,9 +531,7 @@ __global__ void __launch_bounds__(kB) k_hr_tris(GpuBvh g, float4* tris, uint32_t
   if (orig >= g.nt) return;
   Tri t;
   load_tri(g, orig, t);
-  tris[3u * li + 0u] = make_float4(t.p0[0], t.p0[1], t.p0[2], __uint_as_float(orig));
-  tris[3u * li + 1u] = make_float4(t.e1[0], t.e1[1], t.e1[2], 0.0f);
-  tris[3u * li + 2u] = make_float4(t.e2[0], t.e2[1], t.e2[2], 0.0f);
+  store_tri(tris + 3u * li, orig, t);
 }
 
 // the nodes of one depth: child boxes (inner children from the deeper level

@@ -247,6 +247,40 @@ def test_host_tree_refit_urban_block(R, ctx):
         sc.release()
 
 
+@pytest.mark.parametrize("builder", [0, 1])
+def test_refit_with_triangles_made_degenerate(R, ctx, builder):
+    """A refit that flattens one cuboid onto a plane and collapses an edge of
+    another makes some triangles exactly degenerate: they stay in their
+    leaves but are never hit, so the scan equals one over a fresh host build
+    (which leaves them out) and the oracle's records."""
+    import torch
+    s = W.tiny_room()
+    V = s.vertices.copy()
+    a = np.unique(s.indices[12:24].reshape(-1))
+    V[a, 0] = V[a, 0].mean(dtype=np.float64).astype(np.float32)
+    f = s.indices[24]
+    V[f[1]] = V[f[0]]
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=builder)
+    try:
+        sc.refit(torch.from_numpy(V).cuda())
+        st = W.Scene("flattened", V, s.indices, s.tri_material, s.materials, s.pose, s.params)
+        got = scan(R, ctx, sc, st)
+        fresh = R.Scene(ctx, V, s.indices, s.tri_material)
+        try:
+            assert fresh.info()["n_hittable"] < s.n_tris
+            want = scan(R, ctx, fresh, st)
+        finally:
+            fresh.release()
+        assert np.array_equal(got["records"], want["records"])
+        assert np.array_equal(got["accum"], want["accum"])
+        ref = oracle.scan_scene(st, records=True, exempt=True, threads=8)
+        ok = ~ref["exempt"]
+        assert not (got["records"][ok] != ref["records"][ok]).any()
+        assert sc.selfcheck(20000, 9) == 0
+    finally:
+        sc.release()
+
+
 def test_refit_errors(R, ctx):
     import torch
     s = W.tiny_room(n_azimuth=8, rays_per_beam=4)
