@@ -230,7 +230,10 @@ rr_status rr_bvh_get_info(const rr_scene* scene, rr_bvh_info* out);
  * keeps its structure and leaf order; triangles, normals, child boxes and
  * node frames are recomputed on the GPU, one launch per tree depth, deepest
  * first, stream-ordered on `stream`, so scans issued after it on that stream
- * see the new geometry.  Either builder's tree can be refitted (a host SAH
+ * see the new geometry.  The caller keeps vertices_dev valid and unchanged
+ * until the refit has run on `stream` (it is read there, not copied on the
+ * call), and orders it after scans of this scene on other streams (the tree
+ * is rewritten in place).  Either builder's tree can be refitted (a host SAH
  * tree keeps its better structure while objects move a little).  A tree
  * built on the GPU refits with no allocation; the first refit of a
  * host-built tree sets up its refit state synchronously (device copies of
