@@ -153,8 +153,8 @@ typedef struct {
                              radix tree, collapsed to four-wide nodes; leaves are
                              subtrees of at most max_leaf_size triangles; width 4
                              and split_pct 0 only) -- about ten times faster to
-                             build, slower to trace, and refittable
-                             (rr_bvh_refit) */
+                             build, slower to trace; either builder's four-wide
+                             tree can be refitted (rr_bvh_refit) */
   uint32_t collapse;      /* host builder, width 4: how the binary SAH tree is
                              collapsed into four-wide nodes.  0: default (2);
                              1: greedy, each node opens its largest-area inner
