@@ -225,13 +225,20 @@ def test_host_tree_refit_follows_moving_objects(R, ctx, opts):
 def test_host_tree_refit_urban_block(R, ctx):
     """The urban block (about 200k triangles) moved by a small scale and
     shift, refitted on the GPU: the scan equals one over a fresh host build,
-    bit for bit."""
+    bit for bit.  Refits after the first allocate no device memory."""
     import torch
     s = W.urban_block(n_azimuth=64)
     sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
     try:
         Vt = (s.vertices.astype(np.float64) * 1.01 + np.array([0.3, -0.2, 0.05])).astype(np.float32)
-        sc.refit(torch.from_numpy(Vt).cuda())
+        V0, V1 = torch.from_numpy(s.vertices).cuda(), torch.from_numpy(Vt).cuda()
+        sc.refit(V0)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        for V in (V1, V0, V1):
+            sc.refit(V)
+        torch.cuda.synchronize()
+        assert torch.cuda.mem_get_info()[0] == free0
         st = W.Scene("moved", Vt, s.indices, s.tri_material, s.materials, s.pose, s.params)
         got = scan(R, ctx, sc, st)
         fresh = R.Scene(ctx, Vt, s.indices, s.tri_material)
