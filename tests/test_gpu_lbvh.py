@@ -164,6 +164,14 @@ def test_refit_follows_moving_objects(R, ctx):
     s = W.tiny_room()
     sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material, builder=1)
     try:
+        # a refit of a GPU-built tree allocates no device memory
+        V0, V1 = torch.from_numpy(s.vertices).cuda(), torch.from_numpy(moved(s, 1)).cuda()
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        for V in (V1, V0):
+            sc.refit(V)
+        torch.cuda.synchronize()
+        assert torch.cuda.mem_get_info()[0] == free0
         for t in (1, 2, 3):
             Vt = moved(s, t)
             sc.refit(torch.from_numpy(Vt).cuda())
