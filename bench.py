@@ -296,8 +296,6 @@ def bench_post(args):
                    "urban_scan_ms": round(fused["plain"], 4),
                    "urban_scan_fused_epilogue_ms": round(fused["fused"], 4)},
         "roofline": roof,
-        "batched": {"scans": len(bscans), "ms_per_scan": round(batch_ms, 4),
-                    "Mray_segments_per_s": round(bst["segments"] / len(bscans) / (batch_ms / 1e3) / 1e6, 1)},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -205,7 +205,11 @@ rr_status rr_destroy(rr_context* ctx);
 const char* rr_last_error(const rr_context* ctx);
 
 /* ---------------------------------------------------------------- scene */
-/* Copy a triangle mesh into the library (host side).  vertices: nv x 3 float
+/* The scene is the triangle mesh every ray of a scan is traced against (Sec.
+ * III-A: rays travel through a triangle mesh of the environment; Sec. III-D:
+ * the ray-tracing engine holds the mesh in an acceleration structure on the
+ * device that computes the scan).
+ * Copy a triangle mesh into the library (host side).  vertices: nv x 3 float
  * (finite, |x| <= 1e7); indices: nt x 3 (each < nv); tri_material: nt ids
  * (checked against the material table at scan time).  nt may be 0.
  * Zero-area triangles are kept but can never be hit (no normal).  ctx may
@@ -217,9 +221,13 @@ rr_status rr_scene_upload(rr_context* ctx, const float* vertices, uint32_t nv,
 
 /* Build the bounding-volume hierarchy on the host (binned SAH, collapsed to
  * four-wide nodes with 8-bit quantised child boxes) and copy nodes and
- * triangles to the context's GPU.  Synchronous.  After it
+ * triangles to the context's GPU.  This is the acceleration structure of the
+ * ray-tracing engine (Sec. III-D, whose run time grows with the logarithm of
+ * the triangle count).  Synchronous.  After it
  * the scene is immutable and may be shared by concurrent scans.  opt may be
- * NULL.  Calling it again rebuilds. */
+ * NULL.  Calling it again rebuilds, which frees the previous device copies:
+ * ESTATE while a graph (rr_graph_create) or a server (rr_server_create) of
+ * this scene exists, since their launches point at those copies. */
 rr_status rr_bvh_build(rr_context* ctx, rr_scene* scene, const rr_bvh_options* opt);
 
 rr_status rr_bvh_get_info(const rr_scene* scene, rr_bvh_info* out);
@@ -255,12 +263,17 @@ rr_status rr_bvh_selfcheck(const rr_scene* scene, uint32_t n_rays, uint64_t seed
                            uint64_t* mismatches);
 
 /* Frees the scene (host and device copies).  The caller must have waited for
- * scans that use it. */
+ * scans that use it.  ESTATE (nothing freed) while a graph or a server of this
+ * scene exists. */
 rr_status rr_scene_release(rr_context* ctx, rr_scene* scene);
 
 /* ---------------------------------------------------------------- scans */
 /* Exact device bytes one scan with these parameters needs as workspace in
- * the default launch mode: two ray queues of N_p * 2^(B-1) rays, the hit
+ * the default launch mode, for memory admission of scan requests.  The sizes
+ * follow the ray tree of Sec. III-A: N_p = n_azimuth * rays_per_beam primaries
+ * (Sec. III-A/B, rays sampled per azimuth), and every interaction may spawn a
+ * reflected and a refracted child until max_bounces interactions, so bounce
+ * level d holds at most N_p * 2^d rays.  Contents: two ray queues of N_p * 2^(B-1) rays, the hit
  * buffer, the fixed-point accumulator, the counters and the traversal-stack
  * spill area.  With rr_tuning.fused = 1 a context also reserves a child pool
  * and hit ring per trace wave (about 1.2 GB) in its own workspace; a
@@ -404,7 +417,9 @@ typedef struct {
   double mseg_per_s;  /* segments / wall_s / 1e6 */
 } rr_server_stats;
 
-/* The material table is copied; the scene must outlive the server. */
+/* The material table is copied; the scene must outlive the server, and
+ * rr_bvh_build / rr_scene_release of it return ESTATE until the server is
+ * destroyed. */
 rr_status rr_server_create(rr_context* ctx, const rr_scene* scene, const rr_material* materials,
                            uint32_t n_materials, const rr_server_options* opt, rr_server** out);
 /* Thread-safe, non-blocking.  image_dev (n_azimuth x n_bins floats) is
@@ -452,7 +467,9 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out);
  * (coordinate descent over refill_lanes, trace_waves_per_cu, pool_rays,
  * tri_batch, fused and shade_batch, each candidate timed with HIP events over `reps` scans
  * on `stream`), keeps the fastest in the context and returns it in *best
- * with its time per scan.  Every candidate produces the same image. */
+ * with its time per scan.  Every candidate produces the same image.  The
+ * one-launch mode (fused = 1) is not a candidate for an air-path scan or an
+ * eight-wide tree, which it does not trace. */
 rr_status rr_autotune(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
                       const rr_sensor_params* params, const rr_material* materials,
                       uint32_t n_materials, float* image_dev, uint32_t reps, rr_tuning* best,
@@ -464,7 +481,10 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* scene, const rr_pose* pos
  * workspace.  rr_graph_launch uploads the per-scan constants (poses, seeds,
  * scan ids and image pointers may change; azimuths, rays per beam, bounces,
  * bins, bin size, beam width and flags must match the scans the graph was
- * created with) and replays the graph on `stream`. */
+ * created with) and replays the graph on `stream`.  The captured launches
+ * point at the scene's device copies: rr_bvh_build and rr_scene_release of
+ * the scene return ESTATE until the graph is destroyed (rr_bvh_refit, which
+ * rewrites the copies in place, stays allowed). */
 typedef struct rr_graph rr_graph;
 rr_status rr_graph_create(rr_context* ctx, const rr_scene* scene, const rr_scan_desc* scans,
                           uint32_t n_scans, const rr_material* materials, uint32_t n_materials,

@@ -721,6 +721,8 @@ rr_status build_on_gpu(rr_context* ctx, rr_scene* sc, uint32_t max_leaf) {
 rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt) {
   if (!sc) return fail(ctx, RR_EINVAL, "scene is NULL");
   if (sc->ctx != ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
+  if (sc->holders.load())
+    return fail(ctx, RR_ESTATE, "%u graph(s) or server(s) still use this scene's BVH", sc->holders.load());
   BvhBuildOptions o;
   if (opt && opt->builder > 1) return fail(ctx, RR_EINVAL, "builder must be 0 (host) or 1 (GPU)");
   if (opt && opt->builder == 1) {
@@ -936,6 +938,8 @@ rr_status rr_bvh_refit(rr_context* ctx, rr_scene* sc, const float* vertices_dev,
 rr_status rr_scene_release(rr_context* ctx, rr_scene* sc) {
   if (!sc) return RR_OK;
   if (sc->ctx != ctx) return fail(ctx, RR_EINVAL, "scene belongs to another context");
+  if (sc->holders.load())
+    return fail(ctx, RR_ESTATE, "%u graph(s) or server(s) still use this scene", sc->holders.load());
   if (ctx) {
     DeviceGuard g(ctx->device);
     free_scene_device(sc);

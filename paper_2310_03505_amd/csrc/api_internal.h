@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,10 @@ struct rr_scene {
   float4* d_tris = nullptr;
   float4* d_aux = nullptr;
   uint64_t dev_bytes = 0;
+  // graphs and servers that hold the device copies (their kernel arguments
+  // or dispatcher point at them): rebuilding or releasing the scene while
+  // any exists would free memory they still read
+  mutable std::atomic<uint32_t> holders{0};
 };
 
 

@@ -27,6 +27,7 @@ struct rr_graph {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool holds_scene = false;  // counted in scene->holders
 };
 
 namespace {
@@ -39,6 +40,7 @@ void graph_free(rr_graph* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   if (g->ws) (void)hipFree(g->ws);
+  if (g->holds_scene) g->scene->holders.fetch_sub(1);
   delete g;
 }
 
@@ -85,6 +87,8 @@ rr_status rr_graph_create(rr_context* ctx, const rr_scene* sc, const rr_scan_des
   rr_graph* g = new rr_graph();
   g->ctx = ctx;
   g->scene = sc;
+  sc->holders.fetch_add(1);
+  g->holds_scene = true;
   g->mats.assign(mats, mats + n_mats);
   std::vector<const rr_sensor_params*> ps(n);
   std::vector<DevScan> scans(n);
@@ -229,6 +233,10 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
               {kTriBatch, 5, &rr_tuning::tri_batch},
               {kFused, 2, &rr_tuning::fused},
               {kShadeBatch, 3, &rr_tuning::shade_batch}};
+  // the one-launch mode traces only plain scans on a four-wide tree; it is
+  // no candidate for air-path scans or an eight-wide tree
+  const bool one_launch_ok = !(params->flags & RR_AIR_PATH) && sc->bvh.width != 8;
+  if (!one_launch_ok && cur.fused == 1) cur.fused = 2;
   double inc = 0.0;
   s = measure(cur, inc);
   for (int pass = 0; pass < 3 && !s; ++pass) {
@@ -236,6 +244,7 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
     for (const Axis& ax : axes) {
       for (size_t i = 0; i < ax.n && !s; ++i) {
         if (cur.*(ax.f) == ax.v[i]) continue;
+        if (ax.f == &rr_tuning::fused && ax.v[i] == 1 && !one_launch_ok) continue;
         rr_tuning t = cur;
         t.*(ax.f) = ax.v[i];
         double ms = 0.0;

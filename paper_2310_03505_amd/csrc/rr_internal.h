@@ -92,7 +92,8 @@ struct DevScan {
 //   a = (o.x, o.y, o.z, L)        L = optical path length so far
 //   b = (d.x, d.y, d.z, g)        g = receive gain of the primary
 //   c = (E lo, E hi, pid, excl)   E float64 energy; pid = primary within the
-//                                 scan; excl = leaf index of the last hit
+//                                 scan; excl = original id of the triangle
+//                                 last hit (0xffffffff for a primary)
 //   m = heap | medium << 8 | scan << 16   (medium 255 = air)
 constexpr uint32_t kAir = 255u;
 constexpr size_t kRayBytes = 16 + 16 + 16 + 4;

@@ -227,6 +227,7 @@ rr_status rr_server_create(rr_context* ctx, const rr_scene* scene, const rr_mate
     sl.h_ctr = static_cast<uint32_t*>(p);
     std::memset(sl.h_ctr, 0, 4 * kCtrHostWords);
   }
+  scene->holders.fetch_add(1);
   s->worker = std::thread(dispatcher, s);
   *out = s;
   return RR_OK;
@@ -352,6 +353,7 @@ rr_status rr_server_destroy(rr_server* s) {
       if (sl.h_ctr) (void)hipHostFree(sl.h_ctr);
     }
   }
+  s->scene->holders.fetch_sub(1);
   delete s;
   return RR_OK;
 }

@@ -190,6 +190,50 @@ def test_offset_moves_origin_off_the_surface(orc):
             assert np.linalg.norm(dp) < 1e-4 * max(1.0, float(np.abs(p).max()))
 
 
+def _steps_along(p: np.float32, k: int) -> np.float32:
+    """p moved |k| representable float32 values towards sign(k) * inf."""
+    target = np.float32(np.inf) if k > 0 else np.float32(-np.inf)
+    for _ in range(abs(k)):
+        p = np.nextafter(p, target, dtype=np.float32)
+    return p
+
+
+def test_offset_ulp_distance_and_published_constants(orc):
+    """Waechter & Binder (Ray Tracing Gems, 2019, ch. 6): away from the origin
+    (|p_i| >= 1/32) the coordinate moves by trunc(256 n_i) representable
+    float32 values in the direction of n_i; closer to it, by the distance
+    n_i / 65536.  The steps are counted with nextafter, not with the bit
+    arithmetic the oracle uses, and the coordinates are chosen on both sides
+    of 1/32 and 1/16 so that another int scale (128), float scale (1/32768)
+    or origin threshold (1/16) fails here."""
+    rng = np.random.default_rng(17)
+    mags = [1.0 / 64, 0.02, 1.0 / 32, 0.04, 0.0625, 0.09, 0.7, 1.0, 3.0, 255.9, 4096.0, 1e6]
+    checked_ulp = checked_near = 0
+    for m in mags:
+        for sign in (1.0, -1.0):
+            for _ in range(6):
+                p = np.array([sign * m * rng.uniform(1.0, 1.2) if m not in (1.0 / 32,) else sign * m,
+                              -sign * m * rng.uniform(1.0, 1.2), sign * m], dtype=np.float32)
+                n = rng.normal(size=3)
+                n = (n / np.linalg.norm(n)).astype(np.float32)
+                q = orc.offset(p, n)
+                for i in range(3):
+                    if abs(float(p[i])) >= 1.0 / 32:
+                        k = int(np.trunc(np.float32(256.0) * n[i]))
+                        want = _steps_along(p[i], k)
+                        checked_ulp += 1
+                    else:
+                        want = np.float32(p[i] + np.float32(n[i] / np.float32(65536.0)))
+                        checked_near += 1
+                    assert q[i] == want, (float(p[i]), float(n[i]), float(q[i]), float(want))
+    assert checked_ulp > 150 and checked_near > 40
+    # an axis-aligned normal at 1/32 exactly: 256 steps, the ulp form
+    p = np.array([1.0 / 32, 0.5, -2.0], dtype=np.float32)
+    q = orc.offset(p, np.array([1.0, 0.0, 0.0], dtype=np.float32))
+    assert q[0] == _steps_along(np.float32(1.0 / 32), 256)
+    assert q[1] == p[1] and q[2] == p[2]
+
+
 # ----------------------------------------------------------------- Snell / Fresnel
 def _dir_at(theta):
     """unit direction hitting the plane with normal (-1,0,0) at incidence theta"""
