@@ -191,6 +191,12 @@ typedef struct {
   rr_pose pose;
   rr_sensor_params params;
   float* image_dev; /* n_azimuth * n_bins floats, row-major [azimuth][bin] */
+  /* Optional (NULL: every primary): n_azimuth * rays_per_beam bytes in device
+   * memory, primary k * rays_per_beam + i traced only if its byte is nonzero
+   * (parity sampling, as the primary_mask of rr_radar_scan_records).  The
+   * image then holds the returns of the traced primaries only.  Read on the
+   * stream when the scans run; the caller keeps it valid until then. */
+  const uint8_t* primary_mask_dev;
 } rr_scan_desc;
 
 /* ---------------------------------------------------------------- context */

@@ -97,7 +97,8 @@ class rr_server_stats(C.Structure):
 
 
 class rr_scan_desc(C.Structure):
-    _fields_ = [("pose", rr_pose), ("params", rr_sensor_params), ("image_dev", C.c_void_p)]
+    _fields_ = [("pose", rr_pose), ("params", rr_sensor_params), ("image_dev", C.c_void_p),
+                ("primary_mask_dev", C.c_void_p)]
 
 
 class rr_post_params(C.Structure):
@@ -356,29 +357,35 @@ def rr_radar_scan_records(ctx, scene, pose: dict, params: dict, materials, prima
     return out
 
 
-def make_scan_descs(scans, images):
+def make_scan_descs(scans, images, masks=None):
+    """masks: optional list of uint8 device tensors (or None) per scan."""
     arr = (rr_scan_desc * len(scans))()
     for i, ((pose, params), img) in enumerate(zip(scans, images)):
-        arr[i] = rr_scan_desc(make_pose(pose), make_params(params), C.c_void_p(img.data_ptr()))
+        m = masks[i] if masks is not None else None
+        arr[i] = rr_scan_desc(make_pose(pose), make_params(params), C.c_void_p(img.data_ptr()),
+                              C.c_void_p(m.data_ptr()) if m is not None else None)
     return arr
 
 
 def rr_batch_workspace_query(scans) -> int:
     arr = (rr_scan_desc * len(scans))()
     for i, (pose, params) in enumerate(scans):
-        arr[i] = rr_scan_desc(make_pose(pose), make_params(params), None)
+        arr[i] = rr_scan_desc(make_pose(pose), make_params(params), None, None)
     out = C.c_size_t()
     _check(load_library().rr_batch_workspace_query(arr, len(scans), C.byref(out)))
     return int(out.value)
 
 
-def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, stream=None):
-    """Many (pose, params) scans in one pass.  Returns (images, stats)."""
+def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, stream=None,
+                        masks=None):
+    """Many (pose, params) scans in one pass.  Returns (images, stats).
+    masks: optional per-scan uint8 device tensors of n_azimuth * rays_per_beam
+    (None entries trace every primary)."""
     import torch
     if images is None:
         images = [torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
                   for _, p in scans]
-    descs = make_scan_descs(scans, images)
+    descs = make_scan_descs(scans, images, masks)
     st = rr_scan_stats() if stats else None
     mats = make_materials(materials)
     _check(load_library().rr_radar_scan_batch(ctx, scene, descs, len(scans), mats, len(materials),
@@ -427,7 +434,7 @@ def rr_autotune(ctx, scene, pose: dict, params: dict, materials, image=None, rep
     return _tuning_dict(t), float(ms.value)
 
 
-def rr_graph_create(ctx, scene, scans, materials, images=None):
+def rr_graph_create(ctx, scene, scans, materials, images=None, masks=None):
     """Captures the launch sequence of these (pose, params) scans.  Returns
     (graph handle, images); the images stay the graph's outputs until a
     launch passes others."""
@@ -435,7 +442,7 @@ def rr_graph_create(ctx, scene, scans, materials, images=None):
     if images is None:
         images = [torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
                   for _, p in scans]
-    descs = make_scan_descs(scans, images)
+    descs = make_scan_descs(scans, images, masks)
     mats = make_materials(materials)
     h = C.c_void_p()
     _check(load_library().rr_graph_create(ctx, scene, descs, len(scans), mats, len(materials),
@@ -443,12 +450,12 @@ def rr_graph_create(ctx, scene, scans, materials, images=None):
     return h, images
 
 
-def rr_graph_launch(graph, scans=None, images=None, stream=None):
+def rr_graph_launch(graph, scans=None, images=None, stream=None, masks=None):
     """Replays the graph; with scans (and their images) the per-scan tables are
     replaced first."""
     if scans is not None and images is None:
         raise ValueError("new scans need their output images")
-    descs = make_scan_descs(scans, images) if scans is not None else None
+    descs = make_scan_descs(scans, images, masks) if scans is not None else None
     _check(load_library().rr_graph_launch(graph, descs, _stream_handle(stream)))
 
 

@@ -1119,6 +1119,7 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
       scans.emplace_back();
       make_scan(descs[i].pose, descs[i].params, scans.back());
       scans.back().image = descs[i].image_dev;
+      scans.back().mask = descs[i].primary_mask_dev;
     }
     rr_scan_stats st{};
     s = run(ctx, sc, scans, ps.data(), mats, n_mats, static_cast<char*>(ctx->ws), ctx->ws_bytes,

@@ -22,6 +22,7 @@ struct rr_graph {
   const rr_scene* scene = nullptr;
   std::vector<rr_sensor_params> params;  // shapes the graph was captured for
   std::vector<rr_material> mats;
+  std::vector<bool> masked;  // scans captured with a primary mask
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t cap_stream = nullptr;
@@ -64,6 +65,7 @@ rr_status graph_upload(rr_graph* g, const rr_scan_desc* d, hipStream_t st) {
     ps[i] = &d[i].params;
     make_scan(d[i].pose, d[i].params, scans[i]);
     scans[i].image = d[i].image_dev;
+    scans[i].mask = d[i].primary_mask_dev;
   }
   return upload_tables(g->ctx, scans, ps.data(), g->mats.data(), (uint32_t)g->mats.size(), g->ws, st,
                        d[0].params.beam_width_rad);
@@ -96,6 +98,8 @@ rr_status rr_graph_create(rr_context* ctx, const rr_scene* sc, const rr_scan_des
     g->params.push_back(descs[i].params);
     make_scan(descs[i].pose, descs[i].params, scans[i]);
     scans[i].image = descs[i].image_dev;
+    scans[i].mask = descs[i].primary_mask_dev;
+    g->masked.push_back(descs[i].primary_mask_dev != nullptr);
   }
   for (uint32_t i = 0; i < n; ++i) ps[i] = &g->params[i];
   Layout L;
@@ -164,6 +168,10 @@ rr_status rr_graph_launch(rr_graph* g, const rr_scan_desc* descs, void* stream) 
         return fail(ctx, RR_EINVAL,
                     "scan %u: azimuths, rays per beam, bins, bounces and the air-path flag must match the "
                     "captured scans", i);
+      // a masked level 0 is compacted by ray generation, an unmasked one is
+      // filled in place: the captured launches differ
+      if ((descs[i].primary_mask_dev != nullptr) != g->masked[i])
+        return fail(ctx, RR_EINVAL, "scan %u: a primary mask must be given exactly when the captured scan had one", i);
     }
     if ((s = graph_upload(g, descs, st))) return s;
   }

@@ -65,26 +65,48 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
-def compare(gpu, ref, cols, n_s, label, mask=None):
-    """records of the listed columns and the image columns"""
+def compare(gpu, ref, cols, n_s, label, mask=None, max_exempt=None):
+    """records of the listed columns and the image columns (P1, P2 raw).
+    Returns (rel-L2, exempt flags of the compared primaries per row)."""
     rows = np.concatenate([np.arange(c * n_s, (c + 1) * n_s) for c in cols])
     g_rec = gpu["records"][rows]
     o_rec = ref["records"]
-    ok = ~ref["exempt"]
-    if mask is not None:
-        ok &= mask[rows].astype(bool)
+    sel = np.ones(len(rows), dtype=bool) if mask is None else mask[rows].astype(bool)
+    ok = sel & ~ref["exempt"]
     diff = (g_rec != o_rec).any(axis=1)
     n_bad = int((diff & ok).sum())
     img = gpu["image"][cols]
     rel = rel_l2(img, ref["image"])
-    # diagnostic: image with exempt primaries masked out on both sides is not
-    # available from one GPU run; report the exempt share instead
-    log(f"{label}: {int(ok.sum())} primaries compared, {n_bad} differ, "
-        f"{int(ref['exempt'].sum())} exempt, image rel-L2 {rel:.3e}")
+    n_sel = int(sel.sum())
+    n_ex = int((sel & ref["exempt"]).sum())
+    share = n_ex / max(n_sel, 1)
+    log(f"{label}: {int(ok.sum())} primaries compared, {n_bad} differ, {n_ex} exempt "
+        f"({share:.2%}; of those {int((diff & sel & ref['exempt']).sum())} differ), image rel-L2 {rel:.3e}")
     if n_bad:
         i = int(np.nonzero(diff & ok)[0][0])
         log("  first differing primary", int(rows[i]), "gpu", g_rec[i].tolist(), "oracle", o_rec[i].tolist())
     assert n_bad == 0
+    assert rel <= REL_L2
+    if max_exempt is not None:
+        assert share <= max_exempt, f"exempt share {share:.2%} above {max_exempt:.2%}"
+    return rel
+
+
+def masked_diagnostic(R, ctx, scene, cols, ref, base_mask=None, label=""):
+    """P2 with the exempt primaries taken out on both sides: the GPU scan and
+    the oracle's scan of the same columns, both with primary mask = sampled
+    and not exempt.  Returns that rel-L2 (it must pass as the raw one does)."""
+    n_az, n_s = scene.params["n_azimuth"], scene.params["rays_per_beam"]
+    rows = np.concatenate([np.arange(c * n_s, (c + 1) * n_s) for c in cols])
+    m = np.zeros(n_az * n_s, dtype=np.uint8)
+    keep = ~ref["exempt"]
+    if base_mask is not None:
+        keep &= base_mask[rows].astype(bool)
+    m[rows[keep]] = 1
+    gpu = gpu_run(R, ctx, scene, mask=m)
+    ref2 = oracle.scan_scene(scene, columns=cols, primary_mask=m, energy=False)
+    rel = rel_l2(gpu["image"][cols], ref2["image"])
+    log(f"{label}: image rel-L2 with exempt primaries masked on both sides {rel:.3e}")
     assert rel <= REL_L2
     return rel
 
@@ -95,7 +117,10 @@ def test_tiny_room_full(R, ctx):
     log("case: tiny room 400 x 64, B = 3")
     gpu = gpu_run(R, ctx, s)
     ref = oracle.scan_scene(s, records=True, exempt=True)
-    compare(gpu, ref, list(range(400)), 64, "tiny room")
+    # the room's flat walls and separate cuboids leave few near-degenerate
+    # primaries (5 of 25,600 at seed 1)
+    compare(gpu, ref, list(range(400)), 64, "tiny room", max_exempt=1e-3)
+    masked_diagnostic(R, ctx, s, list(range(400)), ref, label="tiny room")
     assert gpu["stats"]["segments"] == int(ref["segments"].sum())
     assert gpu["stats"]["overflow"] == 0
 
@@ -179,23 +204,41 @@ def test_urban_block_columns(R, ctx):
     gpu = gpu_run(R, ctx, s)
     cols = [0, 57, 113, 171, 229, 286, 331, 399]
     ref = oracle.scan_scene(s, columns=cols, records=True, exempt=True)
-    compare(gpu, ref, cols, n_s, "urban block")
+    # exemptions here are mostly near-ties at coincident faces (building
+    # floors on the ground grid, stacked car boxes): 234 of 8,192 at seed 2
+    compare(gpu, ref, cols, n_s, "urban block", max_exempt=0.04)
+    masked_diagnostic(R, ctx, s, cols, ref, label="urban block")
     assert gpu["stats"]["overflow"] == 0
 
 
 # ---------------------------------------------------------------- large scene (full config)
 def test_large_scene_sampled_primaries(R, ctx):
+    """The full large-scene configuration (400 x 4096 rays, B = 5) on 1,024
+    seeded primaries over 16 columns.  The sample reaches depth 3 and
+    beyond, and passes refracted children through the glass panels (n =
+    2.0), which is what sets this scene apart from the urban block."""
     s = W.large_scene()
     n_az, n_s = s.params["n_azimuth"], s.params["rays_per_beam"]
     rng = np.random.default_rng(123)
-    cols = [17, 140, 263, 388]
+    cols = [int(c) for c in np.sort(rng.choice(n_az, size=16, replace=False))]
     mask = np.zeros(n_az * n_s, dtype=np.uint8)
     for c in cols:
-        mask[c * n_s + rng.choice(n_s, size=24, replace=False)] = 1
-    log("case: large scene 400 x 4096, B = 5, 96 sampled primaries")
+        mask[c * n_s + rng.choice(n_s, size=64, replace=False)] = 1
+    log("case: large scene 400 x 4096, B = 5, 1024 sampled primaries over 16 columns")
     gpu = gpu_run(R, ctx, s, mask=mask)
-    ref = oracle.scan_scene(s, columns=cols, primary_mask=mask, records=True, exempt=True)
-    compare(gpu, ref, cols, n_s, "large scene", mask=mask)
+    ref = oracle.scan_scene(s, columns=cols, primary_mask=mask, records=True, exempt=True,
+                            threads=min(16, len(cols)))
+    # 42 of 1,024 at seed 123, mostly near-ties at coincident faces
+    compare(gpu, ref, cols, n_s, "large scene", mask=mask, max_exempt=0.06)
+    rows = np.concatenate([np.arange(c * n_s, (c + 1) * n_s) for c in cols])
+    rec = ref["records"][mask[rows].astype(bool)]
+    glass0 = 9 * s.meta["n_base"]   # the panels follow the nine tiles' triangles
+    deep = int((rec[:, 7:] >= 0).any(axis=1).sum())          # heap ids 8.. are depth >= 3
+    through_glass = sum(int(r[h - 1] >= glass0 and r[2 * h] != -2) for r in rec for h in range(1, 16))
+    log(f"large scene: {deep} sampled primaries hit at depth >= 3, {through_glass} refracted "
+        f"children leave glass-panel hits")
+    assert deep >= 512 and through_glass >= 100
+    masked_diagnostic(R, ctx, s, cols, ref, base_mask=mask, label="large scene")
 
 
 # ---------------------------------------------------------------- batch and workspace variants
@@ -499,5 +542,55 @@ def test_server_mix_equals_alone(R, ctx):
         assert 1 <= st["batches"] <= 40
         assert min(lats) > 0 and st["latency_p99_ms"] >= st["latency_p50_ms"] > 0
         log(f"server: {st['batches']} batches for 40 requests, p50 {st['latency_p50_ms']:.2f} ms")
+    finally:
+        sc.release()
+
+
+def test_autotune_air_path_scan(R, ctx):
+    """Autotuning an air-path scan skips the one-launch mode (which does not
+    trace air-path returns) instead of failing on it; the image is unchanged."""
+    import torch
+    s = W.tiny_room(n_azimuth=64, rays_per_beam=16, flags=W.FLAG_BEAM_GAIN | W.FLAG_AIR_PATH)
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    before = R.rr_get_tuning(ctx.handle)
+    try:
+        a, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        torch.cuda.synchronize()
+        t, ms = R.rr_autotune(ctx.handle, sc.handle, s.pose, s.params, s.materials, reps=1)
+        assert t["fused"] == 2 and ms > 0
+        b, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+    finally:
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
+        sc.release()
+
+
+def test_scene_held_by_graph_or_server_is_not_rebuilt(R, ctx):
+    """While a graph or a server points at a scene's device copies, a rebuild
+    or a release of the scene is refused (ESTATE); after they are destroyed
+    both work again."""
+    import torch
+    s = W.tiny_room(n_azimuth=16, rays_per_beam=4)
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    lib = R.load_library()
+    try:
+        g, _ = R.rr_graph_create(ctx.handle, sc.handle, [(s.pose, s.params)], s.materials)
+        with pytest.raises(R.RadarError) as e:
+            R.rr_bvh_build(ctx.handle, sc.handle)
+        assert e.value.status == R.RR_ESTATE
+        assert lib.rr_scene_release(ctx.handle, sc.handle) == R.RR_ESTATE
+        R.rr_graph_launch(g)
+        torch.cuda.synchronize()
+        R.rr_graph_destroy(g)
+        srv = R.rr_server_create(ctx.handle, sc.handle, s.materials)
+        with pytest.raises(R.RadarError) as e:
+            R.rr_bvh_build(ctx.handle, sc.handle)
+        assert e.value.status == R.RR_ESTATE
+        R.rr_server_destroy(srv)
+        R.rr_bvh_build(ctx.handle, sc.handle)
+        im, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        torch.cuda.synchronize()
+        assert float(im.sum()) > 0
     finally:
         sc.release()
