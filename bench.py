@@ -57,8 +57,11 @@ FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 # what they read for a plain 1 GiB device copy (`--copy-calibration`):
 # FETCH_SIZE counts half the bytes a copy reads, WRITE_SIZE all it writes.
 # The figures hold only for the kernel sources they were taken on.
-TRACE_COUNTERS = {}
-TRACE_COUNTERS_SOURCES = None
+TRACE_COUNTERS = {
+    "large_scene_2m": dict(fetch_kib=352692.6, write_kib=173403.7, sq_insts_valu=1037051259.7,
+                           grbm_gui_active_per_xcd=32754717.0 / 8),
+}
+TRACE_COUNTERS_SOURCES = "487ae90e5ab4c858cf4249b0304969241ab79260d5fbaa590a24ede1d15e1216"
 COUNTER_SCALE = dict(fetch_scale=2.0, write_scale=1.0)
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h", "api.cpp")
 
@@ -223,8 +226,8 @@ def roofline_of(res, wname, p):
                               + ctr["write_kib"] * COUNTER_SCALE["write_scale"]))
         hbm_frac = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
         valu_frac = round(ctr["sq_insts_valu"] / (VALU_ISSUE_PEAK * launch_s), 4)
-        if ctr.get("grbm_gui_active"):
-            clock = round(ctr["grbm_gui_active"] / launch_s / 1e9, 3)
+        if ctr.get("grbm_gui_active_per_xcd"):
+            clock = round(ctr["grbm_gui_active_per_xcd"] / launch_s / 1e9, 3)
     roof = dict(bound="vmem", achieved=round(gbs, 1), peak=round(VMEM_PEAK_GBS, 1), unit="GB/s",
                 frac=round(gbs / VMEM_PEAK_GBS, 4), traffic=traffic)
     roof.update(

@@ -71,8 +71,8 @@ def oracle_many(scene, jobs, threads_each):
     def one(job):
         pose, params, cols, mask = job
         return oracle.scan(scene.vertices, scene.indices, scene.tri_material, pose, params,
-                           scene.materials, columns=cols, primary_mask=mask, exempt=True,
-                           energy=False, threads=threads_each)
+                           scene.materials, columns=cols, primary_mask=mask, records=True,
+                           exempt=True, energy=False, threads=threads_each)
     with cf.ThreadPoolExecutor(max(1, CPU // max(threads_each, 1))) as ex:
         return list(ex.map(one, jobs))
 
