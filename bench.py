@@ -246,6 +246,11 @@ def roofline_of(res, wname, p):
         gather_probe=dict(l2_resident_gbs=round(res["gather_l2_gbs"], 1),
                           scene_working_set_gbs=round(res["gather_ws_gbs"], 1),
                           scene_working_set_bytes=int(res["info"]["device_bytes"])),
+        lanes_busy_per_level=[round(a / max(64 * w, 1), 3) for a, w in
+                              zip(cnt["active_lanes"][:p["max_bounces"]], cnt["wave_iters"][:p["max_bounces"]])],
+        tail_iter_share_per_level=[round(t / max(w, 1), 3) for t, w in
+                                   zip(cnt["tail_wave_iters"][:p["max_bounces"]], cnt["wave_iters"][:p["max_bounces"]])],
+        longest_ray_iters_per_level=[int(x) for x in cnt["max_ray_iters"][:p["max_bounces"]]],
         node_visits_per_segment=round(cnt["node_visits"] / max(cnt["rays"], 1), 2),
         tri_tests_per_segment=round(cnt["tri_tests"] / max(cnt["rays"], 1), 2),
         trace_level_ms=[round(x / steps, 4) for x in split["trace_level_ms"][:p["max_bounces"]]],
