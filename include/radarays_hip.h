@@ -306,6 +306,30 @@ rr_status rr_radar_scan_ws(rr_context* ctx, const rr_scene* scene, const rr_pose
                            uint32_t n_materials, float* image_dev, void* workspace_dev,
                            size_t workspace_bytes, rr_scan_stats* stats, void* stream);
 
+/* Allocation-free variant of rr_radar_scan, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same kernels and the same image,
+ * bit for bit; the workspace is a fixed device array of rr_scratch_bytes()
+ * bytes (64 MiB) that the library holds on every device it runs on, from
+ * its load to the end of the process, instead of the context's workspace.
+ * The call makes no hipMalloc, hipFree or other device allocation.  The
+ * traversal-stack spill area in it is sized for the scene's tree (none for
+ * a tree whose worst-case stack fits the 16 LDS entries per lane), so the
+ * scans that fit are those of modest size: a 400 x 64 ray, three-bounce
+ * scan of a small scene needs about 15 MB.  ENOMEM (nothing launched) when
+ * the scan's workspace exceeds the array; EINVAL for an eight-wide tree or
+ * the one-launch mode (rr_tuning.fused = 1).  Every call on one device
+ * shares that device's array, which keeps the last call's contents (each
+ * call's first kernel clears the counters and the accumulator it uses):
+ * calls that overlap on one device, on any streams or contexts, race, so
+ * the caller orders them.  Profiling (rr_profile_enable) is ignored. */
+rr_status rr_radar_scan_noalloc(rr_context* ctx, const rr_scene* scene, const rr_pose* pose,
+                                const rr_sensor_params* params, const rr_material* materials,
+                                uint32_t n_materials, float* image_dev, rr_scan_stats* stats,
+                                void* stream);
+/* Size of the array rr_radar_scan_noalloc works in, bytes. */
+rr_status rr_scratch_bytes(size_t* bytes);
+
 /* Debug/parity variant of rr_radar_scan.  Optional outputs (NULL = skip):
  *  records_dev  int32 [n_azimuth * rays_per_beam][2^B - 1], heap order per
  *               primary (slot h-1 for heap id h; 1 = primary, 2h = reflected

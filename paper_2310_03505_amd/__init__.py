@@ -116,7 +116,7 @@ EXPORTS = (
     "rr_set_tuning", "rr_get_tuning", "rr_server_create", "rr_server_submit", "rr_server_wait",
     "rr_server_poll", "rr_server_get_stats", "rr_server_reset_stats", "rr_server_destroy",
     "rr_autotune", "rr_graph_create", "rr_graph_launch", "rr_graph_destroy", "rr_measure_gather",
-    "rr_postprocess", "rr_radar_scan_post", "rr_bvh_refit",
+    "rr_postprocess", "rr_radar_scan_post", "rr_bvh_refit", "rr_radar_scan_noalloc", "rr_scratch_bytes",
 )
 
 _lib = None
@@ -149,6 +149,9 @@ def load_library():
                                vp, P(rr_scan_stats), vp]),
         "rr_radar_scan_ws": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material),
                                   C.c_uint32, vp, vp, C.c_size_t, P(rr_scan_stats), vp]),
+        "rr_radar_scan_noalloc": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material),
+                                       C.c_uint32, vp, P(rr_scan_stats), vp]),
+        "rr_scratch_bytes": (st, [P(C.c_size_t)]),
         "rr_radar_scan_records": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material),
                                        C.c_uint32, vp, vp, vp, vp, P(rr_scan_stats), vp]),
         "rr_radar_scan_batch": (st, [vp, vp, P(rr_scan_desc), C.c_uint32, P(rr_material),
@@ -326,6 +329,25 @@ def rr_radar_scan_ws(ctx, scene, pose: dict, params: dict, materials, image, wor
                                            C.byref(st) if st is not None else None,
                                            _stream_handle(stream)), ctx)
     return image, (_stats_dict(st) if st is not None else None)
+
+
+def rr_radar_scan_noalloc(ctx, scene, pose: dict, params: dict, materials, image, stats=False, stream=None):
+    """rr_radar_scan on the library's fixed scratch array: no device allocation
+    (the caller passes the output image)."""
+    st = rr_scan_stats() if stats else None
+    mats = make_materials(materials)
+    pr, ps = make_pose(pose), make_params(params)
+    _check(load_library().rr_radar_scan_noalloc(ctx, scene, C.byref(pr), C.byref(ps), mats,
+                                                len(materials), _ptr(image),
+                                                C.byref(st) if st is not None else None,
+                                                _stream_handle(stream)), ctx)
+    return image, (_stats_dict(st) if st is not None else None)
+
+
+def rr_scratch_bytes() -> int:
+    out = C.c_size_t()
+    _check(load_library().rr_scratch_bytes(C.byref(out)))
+    return int(out.value)
 
 
 def rr_radar_scan_records(ctx, scene, pose: dict, params: dict, materials, primary_mask=None,

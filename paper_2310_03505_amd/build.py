@@ -16,7 +16,7 @@ LIB = os.path.join(PKG, "libradarays_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RADARAYS_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "post.hip", "bvh_gpu.hip", "api.cpp", "bvh.cpp", "server.cpp", "graph.cpp"]
+SOURCES = ["kernels.hip", "post.hip", "bvh_gpu.hip", "noalloc.hip", "api.cpp", "bvh.cpp", "server.cpp", "graph.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-x", "hip",

@@ -196,9 +196,6 @@ void make_materials(const rr_material* m, uint32_t n, float beam_width, std::vec
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// lanes whose traversal stack may spill into the workspace: 256 compute
-// units x 32 waves x 64 lanes
-constexpr uint32_t kSpillLanes = 256u * 32u * 64u;
 // fused scan: per-wave child pool and hit ring, for every wave a trace grid
 // can have (kSpillLanes / 64)
 constexpr uint32_t kWqPool = 2048u, kWqHits = 256u;
@@ -207,9 +204,12 @@ constexpr size_t kWqBytes = (size_t)(kSpillLanes / 64u) * (kWqPool + kWqHits) * 
 // Levels alternate between two queues; level d of a scan has at most
 // N_p * 2^d rays, and only scans with B > d have a level d.  The hit buffer
 // holds one (t, leaf) pair per ray of the current level.
-void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool fused) {
+void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool fused,
+                 uint32_t spill_entries, uint32_t spill_lanes) {
   uint64_t level[RR_MAX_BOUNCES] = {};
   L = Layout();
+  L.spill_entries = spill_entries;
+  L.spill_lanes = spill_lanes;
   for (uint32_t i = 0; i < n; ++i) {
     const rr_sensor_params& p = *ps[i];
     uint64_t np = (uint64_t)p.n_azimuth * p.rays_per_beam;
@@ -234,7 +234,7 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool 
   L.off_hits = o;
   o += align256(8 * cap);
   L.off_spill = o;
-  o += align256(sizeof(int32_t) * (size_t)kSpill * kSpillLanes);
+  o += align256(sizeof(int32_t) * (size_t)spill_entries * spill_lanes);
   L.off_wq = o;
   if (fused) o += align256(kWqBytes);
   if (L.air) {
@@ -266,6 +266,18 @@ QueueView queue_at(char* ws, const Layout& L, int q) {
                    reinterpret_cast<uint4*>(ws + L.off_q[q][2]), reinterpret_cast<uint32_t*>(ws + L.off_q[q][3])};
 }
 
+uint32_t trace_grid_blocks(const rr_context* ctx) {
+  uint32_t g = std::max(1u, (uint32_t)ctx->n_cu * ctx->trace_waves_per_cu / (kTraceBlock / 64u));
+  return std::min(g, kSpillLanes / (uint32_t)kTraceBlock);
+}
+
+uint32_t scene_spill_need(const rr_scene* sc) {
+  // in 32-bit words per lane: an eight-wide stack entry (a node group) takes two
+  if (sc->bvh.width == 8)
+    return sc->bvh.max_stack > (uint32_t)kStack8 ? 2u * (sc->bvh.max_stack - (uint32_t)kStack8) : 0u;
+  return sc->bvh.max_stack > (uint32_t)kStack ? sc->bvh.max_stack - (uint32_t)kStack : 0u;
+}
+
 rr_status check_scene(rr_context* ctx, const rr_scene* sc) {
   if (!sc) return fail(ctx, RR_EINVAL, "scene is NULL");
   if (!sc->built) return fail(ctx, RR_ESTATE, "scene has no BVH (call rr_bvh_build)");
@@ -278,10 +290,19 @@ rr_status check_scene(rr_context* ctx, const rr_scene* sc) {
 rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
-              float beam_width_for_mats, uint32_t* counters_host, bool upload, const PostArgs* post) {
+              float beam_width_for_mats, uint32_t* counters_host, bool upload, const PostArgs* post,
+              uint32_t spill_entries) {
   if (post && scans.size() != 1) return fail(ctx, RR_EINVAL, "the fused epilogue takes one scan");
+  // trace: persistent, enough waves to fill every CU
+  const uint32_t trace_grid = trace_grid_blocks(ctx);
   Layout L;
-  make_layout(ps, (uint32_t)scans.size(), L, ctx->fused != 0);
+  if (spill_entries >= (uint32_t)kSpill)
+    make_layout(ps, (uint32_t)scans.size(), L, ctx->fused != 0);
+  else
+    make_layout(ps, (uint32_t)scans.size(), L, ctx->fused != 0, spill_entries, trace_grid * (uint32_t)kTraceBlock);
+  if (scene_spill_need(sc) > L.spill_entries)
+    return fail(ctx, RR_EINVAL, "the spill area holds %u stack entries per lane, the tree needs %u",
+                L.spill_entries, scene_spill_need(sc));
   if (ws_bytes < L.total)
     return fail(ctx, RR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
   if (L.cap >= (1ull << 31) || L.n_first >= (1ull << 31))
@@ -341,9 +362,6 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
   a.prof = (ctx->prof_flags & RR_PROFILE_COUNT) ? ctx->d_prof : nullptr;
   const bool timed_all = (ctx->prof_flags & RR_PROFILE_TIME) != 0;
   const bool timed_trace = timed_all || (ctx->prof_flags & RR_PROFILE_TRACE_TIME) != 0;
-  // trace: persistent, enough waves to fill every CU; raygen/shade: grid-stride
-  uint32_t trace_grid = std::max(1u, (uint32_t)ctx->n_cu * ctx->trace_waves_per_cu / (kTraceBlock / 64u));
-  trace_grid = std::min(trace_grid, kSpillLanes / (uint32_t)kTraceBlock);
   a.refill = ctx->refill_lanes;
   a.pool = ctx->pool_rays;
   a.tri_batch = ctx->tri_batch;
@@ -575,6 +593,12 @@ rr_status rr_create(int device, rr_context** out) {
     return fail(nullptr, RR_ENOMEM, "pinned host buffer: %s", hipGetErrorString(e));
   }
   c->h_ctr = static_cast<uint32_t*>(p);
+  rr_status ss = scratch_setup(device);
+  if (ss) {
+    (void)hipHostFree(p);
+    delete c;
+    return ss;
+  }
   *out = c;
   return RR_OK;
 }

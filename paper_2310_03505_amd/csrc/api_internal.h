@@ -75,6 +75,10 @@ namespace rr {
                   hipGetErrorString(e_));                                                     \
   } while (0)
 
+// lanes whose traversal stack may spill into the workspace: 256 compute
+// units x 32 waves x 64 lanes
+constexpr uint32_t kSpillLanes = 256u * 32u * 64u;
+
 // Workspace layout of a set of scans (see api.cpp).
 struct Layout {
   size_t off_scans = 0, off_mats = 0, off_ctr = 0, off_acc = 0, off_hits = 0, off_spill = 0, off_wq = 0;
@@ -87,6 +91,8 @@ struct Layout {
   uint64_t acc_cells = 0;
   uint64_t n_first = 0;
   uint32_t max_b = 0;
+  uint32_t spill_entries = 0;  // stack entries per lane in the spill area
+  uint32_t spill_lanes = 0;    // lanes the spill area holds
 };
 
 struct DeviceGuard {
@@ -100,8 +106,17 @@ struct DeviceGuard {
   }
 };
 
-// fused: add the per-wave child pools and hit rings of the one-launch mode
-void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool fused = false);
+// fused: add the per-wave child pools and hit rings of the one-launch mode.
+// The spill area holds spill_entries stack entries for each of spill_lanes
+// lanes; the defaults cover any tree the builders accept and any grid.
+void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool fused = false,
+                 uint32_t spill_entries = kSpill, uint32_t spill_lanes = kSpillLanes);
+// Persistent trace blocks of a launch at the context's tuning (the spill
+// area must hold this many blocks' lanes).
+uint32_t trace_grid_blocks(const rr_context* ctx);
+// 32-bit spill words a lane may need beyond its LDS stack when tracing this
+// scene's tree (from the build's worst-case stack need).
+uint32_t scene_spill_need(const rr_scene* sc);
 void make_scan(const rr_pose& pose, const rr_sensor_params& p, DevScan& s);
 rr_status check_params(rr_context* ctx, const rr_sensor_params* p);
 rr_status check_pose(rr_context* ctx, const rr_pose* q);
@@ -114,7 +129,8 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
               const rr_sensor_params* const* ps, const rr_material* mats, uint32_t n_mats, char* ws,
               size_t ws_bytes, rr_scan_stats* stats, hipStream_t st, uint64_t* accum_out,
               float beam_width_for_mats, uint32_t* counters_host = nullptr,
-              bool upload_tables = true, const PostArgs* post = nullptr);
+              bool upload_tables = true, const PostArgs* post = nullptr,
+              uint32_t spill_entries = kSpill);
 // Validates an epilogue parameter block and fills the launch arguments
 // (blur weights included); the caller sets the image pointers and sizes.
 rr_status make_post_args(rr_context* ctx, const rr_post_params* p, PostArgs& a);
@@ -124,5 +140,8 @@ rr_status upload_tables(rr_context* ctx, std::vector<DevScan>& scans, const rr_s
                         const rr_material* mats, uint32_t n_mats, char* ws, hipStream_t st,
                         float beam_width_for_mats);
 rr_status ensure_ws(rr_context* ctx, size_t bytes);
+// Device address of this device's copy of the allocation-free scan's scratch
+// array (noalloc.hip), looked up once per device with that device current.
+rr_status scratch_setup(int device);
 
 }  // namespace rr
