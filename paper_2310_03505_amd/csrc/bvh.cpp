@@ -341,7 +341,9 @@ struct Flattener4 {
     origin = lo;
     double ext = (double)hi - (double)lo;
     // smallest e with ext <= 255 * 2^e, so every child fits in 8 bits
-    int e = -126;
+    // a node with no box at all (every child empty) keeps step 1, so its
+    // inverted empty slots stay far from any ray's interval
+    int e = 0;
     if (ext > 0.0) {
       std::frexp(ext / 255.0, &e);
       while (e > -126 && ext <= 255.0 * std::ldexp(1.0, e - 1)) --e;
@@ -452,6 +454,7 @@ struct Flattener4 {
         ++n_kids;
       }
     }
+    invert_empty_slots(ref, qlo, qhi);
     Node4 nd{};
     uint32_t ebits = eb[0] | (eb[1] << 8) | (eb[2] << 16);
     float ebf;

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(kB) k_head_index(GpuBvh g, const uint32_t* sca
 __device__ __forceinline__ void quantise_axis(float lo, float hi, float& origin, uint32_t& ebyte) {
   origin = lo;
   const double ext = (double)hi - (double)lo;
-  int e = -126;
+  int e = 0;  // a node with no box at all keeps step 1 (see the host build)
   if (ext > 0.0) {
     frexp(ext / 255.0, &e);
     while (e > -126 && ext <= 255.0 * ldexp(1.0, e - 1)) --e;
@@ -358,6 +358,7 @@ __device__ void write_node(Node4* out, const Kid* kids, int n_kids, float pad) {
     }
     ref[j] = kids[j].ref;
   }
+  invert_empty_slots(ref, qlo, qhi);
   Node4 nd;
   nd.w0 = make_float4(origin[0], origin[1], origin[2], __uint_as_float(eb[0] | (eb[1] << 8) | (eb[2] << 16)));
   nd.w1 = make_uint4(qlo[0], qhi[0], qlo[1], qhi[1]);
@@ -536,9 +537,9 @@ __global__ void __launch_bounds__(kB) k_hr_tris(GpuBvh g, float4* tris, uint32_t
 
 // the nodes of one depth: child boxes (inner children from the deeper level
 // just refitted, leaves from their triangles), the quantised node and its
-// own box for its parent.  A slot counts as written by the build if it holds
-// a child or nonzero box bytes (an empty leaf the build quantised as the
-// point 0), so a refit with unmoved vertices rewrites every byte as built.
+// own box for its parent.  All four slots are rewritten; a slot without a
+// child gets the inverted box, as in the builds, so a refit with unmoved
+// vertices rewrites every byte as built.
 __global__ void __launch_bounds__(kB) k_hr_level(GpuBvh g, Node4* nodes, const float4* tris, float* nbox,
                                                  const uint32_t* order, uint32_t first, uint32_t count,
                                                  uint32_t n_nodes, uint32_t n_leaf_tris) {
@@ -549,9 +550,8 @@ __global__ void __launch_bounds__(kB) k_hr_level(GpuBvh g, Node4* nodes, const f
   const float pad = __uint_as_float(g.misc[6]) * (1.0f / 262144.0f);
   const Node4 nd = nodes[id];
   const int32_t refs[4] = {nd.w3.x, nd.w3.y, nd.w3.z, nd.w3.w};
-  const uint32_t qb = nd.w1.x | nd.w1.y | nd.w1.z | nd.w1.w | nd.w2.x | nd.w2.y;
   Kid kids[4];
-  int n_kids = 0;
+  const int n_kids = 4;
   float nlo[3] = {INFINITY, INFINITY, INFINITY}, nhi[3] = {-INFINITY, -INFINITY, -INFINITY};
   for (int j = 0; j < 4; ++j) {
     Kid& kd = kids[j];
@@ -561,7 +561,6 @@ __global__ void __launch_bounds__(kB) k_hr_level(GpuBvh g, Node4* nodes, const f
       kd.lo[a] = INFINITY;
       kd.hi[a] = -INFINITY;
     }
-    if (refs[j] != kEmpty || ((qb >> (8 * j)) & 255u) != 0u) n_kids = j + 1;
     if (refs[j] == kEmpty) continue;
     if (refs[j] >= 0) {
       if ((uint32_t)refs[j] < n_nodes) {

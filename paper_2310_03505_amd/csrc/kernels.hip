@@ -340,101 +340,112 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
       // completion checks run once per run of steps
 #pragma unroll 1
       for (uint32_t step = 0;;) {
-        uint32_t leaves = 0;  // hit leaf children of this lane's node
-        int32_t lref[4] = {0, 0, 0, 0};
-        if (valid && !trav_done) {
-          // top of the LDS stack, read ahead of the decision to pop so the pop
-          // stays an LDS access (entries beyond kStack come from the workspace)
-          const int32_t top = stk[min(max(sp - 1, 0), kStack - 1) * kTraceBlock];
-          if (cur == kEmpty) {
-            if (sp > 0) {
-              --sp;
-              cur = sp < kStack ? top : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
-            } else {
-              trav_done = true;
-            }
-          }
-          if (!trav_done) {
-            const float4* np = reinterpret_cast<const float4*>(nodes + cur);
-            const float4 w0 = np[0];
-            const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
-            const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
-            const int4 w3 = reinterpret_cast<const int4*>(np)[3];
-            if (kCount) ++cnt_nodes;
-            float tn[4];
-            const uint32_t mask = node4_boxes(w0, w1, w2, w3, rb, best_t, tn);
-            const int32_t ref[4] = {w3.x, w3.y, w3.z, w3.w};
-            // hit inner children far to near, everything else last: 5 compare-exchanges
-            float key[4];
-            int32_t val[4];
-    #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const bool h = (mask >> j) & 1u;
-              const bool inner = h && ref[j] >= 0;
-              if (h && ref[j] < 0) leaves |= 1u << j;
-              lref[j] = ref[j];
-              key[j] = inner ? tn[j] : -INFINITY;
-              val[j] = inner ? ref[j] : kEmpty;
-            }
-    #define RR_CX(i, j)                     \
-      if (key[j] > key[i]) {                \
-        const float tk = key[i];            \
-        key[i] = key[j];                    \
-        key[j] = tk;                        \
-        const int32_t tv = val[i];          \
-        val[i] = val[j];                    \
-        val[j] = tv;                        \
-      }
-            RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
-    #undef RR_CX
-            // the nearest hit inner child is visited next; the h - 1 others are
-            // pushed farthest first.  Where three slots are free in LDS all three
-            // are written unconditionally (slots at or above the new top are
-            // unused); otherwise entry by entry, deeper ones into the workspace.
-            // The builder bounds the worst-case depth by kStack + kSpill.
-            const int h = __popc(mask & ~leaves);
-            if (sp + 3 <= kStack) {
-              stk[(sp + 0) * kTraceBlock] = val[0];
-              stk[(sp + 1) * kTraceBlock] = val[1];
-              stk[(sp + 2) * kTraceBlock] = val[2];
-              sp += h > 1 ? h - 1 : 0;
-            } else {
-    #pragma unroll
-              for (int j = 0; j < 3; ++j) {
-                if (j < h - 1 && sp < kStack + kSpill) {
-                  if (sp < kStack)
-                    stk[sp * kTraceBlock] = val[j];
-                  else
-                    A.spill[(size_t)(sp - kStack) * spill_stride + gtid] = val[j];
-                  ++sp;
-                }
-              }
-            }
-            cur = h == 0 ? kEmpty : h == 1 ? val[0] : h == 2 ? val[1] : h == 3 ? val[2] : val[3];
-            // every node is entered at most once per ray; the bound only guards
-            // against a malformed tree
-            if (++visits > A.n_nodes) trav_done = true;
+        // Every lane runs the node step; one without a node to visit (idle,
+        // done, or holding a reference outside the tree) reads the root and
+        // pushes and appends nothing.  Predication instead of a branch keeps
+        // the per-child conditions as wave masks.
+        const bool walk = valid && !trav_done;
+        // top of the LDS stack, read ahead of the decision to pop so the pop
+        // stays an LDS access (entries beyond kStack come from the workspace)
+        const int32_t top = stk[min(max(sp - 1, 0), kStack - 1) * kTraceBlock];
+        // a reference outside the tree (kEmpty: none) takes the next stack
+        // entry; a popped entry still outside it is dropped at the next step
+        if (walk && (uint32_t)cur >= A.n_nodes) {
+          if (sp > 0) {
+            --sp;
+            cur = sp < kStack ? top : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
+          } else {
+            trav_done = true;
           }
         }
-        // hit leaves into the ring, lane by lane: the lane's position is the
-        // exclusive prefix sum of the leaf counts (at most 4, three bits, one
-        // ballot each); most steps hit no leaf and skip it after one ballot.
-        // All lanes take part, so the ring head stays the same in every lane.
-        const uint32_t nleaf = (uint32_t)__popc(leaves);
-        if (__ballot(nleaf != 0u)) {
-          const uint64_t c0 = __ballot(nleaf & 1u), c1 = __ballot(nleaf & 2u), c2 = __ballot(nleaf & 4u);
-          uint32_t p = ring_head + lane_prefix(c0) + 2u * lane_prefix(c1) +
-                       4u * lane_prefix(c2);
+        const bool vis = walk & !trav_done & ((uint32_t)cur < A.n_nodes);
+        const float4* np = reinterpret_cast<const float4*>(nodes + (vis ? cur : 0));
+        const float4 w0 = np[0];
+        const uint4 w1 = reinterpret_cast<const uint4*>(np)[1];
+        const uint4 w2 = reinterpret_cast<const uint4*>(np)[2];
+        const int4 w3 = reinterpret_cast<const int4*>(np)[3];
+        if (kCount && vis) ++cnt_nodes;
+        float tn[4];
+        bool hit[4];
+        node4_slabs(w0, w1, w2, rb, best_t, tn, hit);
+        const int32_t lref[4] = {w3.x, w3.y, w3.z, w3.w};
+        // hit inner children far to near, everything else last: 5 compare-exchanges
+        bool lf[4];
+        float key[4];
+        int32_t val[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if ((leaves >> j) & 1u) {
-              lds_leaf[wib][p & (kLeafRing - 1u)] = (uint32_t)lref[j];
-              lds_own[wib][p & (kLeafRing - 1u)] = (uint8_t)lane;
-              ++p;
+        for (int j = 0; j < 4; ++j) {
+          // bitwise, not short-circuit: no branches around the conditions
+          const bool inner = vis & hit[j] & (lref[j] >= 0);
+          lf[j] = vis & hit[j] & (lref[j] < 0);
+          key[j] = inner ? tn[j] : -INFINITY;
+          val[j] = inner ? lref[j] : kEmpty;
+        }
+#define RR_CX(i, j)                     \
+  if (key[j] > key[i]) {                \
+    const float tk = key[i];            \
+    key[i] = key[j];                    \
+    key[j] = tk;                        \
+    const int32_t tv = val[i];          \
+    val[i] = val[j];                    \
+    val[j] = tv;                        \
+  }
+        RR_CX(0, 1) RR_CX(2, 3) RR_CX(0, 2) RR_CX(1, 3) RR_CX(1, 2)
+#undef RR_CX
+        // h hit inner children sit in entries 0 .. h - 1; the nearest, entry
+        // h - 1, is visited next and the h - 1 others are pushed farthest
+        // first.  Where three slots are free in LDS all three are written
+        // unconditionally (slots at or above the new top are unused, and a
+        // lane that visits nothing pushes nothing); otherwise entry by entry,
+        // deeper ones into the workspace.  The builder bounds the worst-case
+        // depth by kStack + kSpill.
+        const bool m1 = key[1] > -INFINITY, m2 = key[2] > -INFINITY, m3 = key[3] > -INFINITY;
+        const int pushes = (int)m1 + (int)m2 + (int)m3;
+        if (sp + 3 <= kStack) {
+          stk[(sp + 0) * kTraceBlock] = val[0];
+          stk[(sp + 1) * kTraceBlock] = val[1];
+          stk[(sp + 2) * kTraceBlock] = val[2];
+          sp += pushes;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            if (j < pushes && sp < kStack + kSpill) {
+              if (sp < kStack)
+                stk[sp * kTraceBlock] = val[j];
+              else
+                A.spill[(size_t)(sp - kStack) * spill_stride + gtid] = val[j];
+              ++sp;
             }
           }
-          if (nleaf) last_pos = p;
-          ring_head += (uint32_t)__popcll(c0) + 2u * (uint32_t)__popcll(c1) + 4u * (uint32_t)__popcll(c2);
+        }
+        if (vis) {
+          cur = m3 ? val[3] : m2 ? val[2] : m1 ? val[1] : val[0];
+          // every node is entered at most once per ray; the bound only guards
+          // against a malformed tree
+          if (++visits > A.n_nodes) trav_done = true;
+        }
+        // hit leaves into the ring, slot by slot: the lanes with a leaf in slot
+        // j take consecutive entries (one ballot and one prefix count per
+        // slot).  All lanes take part, so the ring head stays the same in
+        // every lane; a lane's leaves all lie before the step's final head.
+        const uint64_t l0 = __ballot(lf[0]), l1 = __ballot(lf[1]);
+        const uint64_t l2 = __ballot(lf[2]), l3 = __ballot(lf[3]);
+        if (l0 | l1 | l2 | l3) {
+          uint32_t p = ring_head;
+          const uint64_t lm[4] = {l0, l1, l2, l3};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (lm[j]) {
+              if (lf[j]) {
+                const uint32_t pos = (p + lane_prefix(lm[j])) & (kLeafRing - 1u);
+                lds_leaf[wib][pos] = (uint32_t)lref[j];
+                lds_own[wib][pos] = (uint8_t)lane;
+              }
+              p += (uint32_t)__popcll(lm[j]);
+            }
+          }
+          if (lf[0] || lf[1] || lf[2] || lf[3]) last_pos = p;
+          ring_head = p;
         }
         if (++step >= kNodeSteps) break;
         const uint64_t still = __ballot(valid && !trav_done);

@@ -35,7 +35,9 @@ constexpr int kSpill = 80;     // further entries per lane in workspace memory
 //   w3 = child refs: inner node index (< 2^30), kEmpty for no child, or a
 //        leaf: bit 31 | (count - 1) << 27 | first leaf triangle (< 2^27)
 // Child j covers origin + q * 2^(e - 127) on each axis, rounded outward from
-// the padded float box, so decoding never shrinks a box.
+// the padded float box, so decoding never shrinks a box.  A slot without a
+// child (ref kEmpty) holds the inverted box qlo = 255, qhi = 0 on every
+// axis, which no ray interval meets (node4_slabs relies on it).
 struct alignas(64) Node4 {
   float4 w0;
   uint4 w1, w2;
@@ -48,6 +50,17 @@ RR_HD int32_t leaf_ref_encode(uint32_t start, uint32_t count) {
   return (int32_t)(0x80000000u | ((count - 1u) << 27) | start);
 }
 RR_HD uint32_t leaf_start(int32_t ref) { return (uint32_t)ref & (kMaxLeafTris - 1u); }
+// Every slot j with ref[j] == kEmpty gets the inverted box: low bytes 255,
+// high bytes 0 on each axis (qlo / qhi hold one byte per slot and axis).
+RR_HD void invert_empty_slots(const int32_t ref[4], uint32_t qlo[3], uint32_t qhi[3]) {
+  for (int j = 0; j < 4; ++j) {
+    if (ref[j] != kEmpty) continue;
+    for (int a = 0; a < 3; ++a) {
+      qlo[a] |= 0xffu << (8 * j);
+      qhi[a] &= ~(0xffu << (8 * j));
+    }
+  }
+}
 RR_HD uint32_t leaf_count(int32_t ref) { return (((uint32_t)ref >> 27) & 15u) + 1u; }
 
 // Leaf-ordered triangle, 48 bytes: v0 with the original id in w, then the
@@ -234,6 +247,40 @@ RR_HD uint32_t node4_boxes(const float4& w0, const uint4& w1, const uint4& w2, c
     if (a <= f * kSlabSlack && ref[j] != kEmpty) mask |= 1u << j;
   }
   return mask;
+}
+
+// The slab tests of node4_boxes without the empty-slot test, for the trace
+// kernel: an empty slot holds an inverted box (see Node4), whose entry
+// distance exceeds its exit distance by at least 255 quantisation steps.
+// hit[j]: child j's box meets [0, tmax]; tn[j]: its entry distance (>= 0).
+RR_HD void node4_slabs(const float4& w0, const uint4& w1, const uint4& w2, const RayBox& r, float tmax,
+                       float tn[4], bool hit[4]) {
+  uint32_t eb;
+#if defined(__HIP_DEVICE_COMPILE__)
+  eb = __float_as_uint(w0.w);
+#else
+  __builtin_memcpy(&eb, &w0.w, 4);
+#endif
+  const float sx = pow2_from_byte(eb & 0xffu) * r.ix;
+  const float sy = pow2_from_byte((eb >> 8) & 0xffu) * r.iy;
+  const float sz = pow2_from_byte((eb >> 16) & 0xffu) * r.iz;
+  const float bx = fmaf(w0.x, r.ix, -r.oix);
+  const float by = fmaf(w0.y, r.iy, -r.oiy);
+  const float bz = fmaf(w0.z, r.iz, -r.oiz);
+  const bool px = r.ix >= 0.0f, py = r.iy >= 0.0f, pz = r.iz >= 0.0f;
+  const uint32_t nx = px ? w1.x : w1.y, fx = px ? w1.y : w1.x;
+  const uint32_t ny = py ? w1.z : w1.w, fy = py ? w1.w : w1.z;
+  const uint32_t nz = pz ? w2.x : w2.y, fz = pz ? w2.y : w2.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float tnx = fmaf(byte_f(nx, j), sx, bx), tfx = fmaf(byte_f(fx, j), sx, bx);
+    const float tny = fmaf(byte_f(ny, j), sy, by), tfy = fmaf(byte_f(fy, j), sy, by);
+    const float tnz = fmaf(byte_f(nz, j), sz, bz), tfz = fmaf(byte_f(fz, j), sz, bz);
+    const float a = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+    const float f = fminf(fminf(tfx, tfy), fminf(tfz, tmax));
+    tn[j] = a;
+    hit[j] = a <= f * kSlabSlack;
+  }
 }
 
 // Eight-wide node, 80 bytes (five 16-byte loads):
