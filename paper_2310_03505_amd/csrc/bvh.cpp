@@ -378,8 +378,12 @@ struct Flattener4 {
     return 0;
   }
 
-  // returns the worst-case stack need of the subtree
-  uint32_t emit(const BNode* b, uint32_t depth, int32_t* ref_out) {
+  // Writes wide node idx (allocated by the caller) for build node b and,
+  // below it, its subtree; returns the worst-case stack need of the subtree.
+  // A node's leaf triangles are appended before any of its inner children
+  // is emitted, and its inner children take consecutive indices (siblings
+  // share cache lines and pages).
+  uint32_t emit(const BNode* b, uint32_t depth, uint32_t idx) {
     std::vector<const BNode*> kids;
     if (optimal) {
       const uint8_t wl = plans[b->plan].wide_l;
@@ -407,8 +411,6 @@ struct Flattener4 {
       kids[(size_t)best] = o->l.get();
       kids.insert(kids.begin() + best + 1, o->r.get());
     }
-    uint32_t idx = (uint32_t)out.nodes.size();
-    out.nodes.emplace_back();
     out.max_depth = std::max(out.max_depth, depth);
     if (root_area > 0.0) out.sah_cost += b->box.area() / root_area;
     // padded child boxes and the node frame
@@ -448,11 +450,20 @@ struct Flattener4 {
         uint32_t cnt;
         leaf_ref(k, &ref[j], &cnt);
         if (cnt) ++n_kids;
-      } else {
-        uint32_t need = emit(k, depth + 1, &ref[j]);
-        need_max = std::max(need_max, need);
-        ++n_kids;
       }
+    }
+    // the inner children: one block of consecutive indices, then their subtrees
+    uint32_t n_inner = 0;
+    for (size_t j = 0; j < kids.size(); ++j) n_inner += is_leaf(kids[j]) ? 0u : 1u;
+    const uint32_t base = (uint32_t)out.nodes.size();
+    out.nodes.resize(out.nodes.size() + n_inner);
+    for (size_t j = 0, k = 0; j < kids.size(); ++j) {
+      if (is_leaf(kids[j])) continue;
+      const uint32_t child = base + (uint32_t)k++;
+      ref[j] = (int32_t)child;
+      uint32_t need = emit(kids[j], depth + 1, child);
+      need_max = std::max(need_max, need);
+      ++n_kids;
     }
     invert_empty_slots(ref, qlo, qhi);
     Node4 nd{};
@@ -464,7 +475,6 @@ struct Flattener4 {
     nd.w2 = uint4{qlo[2], qhi[2], 0u, 0u};
     nd.w3 = int4{ref[0], ref[1], ref[2], ref[3]};
     out.nodes[idx] = nd;
-    *ref_out = (int32_t)idx;
     // every hit child but the nearest is pushed (leaves too); the deepest
     // inner child adds its own need on top
     return (n_kids ? n_kids - 1 : 0) + need_max;
@@ -800,8 +810,8 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
       fl.plans.reserve(2 * (size_t)n + 2);
       fl.plan(root.get());
     }
-    int32_t root_ref;
-    out.max_stack = fl.emit(root.get(), 0, &root_ref);
+    out.nodes.resize(1);
+    out.max_stack = fl.emit(root.get(), 0, 0);
   }
   out.aux = std::move(aux0);
   auto t1 = std::chrono::steady_clock::now();
