@@ -52,16 +52,18 @@ FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
 # Counters of one k_trace dispatch, averaged over the trace dispatches of
 # the timed scans, from rocprofv3 --pmc passes of `bench.py --no-extras
-# --no-cpu-baseline` (FETCH_SIZE, WRITE_SIZE in KiB per dispatch; SQ_INSTS_VALU
-# and GRBM_GUI_ACTIVE per dispatch).  FETCH_SIZE and WRITE_SIZE are scaled by
+# --no-cpu-baseline` (FETCH_SIZE, WRITE_SIZE in KiB per dispatch; SQ_INSTS_VALU,
+# GRBM_GUI_ACTIVE summed over the eight XCDs, TCP_TOTAL_CACHE_ACCESSES_sum and
+# TCP_TCC_READ_REQ_sum per dispatch).  FETCH_SIZE and WRITE_SIZE are scaled by
 # what they read for a plain 1 GiB device copy (`--copy-calibration`):
 # FETCH_SIZE counts half the bytes a copy reads, WRITE_SIZE all it writes.
 # The figures hold only for the kernel sources they were taken on.
 TRACE_COUNTERS = {
-    "large_scene_2m": dict(fetch_kib=352692.6, write_kib=173403.7, sq_insts_valu=1037051259.7,
-                           grbm_gui_active_per_xcd=32754717.0 / 8),
+    "large_scene_2m": dict(fetch_kib=355192.5, write_kib=173686.4, sq_insts_valu=941210266.8,
+                           grbm_gui_active_per_xcd=32525804.1 / 8, tcp_accesses=949780688.7,
+                           tcp_tcc_read_req=76113272.0),
 }
-TRACE_COUNTERS_SOURCES = "487ae90e5ab4c858cf4249b0304969241ab79260d5fbaa590a24ede1d15e1216"
+TRACE_COUNTERS_SOURCES = "a21947f0ca96e3c35770dd679969ef72aa63f57d39d09dad083286b59546c44d"
 COUNTER_SCALE = dict(fetch_scale=2.0, write_scale=1.0)
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h", "api.cpp")
 
@@ -220,7 +222,7 @@ def roofline_of(res, wname, p):
     gbs = bytes_launch / launch_s / 1e9
     tfl = flops_launch / launch_s / 1e12
     ctr = trace_counters(wname)
-    traffic = hbm_frac = valu_frac = clock = None
+    traffic = hbm_frac = valu_frac = clock = l1 = None
     if ctr is not None:
         traffic = int(1024 * (ctr["fetch_kib"] * COUNTER_SCALE["fetch_scale"]
                               + ctr["write_kib"] * COUNTER_SCALE["write_scale"]))
@@ -228,6 +230,10 @@ def roofline_of(res, wname, p):
         valu_frac = round(ctr["sq_insts_valu"] / (VALU_ISSUE_PEAK * launch_s), 4)
         if ctr.get("grbm_gui_active_per_xcd"):
             clock = round(ctr["grbm_gui_active_per_xcd"] / launch_s / 1e9, 3)
+        l1 = dict(accesses_per_launch=ctr["tcp_accesses"],
+                  accesses_per_cu_per_clock=round(ctr["tcp_accesses"] / N_CU / ctr["grbm_gui_active_per_xcd"], 3),
+                  hit_rate=round(1.0 - ctr["tcp_tcc_read_req"] / ctr["tcp_accesses"], 3),
+                  source="TCP_TOTAL_CACHE_ACCESSES_sum, TCP_TCC_READ_REQ_sum (rocprofv3 --pmc)")
     roof = dict(bound="vmem", achieved=round(gbs, 1), peak=round(VMEM_PEAK_GBS, 1), unit="GB/s",
                 frac=round(gbs / VMEM_PEAK_GBS, 4), traffic=traffic)
     roof.update(
@@ -241,6 +247,7 @@ def roofline_of(res, wname, p):
                         peak_insts_per_s=VALU_ISSUE_PEAK,
                         measured_clock_ghz=clock,
                         source="SQ_INSTS_VALU x 4 clocks / (1024 SIMDs x 2.4 GHz x launch time)"),
+        vector_l1=l1,
         alu_fp32=dict(achieved_tflops=round(tfl, 3), peak_tflops=FP32_PEAK_TFLOPS,
                       frac=round(tfl / FP32_PEAK_TFLOPS, 4), flops_per_launch=int(flops_launch)),
         gather_probe=dict(l2_resident_gbs=round(res["gather_l2_gbs"], 1),
@@ -433,7 +440,7 @@ POST_BYTES_PER_PIXEL = 9   # float32 energy read, float32 dB and 8-bit pixel wri
 # same two rocprofv3 --pmc passes and copy-kernel scale as the trace kernel's
 POST_HBM = dict(workload="polar_epilogue_64x400x3776", fetch_kib=198520.1, write_kib=472000.0,
                 fetch_scale=2.0, write_scale=1.0,
-                sources_sha256="25aca0723d84e536dcba3a684e466421b9eda9a926da7bc8e08d0d1a6823a1d7")
+                sources_sha256="16f73445cdf31b59f979432a75fadc0b624845713979e8f2c457a8ed38fe9417")
 POST_SOURCES = ("post.hip", "post.h", "philox.h", "rr_internal.h")
 
 
