@@ -147,6 +147,17 @@ __device__ __forceinline__ double ct_return(const DevMaterial& M, float nfx, flo
   return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
 }
 
+// c^C of the specular lobe of the standard BRDF (Eq. 5) for c in [0, 1],
+// given u = c - 1 (-1 <= u <= 0) in float32: c^C = exp(C log1p(u)).  With
+// the lobe's large exponents (C up to a few thousand) c^C is only
+// non-negligible for c within ~1e-2 of 1, where rounding c itself would
+// cost C ulps of relative accuracy; u keeps its own relative accuracy there.
+// u <= -1 means c <= 0: the lobe is 0 (1 for C = 0, as pow(0, 0)).
+__device__ __forceinline__ float lobe_pow(float u, float C) {
+  if (u <= -1.0f) return C == 0.0f ? 1.0f : 0.0f;
+  return expf(C * log1pf(u));
+}
+
 // Origin offset of Waechter & Binder (Ray Tracing Gems, 2019, ch. 6).
 __device__ __forceinline__ float offset1(float p, float n) {
   const float origin = 1.0f / 32.0f, float_scale = 1.0f / 65536.0f, int_scale = 256.0f;
@@ -826,7 +837,8 @@ struct Shaded {
 // reflection) from hits at depth >= 1 in air, for a visibility ray to decide.
 template <bool kAirPath>
 __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, const float4 b, const uint4 c,
-                                          uint32_t m, uint32_t t_bits, int32_t hit, Shaded& o) {
+                                          uint32_t m, uint32_t t_bits, int32_t hit, Shaded& o,
+                                          const float4* normal = nullptr) {
   const uint32_t heap = m & 0xffu;
   const uint32_t medium = (m >> 8) & 0xffu;
   const uint32_t scan = m >> 16;
@@ -846,7 +858,7 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
   const float dx = b.x, dy = b.y, dz = b.z;
   o.g = b.w;
   const float n_cur = medium == kAir ? 1.0f : A.mats[medium].n;
-  const float4 ax = A.aux[hit];  // per original triangle
+  const float4 ax = normal ? *normal : A.aux[hit];  // per original triangle
   const uint32_t mat = __float_as_uint(ax.w);
   const DevMaterial M = A.mats[mat];
   const float dn = dot3(dx, dy, dz, ax.x, ax.y, ax.z);
@@ -913,7 +925,9 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
   } else {
     double cw = 2.0 * ci * ci - 1.0;
     if (cw < 0.0) cw = 0.0;
-    w = M.a + M.beta * cw + M.s * pow(cw, (double)M.C);
+    // cw - 1 = -2 (1 - cos)(1 + cos), accurate near the specular direction
+    const float u = -2.0f * ((1.0f - cosi) * (1.0f + cosi));
+    w = M.a + M.beta * cw + M.s * (double)lobe_pow(u, M.C);
     w = w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
   }
   const double e_ret = E * R * w;
@@ -951,7 +965,7 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
         } else {
           double ca = (double)o.rdx * sx + (double)o.rdy * sy + (double)o.rdz * sz;
           ca = ca < 0.0 ? 0.0 : (ca > 1.0 ? 1.0 : ca);
-          w_air = M.a + M.beta * ca + M.s * pow(ca, (double)M.C);
+          w_air = M.a + M.beta * ca + M.s * (double)lobe_pow((float)(ca - 1.0), M.C);
           w_air = w_air < 0.0 ? 0.0 : (w_air > 1.0 ? 1.0 : w_air);
         }
         e_air = E * R * w_air;
@@ -1051,20 +1065,44 @@ __global__ void __launch_bounds__(shade_block(kAirPath)) k_shade(LevelArgs A) {
   const uint32_t end = min(begin + per_block, n_in);
   uint32_t cnt_hits = 0;
   uint32_t par = 0;
+  // a step's ray and hit are loaded one step ahead and the hit triangle's
+  // normal (which waits for the hit) during the step before, so neither
+  // load's latency falls inside the step that uses it
+  uint2 hn = make_uint2(0u, 0xffffffffu);
+  float4 an = make_float4(0.0f, 0.0f, 0.0f, 0.0f), bn = an, nn = an;
+  uint4 cn = make_uint4(0u, 0u, 0u, 0u);
+  uint32_t mn = 0;
+  if (begin + threadIdx.x < end) {
+    const uint32_t idx = begin + threadIdx.x;
+    hn = A.hits[idx];
+    an = A.in.a[idx];
+    bn = A.in.b[idx];
+    cn = A.in.c[idx];
+    mn = A.in.m[idx];
+    if ((int32_t)hn.y >= 0) nn = A.aux[hn.y];
+  }
   for (uint32_t base = begin; base < end; base += kShadeLanes, par ^= 1u) {
     const uint32_t idx = base + threadIdx.x;
     const bool active = idx < end;
+    const uint2 h = hn;
+    const float4 a = an, b = bn, nrm = nn;
+    const uint4 c = cn;
+    const uint32_t m = mn;
+    const uint32_t next = idx + kShadeLanes;
+    if (next < end) {
+      hn = A.hits[next];
+      an = A.in.a[next];
+      bn = A.in.b[next];
+      cn = A.in.c[next];
+      mn = A.in.m[next];
+    }
     Shaded o;
     if (active) {
-      const uint2 h = A.hits[idx];
       const int32_t hit = (int32_t)h.y;
-      // loaded whether or not the ray hit, so these loads do not wait for the
-      // hit record
-      const float4 a = A.in.a[idx];
-      const float4 b = A.in.b[idx];
-      shade_hit<kAirPath>(A, a, b, A.in.c[idx], A.in.m[idx], h.x, hit, o);
+      shade_hit<kAirPath>(A, a, b, c, m, h.x, hit, o, &nrm);
       if (kCount && hit >= 0) ++cnt_hits;
     }
+    if (next < end && (int32_t)hn.y >= 0) nn = A.aux[hn.y];
     const bool has_q = o.has_q, has_r = o.has_r, has_t = o.has_t;
     const uint32_t cell = o.cell;
     const unsigned long long qv = o.qv;
