@@ -163,6 +163,13 @@ typedef struct {
                              the expected surface-area cost of node steps and
                              triangle tests.  Ignored by the GPU builder and
                              for width 8. */
+  int32_t spatial_pct;    /* host builder: spatial splits (a reference that
+                             straddles a split plane goes to both sides,
+                             bounded by its triangle's part on each side,
+                             where the surface-area cost says so), extra
+                             triangle references allowed, in percent of the
+                             triangle count: 0 default (10), 1..200, -1 none.
+                             The GPU builder takes 0 or -1. */
 } rr_bvh_options;
 
 typedef struct {

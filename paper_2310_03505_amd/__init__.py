@@ -47,7 +47,8 @@ class rr_material(C.Structure):
 class rr_bvh_options(C.Structure):
     _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32),
                 ("n_threads", C.c_uint32), ("split_pct", C.c_uint32), ("width", C.c_uint32),
-                ("merge_leaves", C.c_uint32), ("builder", C.c_uint32), ("collapse", C.c_uint32)]
+                ("merge_leaves", C.c_uint32), ("builder", C.c_uint32), ("collapse", C.c_uint32),
+                ("spatial_pct", C.c_int32)]
 
 
 class rr_bvh_info(C.Structure):
@@ -254,12 +255,13 @@ def rr_scene_upload(ctx, vertices, indices, tri_material):
 
 def rr_bvh_build(ctx, scene, max_leaf_size: int = 0, sah_bins: int = 0, n_threads: int = 0,
                  split_pct: int = 0, width: int = 0, merge_leaves: int = 0, builder: int = 0,
-                 collapse: int = 0):
+                 collapse: int = 0, spatial_pct: int = 0):
     """builder 0: binned SAH on the host; 1: linear BVH on the GPU.
     collapse (host builder, four-wide): 0 default (cost-optimal), 1 greedy,
-    2 cost-optimal."""
+    2 cost-optimal.  spatial_pct (host builder): spatial-split budget in
+    percent of the triangles, 0 default (10), -1 none."""
     opt = rr_bvh_options(max_leaf_size, sah_bins, n_threads, split_pct, width, merge_leaves, builder,
-                         collapse)
+                         collapse, spatial_pct)
     _check(load_library().rr_bvh_build(ctx, scene, C.byref(opt)), ctx)
 
 

@@ -753,7 +753,7 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
     const uint32_t leaf = opt->max_leaf_size ? opt->max_leaf_size : 2u;
     if (leaf > 16) return fail(ctx, RR_EINVAL, "max_leaf_size out of [1, 16]");
     if (opt->width && opt->width != 4) return fail(ctx, RR_EINVAL, "the GPU builder makes four-wide trees");
-    if (opt->split_pct) return fail(ctx, RR_EINVAL, "the GPU builder does not split triangles");
+    if (opt->split_pct || opt->spatial_pct > 0) return fail(ctx, RR_EINVAL, "the GPU builder does not split triangles");
     sc->built = false;
     return build_on_gpu(ctx, sc, leaf);
   }
@@ -762,6 +762,8 @@ rr_status rr_bvh_build(rr_context* ctx, rr_scene* sc, const rr_bvh_options* opt)
     if (opt->sah_bins) o.bins = opt->sah_bins;
     o.threads = opt->n_threads;
     o.split_pct = opt->split_pct;
+    if (opt->spatial_pct < -1 || opt->spatial_pct > 200) return fail(ctx, RR_EINVAL, "spatial_pct out of [-1, 200]");
+    if (opt->spatial_pct) o.spatial_pct = opt->spatial_pct < 0 ? 0u : (uint32_t)opt->spatial_pct;
     o.width = opt->width ? opt->width : 4u;
     if (opt->merge_leaves > 2) return fail(ctx, RR_EINVAL, "merge_leaves out of [0, 2]");
     o.merge_leaves = opt->merge_leaves != 2;

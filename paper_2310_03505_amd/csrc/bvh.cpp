@@ -112,7 +112,297 @@ struct BNode {
   uint32_t begin = 0, count = 0;  // leaf range in the ref array
   uint32_t span = 0;              // references below an inner node (from begin)
   uint32_t plan = 0;              // cost-optimal collapse: index of the node's Plan
+  std::vector<Ref> items;         // spatial-split build: a leaf's references until they are gathered
   bool leaf() const { return !l; }
+};
+
+// Binned SAH with spatial splits (after Stich, Friedrich and Dietrich,
+// "Spatial splits in bounding volume hierarchies", HPG 2009).  Next to the
+// object split over centroid bins, a node whose two object-split halves
+// overlap also tries splitting space at the planes of bins over its box: a
+// reference that straddles the plane goes to both sides, each copy bounded by
+// the part of its triangle on that side (clipped_bounds), so large triangles
+// stop inflating the boxes of the small ones around them.  The split with the
+// lower surface-area cost wins while the node's allowance of extra references
+// lasts; what a split does not use passes to the two children in proportion
+// to their sizes, so the tree does not depend on the thread count.  Each
+// subtree keeps its references in vectors of its own; gather() lays them out
+// depth-first into one array afterwards.
+constexpr double kSpatialOverlap = 1e-5;  // of the scene box's area
+
+struct SpatialBuilder {
+  const float* V;
+  const uint32_t* F;
+  uint32_t max_leaf, bins;
+  int par_depth;
+  double min_overlap;  // overlap area of the object split that starts a spatial search
+
+  void tri(uint32_t id, double p[3][3]) const {
+    for (int v = 0; v < 3; ++v) {
+      const float* q = V + 3 * (size_t)F[3 * (size_t)id + v];
+      for (int a = 0; a < 3; ++a) p[v][a] = q[a];
+    }
+  }
+
+  // bounds of the part of r's triangle inside r.box with lo <= x_a <= hi
+  bool chop(const Ref& r, int a, double lo, double hi, Box& out) const {
+    double rlo[3], rhi[3];
+    for (int q = 0; q < 3; ++q) {
+      rlo[q] = r.box.lo[q];
+      rhi[q] = r.box.hi[q];
+    }
+    rlo[a] = std::max(rlo[a], lo);
+    rhi[a] = std::min(rhi[a], hi);
+    if (rlo[a] > rhi[a]) return false;
+    double p[3][3];
+    tri(r.id, p);
+    if (!clipped_bounds(p, rlo, rhi, out)) return false;
+    for (int q = 0; q < 3; ++q) {  // never wider than the reference
+      out.lo[q] = std::max(out.lo[q], r.box.lo[q]);
+      out.hi[q] = std::min(out.hi[q], r.box.hi[q]);
+    }
+    return !out.empty();
+  }
+
+  static void set_centroid(Ref& r) {
+    for (int a = 0; a < 3; ++a) r.c[a] = 0.5f * (r.box.lo[a] + r.box.hi[a]);
+  }
+
+  std::unique_ptr<BNode> make_leaf(std::vector<Ref>& v, const Box& box) {
+    auto nd = std::make_unique<BNode>();
+    nd->box = box;
+    nd->count = (uint32_t)v.size();
+    nd->items = std::move(v);
+    return nd;
+  }
+
+  // bin of coordinate x among `bins` bins of width w from lo
+  int bin_of(double x, double lo, double w) const {
+    int b = (int)((x - lo) / w);
+    return std::min<int>(std::max(b, 0), (int)bins - 1);
+  }
+
+  std::unique_ptr<BNode> build(std::vector<Ref> v, int depth, int64_t allow) {
+    const uint32_t n = (uint32_t)v.size();
+    Box box, cb;
+    for (const Ref& r : v) {
+      box.grow(r.box);
+      cb.grow(r.c);
+    }
+    if (n <= 1) return make_leaf(v, box);
+    int budget = 0;
+    while ((1ull << budget) < (uint64_t)((n + max_leaf - 1) / max_leaf)) ++budget;
+    bool median = depth + budget >= kMaxDepth - 1;
+    std::vector<Ref> L, R;
+    int64_t used = 0;
+    if (!median) {
+      // object split: binned SAH over centroids, all three axes
+      double best = INFINITY;
+      int best_axis = -1, best_bin = -1;
+      for (int a = 0; a < 3; ++a) {
+        const float ext = cb.hi[a] - cb.lo[a];
+        if (!(ext > 0.0f)) continue;
+        std::vector<Box> bb(bins);
+        std::vector<uint32_t> cnt(bins, 0);
+        const double k = (double)bins / ext;
+        for (const Ref& r : v) {
+          int bi = std::min<int>(std::max((int)((r.c[a] - cb.lo[a]) * k), 0), (int)bins - 1);
+          bb[bi].grow(r.box);
+          cnt[bi]++;
+        }
+        std::vector<double> rarea(bins, 0.0);
+        std::vector<uint32_t> rcnt(bins, 0);
+        Box acc;
+        uint32_t c = 0;
+        for (int i = (int)bins - 1; i > 0; --i) {
+          acc.grow(bb[i]);
+          c += cnt[i];
+          rarea[i] = acc.empty() ? 0.0 : acc.area();
+          rcnt[i] = c;
+        }
+        Box lacc;
+        uint32_t lc = 0;
+        for (uint32_t i = 0; i + 1 < bins; ++i) {
+          lacc.grow(bb[i]);
+          lc += cnt[i];
+          if (lc == 0 || rcnt[i + 1] == 0) continue;
+          const double cost = lacc.area() * lc + rarea[i + 1] * rcnt[i + 1];
+          if (cost < best) {
+            best = cost;
+            best_axis = a;
+            best_bin = (int)i;
+          }
+        }
+      }
+      // the object split's halves and their overlap
+      Box ol, orr;
+      if (best_axis >= 0) {
+        const int a = best_axis;
+        const double k = (double)bins / (cb.hi[a] - cb.lo[a]);
+        for (const Ref& r : v) {
+          const int bi = std::min<int>(std::max((int)((r.c[a] - cb.lo[a]) * k), 0), (int)bins - 1);
+          (bi <= best_bin ? ol : orr).grow(r.box);
+        }
+      }
+      double overlap = 0.0;
+      if (best_axis >= 0) {
+        Box ov;
+        for (int a = 0; a < 3; ++a) {
+          ov.lo[a] = std::max(ol.lo[a], orr.lo[a]);
+          ov.hi[a] = std::min(ol.hi[a], orr.hi[a]);
+        }
+        overlap = ov.empty() ? 0.0 : ov.area();
+      }
+      // spatial split: bins over the node box, straddling references chopped
+      double sbest = INFINITY;
+      int s_axis = -1, s_bin = -1;
+      if (allow > 0 && (best_axis < 0 || overlap > min_overlap)) {
+        for (int a = 0; a < 3; ++a) {
+          const double lo = box.lo[a], ext = (double)box.hi[a] - lo;
+          if (!(ext > 0.0)) continue;
+          const double w = ext / bins;
+          std::vector<Box> bb(bins);
+          std::vector<uint32_t> ent(bins, 0), ex(bins, 0);
+          for (const Ref& r : v) {
+            const int b0 = bin_of(r.box.lo[a], lo, w), b1 = bin_of(r.box.hi[a], lo, w);
+            if (b0 == b1) {
+              bb[b0].grow(r.box);
+            } else {
+              for (int k = b0; k <= b1; ++k) {
+                Box part;
+                const double plo = k == b0 ? -INFINITY : lo + k * w;
+                const double phi = k == b1 ? INFINITY : lo + (k + 1) * w;
+                if (chop(r, a, plo, phi, part)) bb[k].grow(part);
+              }
+            }
+            ent[b0]++;
+            ex[b1]++;
+          }
+          std::vector<double> rarea(bins, 0.0);
+          std::vector<uint32_t> rcnt(bins, 0);
+          Box acc;
+          uint32_t c = 0;
+          for (int i = (int)bins - 1; i > 0; --i) {
+            acc.grow(bb[i]);
+            c += ex[i];
+            rarea[i] = acc.empty() ? 0.0 : acc.area();
+            rcnt[i] = c;
+          }
+          Box lacc;
+          uint32_t lc = 0;
+          for (uint32_t i = 0; i + 1 < bins; ++i) {
+            lacc.grow(bb[i]);
+            lc += ent[i];
+            const uint32_t rc = rcnt[i + 1];
+            if (lc == 0 || rc == 0 || lc >= n || rc >= n) continue;
+            if ((int64_t)lc + rc - n > allow) continue;
+            const double cost = lacc.area() * lc + rarea[i + 1] * rc;
+            if (cost < sbest) {
+              sbest = cost;
+              s_axis = a;
+              s_bin = (int)i;
+            }
+          }
+        }
+      }
+      const double parea = box.area();
+      const double cost = std::min(best, sbest);
+      const double split_cost = parea > 0.0 ? 1.0 + cost / parea : INFINITY;
+      if (n <= max_leaf && ((best_axis < 0 && s_axis < 0) || (double)n <= split_cost)) return make_leaf(v, box);
+      if (s_axis >= 0 && sbest < best) {
+        const int a = s_axis;
+        const double lo = box.lo[a], w = ((double)box.hi[a] - lo) / bins;
+        const double x = lo + (s_bin + 1) * w;
+        for (const Ref& r : v) {
+          const int b0 = bin_of(r.box.lo[a], lo, w), b1 = bin_of(r.box.hi[a], lo, w);
+          if (b1 <= s_bin) {
+            L.push_back(r);
+          } else if (b0 > s_bin) {
+            R.push_back(r);
+          } else {
+            Box lb, rb;
+            const bool hl = chop(r, a, -INFINITY, x, lb), hr = chop(r, a, x, INFINITY, rb);
+            if (hl) {
+              Ref q = r;
+              q.box = lb;
+              set_centroid(q);
+              L.push_back(q);
+            }
+            if (hr) {
+              Ref q = r;
+              q.box = rb;
+              set_centroid(q);
+              R.push_back(q);
+            }
+            if (!hl && !hr) L.push_back(r);
+          }
+        }
+        if (L.empty() || R.empty()) {
+          L.clear();
+          R.clear();
+        } else {
+          used = (int64_t)L.size() + (int64_t)R.size() - n;
+        }
+      }
+      if (L.empty() && best_axis >= 0) {
+        const int a = best_axis;
+        const double k = (double)bins / (cb.hi[a] - cb.lo[a]);
+        for (const Ref& r : v) {
+          const int bi = std::min<int>(std::max((int)((r.c[a] - cb.lo[a]) * k), 0), (int)bins - 1);
+          (bi <= best_bin ? L : R).push_back(r);
+        }
+        if (L.empty() || R.empty()) {
+          L.clear();
+          R.clear();
+        }
+      }
+      if (L.empty()) median = true;
+    }
+    if (L.empty()) {
+      if (n <= max_leaf && !median) return make_leaf(v, box);
+      int a = 0;
+      for (int q = 1; q < 3; ++q)
+        if (cb.hi[q] - cb.lo[q] > cb.hi[a] - cb.lo[a]) a = q;
+      const uint32_t mid = n / 2;
+      std::nth_element(v.begin(), v.begin() + mid, v.end(), [&](const Ref& x, const Ref& y) {
+        return x.c[a] < y.c[a] || (x.c[a] == y.c[a] && x.id < y.id);
+      });
+      if (n <= max_leaf && budget == 0) return make_leaf(v, box);
+      L.assign(v.begin(), v.begin() + mid);
+      R.assign(v.begin() + mid, v.end());
+    }
+    v.clear();
+    v.shrink_to_fit();
+    auto nd = std::make_unique<BNode>();
+    nd->box = box;
+    const int64_t rest = std::max<int64_t>(allow - used, 0);
+    const int64_t al = (int64_t)((double)rest * (double)L.size() / (double)(L.size() + R.size()));
+    const int64_t ar = rest - al;
+    if (depth < par_depth && n > 4096) {
+      auto fut = std::async(std::launch::async,
+                            [this, &L, depth, al] { return build(std::move(L), depth + 1, al); });
+      nd->r = build(std::move(R), depth + 1, ar);
+      nd->l = fut.get();
+    } else {
+      nd->l = build(std::move(L), depth + 1, al);
+      nd->r = build(std::move(R), depth + 1, ar);
+    }
+    return nd;
+  }
+
+  // depth-first layout of the leaves' references; sets begin / count / span
+  static void gather(BNode* n, std::vector<Ref>& out) {
+    n->begin = (uint32_t)out.size();
+    if (n->leaf()) {
+      out.insert(out.end(), n->items.begin(), n->items.end());
+      n->count = (uint32_t)n->items.size();
+      std::vector<Ref>().swap(n->items);
+      return;
+    }
+    gather(n->l.get(), out);
+    gather(n->r.get(), out);
+    n->span = (uint32_t)out.size() - n->begin;
+  }
 };
 
 // Four-wide collapse plan of one build node (cost-optimal mode): cover[j-1]
@@ -783,7 +1073,16 @@ void build_bvh(const float* V, const uint32_t* F, uint32_t nt, const uint16_t* M
   Builder bld{refs, leaf2, std::max(4u, opt.bins), par_depth};
   std::unique_ptr<BNode> root;
   uint32_t n = (uint32_t)refs.size();
-  if (n >= 2) {
+  if (n >= 2 && opt.spatial_pct > 0) {
+    const double ra = scene.empty() ? 0.0 : scene.area();
+    SpatialBuilder sb{V, F, leaf2, std::max(4u, opt.bins), par_depth, kSpatialOverlap * ra};
+    const int64_t allow = (int64_t)((uint64_t)n * std::min(opt.spatial_pct, 200u) / 100u);
+    root = sb.build(std::move(refs), 0, allow);
+    refs.clear();
+    SpatialBuilder::gather(root.get(), refs);
+    n = (uint32_t)refs.size();
+    out.n_refs = n;
+  } else if (n >= 2) {
     root = bld.build(0, n, 0);
   }
   if (!root || root->leaf()) {

@@ -14,6 +14,7 @@ struct BvhBuildOptions {
   uint32_t bins = 16;
   uint32_t threads = 0;
   uint32_t split_pct = 0;  // early split clipping budget, percent of the triangles
+  uint32_t spatial_pct = 10;  // spatial-split budget (extra references), percent of the triangles; 0 = none
   uint32_t width = 4;      // 4: Node4 tree; 8: Node8 tree
   bool merge_leaves = true;  // binary tree to single triangles, leaves formed by the wide collapse
   uint32_t collapse = 0;     // four-wide collapse: 0 cost-optimal, 1 greedy (largest area opened first)

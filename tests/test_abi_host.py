@@ -151,10 +151,68 @@ def test_host_bvh_collapse(R, collapse, leaf, split, merge):
     assert infos[0]["n_nodes"] == infos[1]["n_nodes"] and infos[0]["sah_cost"] == infos[1]["sah_cost"]
 
 
+def _long_over_clutter(seed=5):
+    """Small random triangles in a 20 m box crossed by long diagonal slivers:
+    the case spatial splits are for."""
+    rng = np.random.default_rng(seed)
+    n_small, n_long = 3000, 24
+    c = rng.uniform(0.0, 20.0, (n_small, 1, 3))
+    small = (c + rng.normal(0.0, 0.15, (n_small, 3, 3))).reshape(-1, 3)
+    a = rng.uniform(0.0, 20.0, (n_long, 3))
+    b = rng.uniform(0.0, 20.0, (n_long, 3))
+    off = rng.normal(0.0, 0.3, (n_long, 3))
+    long_ = np.stack([a, b, a + off], axis=1).reshape(-1, 3)
+    V = np.concatenate([small, long_]).astype(np.float32)
+    n = n_small + n_long
+    F = np.arange(3 * n, dtype=np.uint32).reshape(n, 3)
+    return V, F, np.zeros(n, np.uint16)
+
+
+@pytest.mark.parametrize("width,merge", [(4, 0), (4, 2), (8, 0)])
+def test_host_bvh_spatial_splits(R, width, merge):
+    """Spatial splits (a triangle cut at a plane is referenced by leaves on
+    both sides, each bounded by its part) at several budgets find the
+    brute-force closest hit; with a budget they lower the tree's
+    surface-area cost and add triangle references where large triangles cross
+    small ones, and none are added with -1."""
+    V, F, M = _long_over_clutter()
+    scenes = [(V, F, M, 6000)]
+    for s, n in ((W.tiny_room(), 3000), (W.thin_pillars_scene(), 3000), (W.urban_block(), 800)):
+        scenes.append((s.vertices, s.indices, s.tri_material, n))
+    for k, (v, f, m, n) in enumerate(scenes):
+        infos = {}
+        for sp in (-1, 10, 200):
+            sc = R.Scene(None, v, f, m, spatial_pct=sp, width=width, merge_leaves=merge,
+                         max_leaf_size=2 if width == 4 else 4)
+            infos[sp] = sc.info()
+            assert infos[sp]["max_stack"] <= (96 if width == 4 else 44)
+            assert sc.selfcheck(n, 23) == 0, (k, sp)
+            sc.release()
+        if k == 0:
+            # the slivers' copies sit in more leaves; the cost falls by > 10%
+            assert infos[10]["n_leaves"] > infos[-1]["n_leaves"]
+            assert infos[10]["sah_cost"] < 0.9 * infos[-1]["sah_cost"]
+            assert infos[200]["sah_cost"] <= infos[10]["sah_cost"] * 1.01
+
+
+def test_host_bvh_spatial_splits_thread_independent(R):
+    """The reference allowance passes down the tree by subtree size, so the
+    tree does not depend on the number of build threads."""
+    s = W.urban_block()
+    infos = []
+    for th in (1, 3, 8):
+        sc = R.Scene(None, s.vertices, s.indices, s.tri_material, n_threads=th, spatial_pct=20)
+        infos.append(sc.info())
+        sc.release()
+    for i in infos[1:]:
+        for key in ("n_nodes", "n_leaves", "max_depth", "max_stack", "device_bytes", "sah_cost"):
+            assert i[key] == infos[0][key], key
+
+
 def test_bvh_option_validation(R):
     s = W.tiny_room()
     for bad in (dict(width=6), dict(width=8, max_leaf_size=5), dict(split_pct=201), dict(merge_leaves=3),
-                dict(collapse=3),
+                dict(collapse=3), dict(spatial_pct=201), dict(spatial_pct=-2),
                 dict(builder=2), dict(builder=1), dict(builder=1, width=8, max_leaf_size=2)):
         with pytest.raises(R.RadarError) as e:
             R.Scene(None, s.vertices, s.indices, s.tri_material, **bad)
