@@ -193,8 +193,30 @@ def test_refit_follows_moving_objects(R, ctx):
         sc.release()
 
 
+def test_spatial_split_trees_keep_records(R, ctx):
+    """Trees without spatial splits, with the default budget and with a large
+    one give the urban block the same hit records, accumulator and image
+    bit for bit: a triangle referenced by several leaves is hit at the same
+    (t, original id) wherever it is tested."""
+    s = W.urban_block()
+    runs = {}
+    for sp in (-1, 0, 100):
+        sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material, spatial_pct=sp)
+        try:
+            info = sc.info()
+            runs[sp] = scan(R, ctx, sc, s)
+            log(f"  spatial_pct {sp}: {info['n_nodes']} nodes, {info['n_leaves']} leaves, "
+                f"cost {info['sah_cost']:.3f}")
+        finally:
+            sc.release()
+    for sp in (0, 100):
+        for k in ("records", "accum", "image"):
+            assert np.array_equal(runs[sp][k], runs[-1][k]), (sp, k)
+
+
 @pytest.mark.parametrize("opts", [dict(), dict(collapse=1), dict(merge_leaves=2, max_leaf_size=4),
-                                  dict(split_pct=50)], ids=["optimal", "greedy", "binary-leaves", "split"])
+                                  dict(split_pct=50), dict(spatial_pct=-1)],
+                         ids=["optimal", "greedy", "binary-leaves", "split", "no-spatial"])
 def test_host_tree_refit_follows_moving_objects(R, ctx, opts):
     """A host-built SAH tree refitted on the GPU: scans over it give the
     records and accumulator of a fresh host build over the moved vertices
