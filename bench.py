@@ -537,8 +537,9 @@ def bench_post(args):
 
 
 def bench_build(args):
-    """BVH build on the GPU (linear BVH) against the host SAH build, on the
-    urban block (0.2 M triangles) and the large scene (2 M): build time,
+    """BVH build on the GPU (linear BVH) against the host SAH build (without
+    spatial splits: the tree one refits), on the urban block (0.2 M
+    triangles) and the large scene (2 M): build time,
     refit time of both trees (HIP events around rr_bvh_refit after moving
     every vertex), and the urban scan over each tree."""
     import numpy as np
@@ -550,7 +551,9 @@ def bench_build(args):
     rows = {}
     for name, scene in (("urban_block_200k", W.urban_block()), ("large_scene_2m", W.large_scene())):
         log(f"bench: BVH builds on {name}")
-        host = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+        # a tree meant for refitting: no spatial splits (a refit bounds every
+        # reference by its whole triangle, which would undo them)
+        host = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material, spatial_pct=-1)
         hinfo = host.info()
         gpu_ms = []
         for _ in range(max(args.warmup, 1) + 3):
