@@ -491,7 +491,7 @@ typedef struct {
                               default 24 GiB) */
   uint32_t tri_batch;      /* leaves a trace wave queues before it tests their
                              triangles in one step, one leaf per lane (1..64,
-                             default 16) */
+                             default 6) */
   uint32_t fused;          /* 0: default (2); 1: every bounce level in one
                              persistent launch, each wave tracing and shading
                              its own rays' children; 2: one trace and one shade

@@ -1180,7 +1180,7 @@ rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   if (t->shade_batch > 64) return fail(ctx, RR_EINVAL, "shade_batch out of [1, 64]");
   ctx->fused = t->fused == 1 ? 1u : 0u;
   ctx->shade_batch = t->shade_batch ? t->shade_batch : 64u;
-  ctx->tri_batch = t->tri_batch ? t->tri_batch : 16u;
+  ctx->tri_batch = t->tri_batch ? t->tri_batch : 6u;
   return RR_OK;
 }
 

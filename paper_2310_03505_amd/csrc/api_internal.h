@@ -35,7 +35,7 @@ struct rr_context {
   uint32_t refill_lanes = 8;
   uint32_t trace_waves_per_cu = 24;
   uint32_t pool_rays = 64;
-  uint32_t tri_batch = 16;  // queued leaves that start a triangle phase
+  uint32_t tri_batch = 6;   // queued leaves that start a triangle phase
   uint32_t fused = 0;       // 1: all bounce levels in one persistent launch
   uint32_t shade_batch = 64;  // fused: finished rays that start a shade phase
   size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group

@@ -228,7 +228,7 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   static const uint32_t kRefill[] = {4, 8, 12, 16, 24, 32, 48};
   static const uint32_t kWaves[] = {8, 12, 16, 20, 24, 32};
   static const uint32_t kPool[] = {64, 128, 256};
-  static const uint32_t kTriBatch[] = {8, 16, 32, 48, 64};
+  static const uint32_t kTriBatch[] = {4, 6, 8, 16, 32};
   static const uint32_t kFused[] = {1, 2};  // one launch per scan, one per level
   static const uint32_t kShadeBatch[] = {16, 32, 64};
   struct Axis {

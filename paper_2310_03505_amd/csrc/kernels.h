@@ -95,10 +95,12 @@ constexpr int kShadeBlock = 512;
 constexpr int kShadeBlockAir = 256;
 constexpr int shade_block(bool air) { return air ? kShadeBlockAir : kShadeBlock; }
 constexpr uint32_t kMaxLevels = 8;   // bounce levels (interactions per path) at most
-constexpr uint32_t kLeafRing = 512;
+constexpr uint32_t kLeafRing = 256;  // four-wide trace: leaf entries per wave (power of two)
+// a node step appends up to four leaves per lane and runs only while they fit
+static_assert(kLeafRing >= 4u * 64u && (kLeafRing & (kLeafRing - 1u)) == 0u, "leaf ring size");
 constexpr uint32_t kNodeSteps = 6;   // four-wide trace: node steps per refill/triangle decision at most
 constexpr uint32_t kLeafRing8 = 1024;  // eight-wide trace: leaf entries per wave (power of two)
-constexpr int kStack8 = 6;              // eight-wide trace: node groups per lane in LDS  // trace: leaf entries per wave in LDS (power of two)
+constexpr int kStack8 = 6;              // eight-wide trace: node groups per lane in LDS
 constexpr int kTraceBlock = 128;  // trace workgroup (LDS stack of kStack words per lane)
 
 }  // namespace rr

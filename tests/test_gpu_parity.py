@@ -450,7 +450,7 @@ def test_autotune_keeps_images(R, ctx):
         assert ms > 0
         assert t["refill_lanes"] in (4, 8, 12, 16, 24, 32, 48)
         assert t["trace_waves_per_cu"] in (8, 12, 16, 20, 24, 32)
-        assert t["pool_rays"] in (64, 128, 256) and t["tri_batch"] in (8, 16, 32, 48, 64)
+        assert t["pool_rays"] in (64, 128, 256) and t["tri_batch"] in (4, 6, 8, 16, 32)
         assert t["fused"] in (1, 2) and t["shade_batch"] in (16, 32, 64)
         assert R.rr_get_tuning(ctx.handle) == t
         b, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
