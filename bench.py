@@ -271,10 +271,11 @@ def run_trajectory(R, ctx, which: str, steps: int, large=None):
     """64 poses along a spline through the large scene (each with its own
     azimuth count in {100, 400, 800} and rays per beam in {256, 1024, 4096},
     B = 5), or 64 seeded poses in the tiny room at its own settings (400 x 64
-    rays, B = 3).  Launch parameters autotuned on the first pose; then the
-    scans as batched launches (groups bounded by the workspace budget), as
-    HIP graphs of those groups replayed with the same tables, and one
-    rr_radar_scan at a time."""
+    rays, B = 3).  Launch parameters autotuned on a batched launch (the
+    whole tiny-room set; the first eight large-scene poses, to bound the
+    tuning time); then the scans as batched launches (groups bounded by the
+    workspace budget), as HIP graphs of those groups replayed with the same
+    tables, and one rr_radar_scan at a time."""
     import torch
     import workloads as W
     own = large is None or which == "tiny"
@@ -294,8 +295,9 @@ def run_trajectory(R, ctx, which: str, steps: int, large=None):
             for _, p in scans]
     singles = [torch.empty_like(x) for x in imgs]
     graphed = [torch.empty_like(x) for x in imgs]
-    tuned, tuned_ms = R.rr_autotune(c, s, scans[0][0], scans[0][1], scene.materials, reps=2)
-    log(f"autotuned on pose 0: {tuned} ({tuned_ms:.3f} ms)")
+    tune_on = scans if which == "tiny" else scans[:8]
+    tuned, tuned_ms = R.rr_autotune_batch(c, s, tune_on, scene.materials, reps=2)
+    log(f"autotuned on a batch of {len(tune_on)} poses: {tuned} ({tuned_ms:.3f} ms per batch)")
     _, st = R.rr_radar_scan_batch(c, s, scans, scene.materials, images=imgs, stats=True)
     segs = st["segments"]
     steps = max(1, min(steps, 3))
@@ -330,6 +332,10 @@ def run_trajectory(R, ctx, which: str, steps: int, large=None):
     graph_ms = timed(replay)
     for g in graphs:
         R.rr_graph_destroy(g)
+    # one scan per launch at the parameters that suit one scan: autotuned
+    # on the first pose alone
+    tuned_single, _ = R.rr_autotune(c, s, scans[0][0], scans[0][1], scene.materials, reps=2)
+    log(f"autotuned on pose 0 alone: {tuned_single}")
     for (pose, p), im in zip(scans, singles):           # warm the single-scan workspace
         R.rr_radar_scan(c, s, pose, p, scene.materials, image=im)
 
@@ -351,7 +357,8 @@ def run_trajectory(R, ctx, which: str, steps: int, large=None):
                 single_scan_ms=round(single_ms, 3),
                 single_scan_mseg_per_s=round(segs / (single_ms / 1e3) / 1e6, 2),
                 batch_speedup=round(single_ms / batch_ms, 3), graph_speedup=round(single_ms / graph_ms, 3),
-                tuning=tuned, groups=len(groups),
+                tuning=tuned, tuned_on=f"a batched launch of {len(tune_on)} of the poses",
+                single_scan_tuning=tuned_single, groups=len(groups),
                 batch_images_equal_single=same, graph_images_equal_batch=same_graph)
 
 

@@ -516,6 +516,16 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* scene, const rr_pose* pos
                       uint32_t n_materials, float* image_dev, uint32_t reps, rr_tuning* best,
                       double* best_ms, void* stream);
 
+/* As rr_autotune for a batch (the many-pose use of Sec. IV): each candidate
+ * is timed on rr_radar_scan_batch over these scans, so the parameters suit
+ * the batched launch rather than one of its scans (a launch-bound scan
+ * alone prefers fewer trace waves than a batch of them).  *best_ms is the
+ * time per batch.  The images of the descriptors are overwritten; the scans
+ * must be valid for rr_radar_scan_batch (EINVAL otherwise, nothing kept). */
+rr_status rr_autotune_batch(rr_context* ctx, const rr_scene* scene, const rr_scan_desc* scans,
+                            uint32_t n_scans, const rr_material* materials, uint32_t n_materials,
+                            uint32_t reps, rr_tuning* best, double* best_ms, void* stream);
+
 /* ---------------------------------------------------------------- graphs */
 /* A HIP graph holding the complete launch sequence of a batch of scans
  * (clear, ray generation, trace and shade per level, finalize) with its own

@@ -118,6 +118,7 @@ EXPORTS = (
     "rr_server_poll", "rr_server_get_stats", "rr_server_reset_stats", "rr_server_destroy",
     "rr_autotune", "rr_graph_create", "rr_graph_launch", "rr_graph_destroy", "rr_measure_gather",
     "rr_postprocess", "rr_radar_scan_post", "rr_bvh_refit", "rr_radar_scan_noalloc", "rr_scratch_bytes",
+    "rr_autotune_batch",
 )
 
 _lib = None
@@ -171,6 +172,8 @@ def load_library():
         "rr_server_destroy": (st, [vp]),
         "rr_autotune": (st, [vp, vp, P(rr_pose), P(rr_sensor_params), P(rr_material), C.c_uint32,
                              vp, C.c_uint32, P(rr_tuning), P(C.c_double), vp]),
+        "rr_autotune_batch": (st, [vp, vp, P(rr_scan_desc), C.c_uint32, P(rr_material), C.c_uint32,
+                                   C.c_uint32, P(rr_tuning), P(C.c_double), vp]),
         "rr_graph_create": (st, [vp, vp, P(rr_scan_desc), C.c_uint32, P(rr_material), C.c_uint32,
                                  P(vp)]),
         "rr_graph_launch": (st, [vp, P(rr_scan_desc), vp]),
@@ -455,6 +458,23 @@ def rr_autotune(ctx, scene, pose: dict, params: dict, materials, image=None, rep
                                       C.byref(make_params(params)), mats, len(materials),
                                       _ptr(image), reps, C.byref(t), C.byref(ms),
                                       _stream_handle(stream)), ctx)
+    return _tuning_dict(t), float(ms.value)
+
+
+def rr_autotune_batch(ctx, scene, scans, materials, images=None, reps: int = 2, stream=None):
+    """Times candidate launch parameters on rr_radar_scan_batch over these
+    (pose, params) scans and keeps the fastest.  Returns (tuning dict, ms per
+    batch)."""
+    import torch
+    if images is None:
+        images = [torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+                  for _, p in scans]
+    descs = make_scan_descs(scans, images)
+    t = rr_tuning()
+    ms = C.c_double()
+    mats = make_materials(materials)
+    _check(load_library().rr_autotune_batch(ctx, scene, descs, len(scans), mats, len(materials), reps,
+                                            C.byref(t), C.byref(ms), _stream_handle(stream)), ctx)
     return _tuning_dict(t), float(ms.value)
 
 

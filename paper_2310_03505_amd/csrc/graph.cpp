@@ -184,22 +184,17 @@ rr_status rr_graph_destroy(rr_graph* g) {
   return RR_OK;
 }
 
-// Coordinate descent over the trace launch parameters.  Each candidate is
-// timed over `reps` scans after one untimed scan; a parameter keeps its new
-// value only when it beats the incumbent by more than 1%, and the descent
-// stops after a pass without change (at most three passes).
-rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, const rr_sensor_params* params,
-                      const rr_material* mats, uint32_t n_mats, float* image_dev, uint32_t reps, rr_tuning* best,
-                      double* best_ms, void* stream) {
-  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
-  if (!image_dev) return fail(ctx, RR_EINVAL, "image_dev is NULL");
-  if (reps == 0 || reps > 1000) return fail(ctx, RR_EINVAL, "reps out of [1, 1000]");
-  rr_status s;
-  if ((s = check_scene(ctx, sc)) || (s = check_params(ctx, params)) || (s = check_pose(ctx, pose)) ||
-      (s = check_materials(ctx, mats, n_mats, sc)))
-    return s;
-  DeviceGuard dg(ctx->device);
-  hipStream_t st = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+// Coordinate descent over the trace launch parameters.  `run_once` enqueues
+// the workload on `st`; each candidate is timed over `reps` runs after one
+// untimed run; a parameter keeps its new value only when it beats the
+// incumbent by more than 1%, and the descent stops after a pass without
+// change (at most three passes).  On success the fastest tuning stays set.
+template <class Run>
+static rr_status tune(rr_context* ctx, hipStream_t st, uint32_t reps, bool one_launch_ok, Run&& run_once,
+                      rr_tuning* best, double* best_ms) {
+  rr_status s = RR_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(ctx, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -216,7 +211,7 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
     if (r) return r;
     for (uint32_t k = 0; k <= reps; ++k) {
       if (k == 1 && hipEventRecord(e0, st) != hipSuccess) return fail(ctx, RR_EDEVICE, "hipEventRecord failed");
-      if ((r = rr_radar_scan(ctx, sc, pose, params, mats, n_mats, image_dev, nullptr, stream))) return r;
+      if ((r = run_once())) return r;
     }
     if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
       return fail(ctx, RR_EDEVICE, "event wait failed");
@@ -241,9 +236,6 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
               {kTriBatch, 5, &rr_tuning::tri_batch},
               {kFused, 2, &rr_tuning::fused},
               {kShadeBatch, 3, &rr_tuning::shade_batch}};
-  // the one-launch mode traces only plain scans on a four-wide tree; it is
-  // no candidate for air-path scans or an eight-wide tree
-  const bool one_launch_ok = !(params->flags & RR_AIR_PATH) && sc->bvh.width != 8;
   if (!one_launch_ok && cur.fused == 1) cur.fused = 2;
   double inc = 0.0;
   s = measure(cur, inc);
@@ -280,6 +272,45 @@ rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, 
   if (best) *best = cur;
   if (best_ms) *best_ms = inc;
   return RR_OK;
+}
+
+extern "C" {
+
+rr_status rr_autotune(rr_context* ctx, const rr_scene* sc, const rr_pose* pose, const rr_sensor_params* params,
+                      const rr_material* mats, uint32_t n_mats, float* image_dev, uint32_t reps, rr_tuning* best,
+                      double* best_ms, void* stream) {
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  if (!image_dev) return fail(ctx, RR_EINVAL, "image_dev is NULL");
+  if (reps == 0 || reps > 1000) return fail(ctx, RR_EINVAL, "reps out of [1, 1000]");
+  rr_status s;
+  if ((s = check_scene(ctx, sc)) || (s = check_params(ctx, params)) || (s = check_pose(ctx, pose)) ||
+      (s = check_materials(ctx, mats, n_mats, sc)))
+    return s;
+  DeviceGuard dg(ctx->device);
+  // the one-launch mode traces only plain scans on a four-wide tree; it is
+  // no candidate for air-path scans or an eight-wide tree
+  const bool one_launch_ok = !(params->flags & RR_AIR_PATH) && sc->bvh.width != 8;
+  return tune(ctx, static_cast<hipStream_t>(stream), reps, one_launch_ok,
+              [&] { return rr_radar_scan(ctx, sc, pose, params, mats, n_mats, image_dev, nullptr, stream); }, best,
+              best_ms);
+}
+
+rr_status rr_autotune_batch(rr_context* ctx, const rr_scene* sc, const rr_scan_desc* scans, uint32_t n_scans,
+                            const rr_material* mats, uint32_t n_mats, uint32_t reps, rr_tuning* best,
+                            double* best_ms, void* stream) {
+  if (!ctx) return fail(nullptr, RR_EINVAL, "context is NULL");
+  if (!scans || n_scans == 0 || n_scans > 65535) return fail(ctx, RR_EINVAL, "need 1..65535 scans");
+  if (reps == 0 || reps > 1000) return fail(ctx, RR_EINVAL, "reps out of [1, 1000]");
+  rr_status s;
+  if ((s = check_scene(ctx, sc)) || (s = check_materials(ctx, mats, n_mats, sc))) return s;
+  bool air = false;
+  for (uint32_t i = 0; i < n_scans; ++i) air = air || (scans[i].params.flags & RR_AIR_PATH) != 0;
+  DeviceGuard dg(ctx->device);
+  const bool one_launch_ok = !air && sc->bvh.width != 8;
+  // the batch call validates the scans (and fails the first candidate otherwise)
+  return tune(ctx, static_cast<hipStream_t>(stream), reps, one_launch_ok,
+              [&] { return rr_radar_scan_batch(ctx, sc, scans, n_scans, mats, n_mats, nullptr, stream); }, best,
+              best_ms);
 }
 
 }  // extern "C"

@@ -462,6 +462,41 @@ def test_autotune_keeps_images(R, ctx):
         sc.release()
 
 
+def test_autotune_batch_keeps_images(R, ctx):
+    """The batch autotuner times its candidates on the batched launch of
+    scans of different shapes (one with the air path) and keeps the fastest;
+    every batched image is the same bit for bit before and after, and each
+    equals its scan alone."""
+    import torch
+    s = W.tiny_room()
+    scans = []
+    for i, (naz, ns, b, fl) in enumerate([(64, 32, 3, 0), (100, 16, 2, W.FLAG_AIR_PATH), (37, 64, 4, 0)]):
+        p = W.sensor_params(naz, ns, b, 1024, bin_size_m=0.044, scan_id=7 + i, seed=31,
+                            flags=W.FLAG_BEAM_GAIN | fl)
+        scans.append((W.yaw_pose((0.4 * i, -0.3, 0.0), 0.5 * i), p))
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    before = R.rr_get_tuning(ctx.handle)
+    try:
+        a, _ = R.rr_radar_scan_batch(ctx.handle, sc.handle, scans, s.materials)
+        torch.cuda.synchronize()
+        t, ms = R.rr_autotune_batch(ctx.handle, sc.handle, scans, s.materials, reps=1)
+        assert ms > 0
+        assert t["refill_lanes"] in (4, 8, 12, 16, 24, 32, 48)
+        assert t["trace_waves_per_cu"] in (8, 12, 16, 20, 24, 32)
+        assert t["tri_batch"] in (4, 6, 8, 16, 32)
+        assert t["fused"] == 2  # an air-path scan in the batch: no one-launch candidate
+        assert R.rr_get_tuning(ctx.handle) == t
+        b, _ = R.rr_radar_scan_batch(ctx.handle, sc.handle, scans, s.materials)
+        alone = [R.rr_radar_scan(ctx.handle, sc.handle, pose, p, s.materials)[0] for pose, p in scans]
+        torch.cuda.synchronize()
+        for x, y, z in zip(a, b, alone):
+            assert torch.equal(x, y) and torch.equal(x, z)
+        log(f"autotune batch: {t} {ms:.3f} ms per batch")
+    finally:
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
+        sc.release()
+
+
 @pytest.mark.parametrize("tuning", [
     dict(refill_lanes=1), dict(refill_lanes=64), dict(trace_waves_per_cu=1), dict(trace_waves_per_cu=32),
     dict(pool_rays=4096), dict(tri_batch=1), dict(tri_batch=64),
