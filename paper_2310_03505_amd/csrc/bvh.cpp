@@ -263,6 +263,20 @@ struct SpatialBuilder {
           const double w = ext / bins;
           std::vector<Box> bb(bins);
           std::vector<uint32_t> ent(bins, 0), ex(bins, 0);
+          // the references a plane would copy are counted before any is cut:
+          // an axis where every plane copies more than the allowance is
+          // skipped (long triangles crossing the whole node would otherwise
+          // be clipped into every bin at every level for nothing)
+          for (const Ref& r : v) {
+            ent[bin_of(r.box.lo[a], lo, w)]++;
+            ex[bin_of(r.box.hi[a], lo, w)]++;
+          }
+          int64_t open = 0, least = INT64_MAX;
+          for (uint32_t i = 0; i + 1 < bins; ++i) {
+            open += (int64_t)ent[i] - (int64_t)ex[i];  // references that start at or left of bin i and end right of it
+            least = std::min(least, open);
+          }
+          if (least > allow) continue;
           for (const Ref& r : v) {
             const int b0 = bin_of(r.box.lo[a], lo, w), b1 = bin_of(r.box.hi[a], lo, w);
             if (b0 == b1) {
@@ -275,8 +289,6 @@ struct SpatialBuilder {
                 if (chop(r, a, plo, phi, part)) bb[k].grow(part);
               }
             }
-            ent[b0]++;
-            ex[b1]++;
           }
           std::vector<double> rarea(bins, 0.0);
           std::vector<uint32_t> rcnt(bins, 0);
