@@ -428,9 +428,11 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     uint64_t tblocks = (level_bound + kTraceBlock - 1) / kTraceBlock;
     uint32_t tgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
     if ((rs = timed_launch(1, d, [&] { return launch_trace(a, tgrid, st); }))) return rs;
-    // shade grid: 8 x 512 lanes per CU (the air-path variant 12 x 256)
+    // shade grid: 32 x 512 lanes per CU (the air-path variant 24 x 256): many
+    // short blocks, so a finishing block hands its CU to the next while the
+    // other resident block still runs
     const uint32_t sb = (uint32_t)shade_block(a.air);
-    const uint32_t lanes_per_cu = a.air ? 12u * 256u : 8u * 512u;
+    const uint32_t lanes_per_cu = a.air ? 24u * 256u : 32u * 512u;
     uint64_t sblocks = (level_bound + sb - 1) / sb;
     uint32_t sgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(sblocks, 1), (uint64_t)ctx->n_cu * (lanes_per_cu / sb));
     if ((rs = timed_launch(2, d, [&] { return launch_shade(a, sgrid, st); }))) return rs;
