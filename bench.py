@@ -59,11 +59,11 @@ FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 # FETCH_SIZE counts half the bytes a copy reads, WRITE_SIZE all it writes.
 # The figures hold only for the kernel sources they were taken on.
 TRACE_COUNTERS = {
-    "large_scene_2m": dict(fetch_kib=374469.5, write_kib=165822.6, sq_insts_valu=903247980.2,
-                           grbm_gui_active_per_xcd=28652578.7 / 8, tcp_accesses=806215380.3,
-                           tcp_tcc_read_req=65990030.4),
+    "large_scene_2m": dict(fetch_kib=327059.4, write_kib=159897.5, sq_insts_valu=902992063.3,
+                           grbm_gui_active_per_xcd=28691529.2 / 8, tcp_accesses=805417283.1,
+                           tcp_tcc_read_req=61204204.8),
 }
-TRACE_COUNTERS_SOURCES = "71ffe404dd176c8f4b092ddb6dc0c68d64b06b2958009f2d9356f50cf6823c55"
+TRACE_COUNTERS_SOURCES = "b4ab791174d2424fd8e6739d6205c7cd682255935d30e9797dc6328eb09e4b68"
 COUNTER_SCALE = dict(fetch_scale=2.0, write_scale=1.0)
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h", "api.cpp")
 
