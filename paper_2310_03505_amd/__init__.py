@@ -672,3 +672,13 @@ class Scene:
         if self.handle:
             rr_scene_release(self._c, self.handle)
             self.handle = None
+
+
+def scan(scene: Scene, pose: dict, params: dict, materials, image=None, stream=None):
+    """One polar image of a resident scene (a Scene built with a context) on
+    the current stream, or `stream`: the float32 [n_azimuth, n_bins] CUDA
+    tensor (rr_radar_scan through the scene's context)."""
+    if scene.ctx is None or not scene.handle:
+        raise ValueError("the scene has no device copy (built without a context, or released)")
+    img, _ = rr_radar_scan(scene._c, scene.handle, pose, params, materials, image=image, stream=stream)
+    return img

@@ -462,6 +462,29 @@ def test_autotune_keeps_images(R, ctx):
         sc.release()
 
 
+def test_python_scan_convenience(R, ctx):
+    """paper_2310_03505_amd.scan(scene, pose, params, materials) returns the
+    image rr_radar_scan writes, on the current stream; a scene without a
+    device copy is refused."""
+    import torch
+    s = W.tiny_room(n_azimuth=32, rays_per_beam=16)
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    try:
+        a = R.scan(sc, s.pose, s.params, s.materials)
+        b, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        torch.cuda.synchronize()
+        assert a.shape == (32, s.params["n_bins"]) and a.dtype == torch.float32
+        assert torch.equal(a, b)
+    finally:
+        sc.release()
+    host = R.Scene(None, s.vertices, s.indices, s.tri_material)
+    try:
+        with pytest.raises(ValueError):
+            R.scan(host, s.pose, s.params, s.materials)
+    finally:
+        host.release()
+
+
 def test_autotune_batch_keeps_images(R, ctx):
     """The batch autotuner times its candidates on the batched launch of
     scans of different shapes (one with the air path) and keeps the fastest;
