@@ -18,7 +18,9 @@
 //
 // Floating-point rules: no contraction except where fmaf is written; the
 // closest-hit, bin and total-internal-reflection decisions and the child
-// geometry are float32 in a fixed order; energies are float64.
+// geometry are float32 in a fixed order; energies are float64, except the
+// specular lobe's power c^C, float32 in a form that keeps its relative
+// accuracy near the specular direction (lobe_pow).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
