@@ -59,11 +59,11 @@ FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 # FETCH_SIZE counts half the bytes a copy reads, WRITE_SIZE all it writes.
 # The figures hold only for the kernel sources they were taken on.
 TRACE_COUNTERS = {
-    "large_scene_2m": dict(fetch_kib=327059.4, write_kib=159897.5, sq_insts_valu=902992063.3,
-                           grbm_gui_active_per_xcd=28691529.2 / 8, tcp_accesses=805417283.1,
-                           tcp_tcc_read_req=61204204.8),
+    "large_scene_2m": dict(fetch_kib=329153.5, write_kib=159325.2, sq_insts_valu=903160077.5,
+                           grbm_gui_active_per_xcd=28610781.8 / 8, tcp_accesses=805478486.8,
+                           tcp_tcc_read_req=61271988.2),
 }
-TRACE_COUNTERS_SOURCES = "b4ab791174d2424fd8e6739d6205c7cd682255935d30e9797dc6328eb09e4b68"
+TRACE_COUNTERS_SOURCES = "68677e47f3291f3298207921b5ed57e5a1ea971c9a16b5851aea7d3242f3bd58"
 COUNTER_SCALE = dict(fetch_scale=2.0, write_scale=1.0)
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h", "api.cpp")
 
