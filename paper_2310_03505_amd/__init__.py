@@ -129,6 +129,14 @@ def load_library():
     global _lib
     if _lib is not None:
         return _lib
+    # Load PyTorch first: the library's libamdhip64 dependency then resolves
+    # (by soname) to the HIP runtime torch has already loaded, so the two
+    # share one runtime.  Loaded the other way round, torch later finds no
+    # device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2310_03505_amd.build` (there is no fallback)")
