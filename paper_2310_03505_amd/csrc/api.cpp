@@ -348,6 +348,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     a.nodes = static_cast<const Node4*>(sc->d_nodes);
     a.n_nodes = sc->n_nodes;
   }
+  a.levels = L.max_b;
   a.tris = sc->d_tris;
   a.aux = sc->d_aux;
   a.scans = d_scans;
@@ -430,7 +431,7 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     if ((rs = timed_launch(1, d, [&] { return launch_trace(a, tgrid, st); }))) return rs;
     // shade grid: 32 x 512 lanes per CU (the air-path variant 24 x 256): many
     // short blocks, so a finishing block hands its CU to the next while the
-    // other resident block still runs
+    // other resident blocks still run
     const uint32_t sb = (uint32_t)shade_block(a.air);
     const uint32_t lanes_per_cu = a.air ? 24u * 256u : 32u * 512u;
     uint64_t sblocks = (level_bound + sb - 1) / sb;

@@ -26,6 +26,7 @@ struct LevelArgs {
   const Node8* nodes8;  // eight-wide tree (exactly one is set)
   uint32_t n_nodes;  // inner nodes (bounds the node visits of one ray)
   uint32_t depth;
+  uint32_t levels;  // bounce levels of the launch: the largest max_b of its scans
   const float4* tris;
   const float4* aux;
   const DevScan* scans;

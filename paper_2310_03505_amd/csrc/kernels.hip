@@ -871,10 +871,16 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
   const float dnf = dot3(dx, dy, dz, nfx, nfy, nfz);
   const float cosi = -dnf;
   const float k2 = 2.0f * dnf;
+  // children exist below the last bounce level of the ray's scan; the
+  // reflected direction is normalised only where a child or the air path
+  // uses it (the last level skips both directions)
+  const bool kids = depth + 1 < S->max_b;
+  bool need_rd = kids;
+  if constexpr (kAirPath) need_rd = need_rd || ((S->flags & kFlagAirPath) && depth >= 1u && medium == kAir);
   o.rdx = dx - k2 * nfx;
   o.rdy = dy - k2 * nfy;
   o.rdz = dz - k2 * nfz;
-  normalize3(o.rdx, o.rdy, o.rdz);
+  if (need_rd) normalize3(o.rdx, o.rdy, o.rdz);
   double R, T;
   const double ci = (double)cosi;
   bool refract = false;
@@ -887,13 +893,15 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
       R = 1.0;
       T = 0.0;
     } else {
-      const float cost = sqrtf(kappa);
-      const float aa = eta * cosi - cost;
-      const float ex = eta * dx, ey = eta * dy, ez = eta * dz;
-      o.tdx = ex + aa * nfx;
-      o.tdy = ey + aa * nfy;
-      o.tdz = ez + aa * nfz;
-      normalize3(o.tdx, o.tdy, o.tdz);
+      if (kids) {
+        const float cost = sqrtf(kappa);
+        const float aa = eta * cosi - cost;
+        const float ex = eta * dx, ey = eta * dy, ez = eta * dz;
+        o.tdx = ex + aa * nfx;
+        o.tdy = ey + aa * nfy;
+        o.tdz = ez + aa * nfz;
+        normalize3(o.tdx, o.tdy, o.tdz);
+      }
       refract = true;
       t_medium = entering ? mat : kAir;
       if (M.kind == 3u) {
@@ -1017,7 +1025,7 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
       }
     }
   }
-  if (depth + 1 < S->max_b) {
+  if (kids) {
     const double ecut = (double)S->e_cut;
     o.e_refl = E * R - e_ret - e_air;
     o.e_refr = refract ? E * T : 0.0;
@@ -1041,8 +1049,14 @@ __device__ __forceinline__ void shade_hit(const LevelArgs& A, const float4 a, co
 // Interaction at the hit of every ray of the level (Sec. III-A): Snell and
 // Fresnel split, the retrace return through the beam window of the standard
 // BRDF, range binning (Sec. III-B) and the two children.
+// Register budgets for occupancy: the kernel mostly waits on its loads, and
+// more resident waves hide more of that wait.  The closest-hit form keeps to
+// 80 registers, six waves per SIMD (three 512-lane blocks per CU instead of
+// two); the air-path form to 168, three waves per SIMD (three 256-lane blocks
+// instead of two).  The closest-hit form spills one register to scratch.
 template <bool kCount, bool kAirPath>
-__global__ void __launch_bounds__(shade_block(kAirPath)) k_shade(LevelArgs A) {
+__global__ void __launch_bounds__(shade_block(kAirPath)) __attribute__((amdgpu_waves_per_eu(kAirPath ? 3 : 6)))
+k_shade(LevelArgs A) {
   constexpr int kShadeLanes = shade_block(kAirPath);
   // returns of the block's rays are summed in an LDS hash table keyed by
   // accumulator cell and flushed with one global atomic per cell at the end;
@@ -1067,36 +1081,23 @@ __global__ void __launch_bounds__(shade_block(kAirPath)) k_shade(LevelArgs A) {
   const uint32_t end = min(begin + per_block, n_in);
   uint32_t cnt_hits = 0;
   uint32_t par = 0;
-  // a step's ray and hit are loaded one step ahead and the hit triangle's
-  // normal (which waits for the hit) during the step before, so neither
-  // load's latency falls inside the step that uses it
-  uint2 hn = make_uint2(0u, 0xffffffffu);
-  float4 an = make_float4(0.0f, 0.0f, 0.0f, 0.0f), bn = an, nn = an;
-  uint4 cn = make_uint4(0u, 0u, 0u, 0u);
-  uint32_t mn = 0;
-  if (begin + threadIdx.x < end) {
-    const uint32_t idx = begin + threadIdx.x;
-    hn = A.hits[idx];
-    an = A.in.a[idx];
-    bn = A.in.b[idx];
-    cn = A.in.c[idx];
-    mn = A.in.m[idx];
-    if ((int32_t)hn.y >= 0) nn = A.aux[hn.y];
-  }
+  // the ray, its hit and the hit triangle's normal are loaded at the top of
+  // the step: the other resident waves cover their latency (loading one
+  // step ahead held 19 more registers and cost spills at this occupancy)
   for (uint32_t base = begin; base < end; base += kShadeLanes, par ^= 1u) {
     const uint32_t idx = base + threadIdx.x;
     const bool active = idx < end;
-    const uint2 h = hn;
-    const float4 a = an, b = bn, nrm = nn;
-    const uint4 c = cn;
-    const uint32_t m = mn;
-    const uint32_t next = idx + kShadeLanes;
-    if (next < end) {
-      hn = A.hits[next];
-      an = A.in.a[next];
-      bn = A.in.b[next];
-      cn = A.in.c[next];
-      mn = A.in.m[next];
+    uint2 h = make_uint2(0u, 0xffffffffu);
+    float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a, nrm = a;
+    uint4 c = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t m = 0;
+    if (active) {
+      h = A.hits[idx];
+      a = A.in.a[idx];
+      b = A.in.b[idx];
+      c = A.in.c[idx];
+      m = A.in.m[idx];
+      if ((int32_t)h.y >= 0) nrm = A.aux[h.y];
     }
     Shaded o;
     if (active) {
@@ -1104,7 +1105,6 @@ __global__ void __launch_bounds__(shade_block(kAirPath)) k_shade(LevelArgs A) {
       shade_hit<kAirPath>(A, a, b, c, m, h.x, hit, o, &nrm);
       if (kCount && hit >= 0) ++cnt_hits;
     }
-    if (next < end && (int32_t)hn.y >= 0) nn = A.aux[hn.y];
     const bool has_q = o.has_q, has_r = o.has_r, has_t = o.has_t;
     const uint32_t cell = o.cell;
     const unsigned long long qv = o.qv;
@@ -1124,60 +1124,63 @@ __global__ void __launch_bounds__(shade_block(kAirPath)) k_shade(LevelArgs A) {
       if (!done) atomicAdd(A.acc + cell, qv);
     }
 
-    // ---- children: one atomic per block iteration for both kinds
-    const uint64_t mr = __ballot(has_r);
-    const uint64_t mt = __ballot(has_t);
-    const uint64_t ma = kAirPath ? __ballot(o.has_air) : 0ull;
-    const uint32_t nr = (uint32_t)__popcll(mr);
-    const uint32_t nt = (uint32_t)__popcll(mt);
-    if (lane == 0) {
-      s_cnt[par][wid][0] = nr;
-      s_cnt[par][wid][1] = nt;
-      s_cnt[par][wid][2] = (uint32_t)__popcll(ma);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t total = 0, total_a = 0;
-      for (uint32_t w = 0; w < kShadeLanes / 64; ++w) {
-        total += s_cnt[par][w][0] + s_cnt[par][w][1];
-        total_a += s_cnt[par][w][2];
+    // ---- children (and visibility rays): one atomic per block iteration for
+    // every kind; the last level of a launch without the air path has none
+    if (kAirPath || A.depth + 1 < A.levels) {
+      const uint64_t mr = __ballot(has_r);
+      const uint64_t mt = __ballot(has_t);
+      const uint64_t ma = kAirPath ? __ballot(o.has_air) : 0ull;
+      const uint32_t nr = (uint32_t)__popcll(mr);
+      const uint32_t nt = (uint32_t)__popcll(mt);
+      if (lane == 0) {
+        s_cnt[par][wid][0] = nr;
+        s_cnt[par][wid][1] = nt;
+        s_cnt[par][wid][2] = (uint32_t)__popcll(ma);
       }
-      s_base[par] = total ? atomicAdd(A.counters + kCtrCount + A.depth + 1, total) : 0u;
-      if (kAirPath) s_abase[par] = total_a ? atomicAdd(A.counters + kCtrShadow, total_a) : 0u;
-    }
-    __syncthreads();
-    // buffer `par` is written again two steps on, after every wave has passed
-    // the next step's first barrier, so no third barrier is needed here
-    uint32_t ob = s_base[par], oa = kAirPath ? s_abase[par] : 0u;
-    for (uint32_t w = 0; w < wid; ++w) {
-      ob += s_cnt[par][w][0] + s_cnt[par][w][1];
-      if (kAirPath) oa += s_cnt[par][w][2];
-    }
-    if (kAirPath && o.has_air) {
-      const uint32_t slot = oa + lane_prefix(ma);
-      if (slot < A.shq_cap) {
-        A.shq.a[slot] = make_float4(o.aox, o.aoy, o.aoz, o.adist);
-        A.shq.b[slot] = make_float4(o.asx, o.asy, o.asz, __uint_as_float(o.aslot));
-        A.shq.c[slot] = make_uint4((uint32_t)o.aqv, (uint32_t)(o.aqv >> 32), o.acell, (uint32_t)o.hit);
-      } else {
-        atomicOr(A.counters + kCtrOverflow, 1u);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t total = 0, total_a = 0;
+        for (uint32_t w = 0; w < kShadeLanes / 64; ++w) {
+          total += s_cnt[par][w][0] + s_cnt[par][w][1];
+          total_a += s_cnt[par][w][2];
+        }
+        s_base[par] = total ? atomicAdd(A.counters + kCtrCount + A.depth + 1, total) : 0u;
+        if (kAirPath) s_abase[par] = total_a ? atomicAdd(A.counters + kCtrShadow, total_a) : 0u;
       }
-    }
-    if (has_r) {
-      const uint32_t slot = ob + lane_prefix(mr);
-      if (slot < A.cap)
-        put_ray(A.out, slot, o.rox, o.roy, o.roz, o.range, o.rdx, o.rdy, o.rdz, o.g, o.e_refl, o.pid,
-                (uint32_t)o.hit, o.r_meta);
-      else
-        atomicOr(A.counters + kCtrOverflow, 1u);
-    }
-    if (has_t) {
-      const uint32_t slot = ob + nr + lane_prefix(mt);
-      if (slot < A.cap)
-        put_ray(A.out, slot, o.tox, o.toy, o.toz, o.range, o.tdx, o.tdy, o.tdz, o.g, o.e_refr, o.pid,
-                (uint32_t)o.hit, o.t_meta);
-      else
-        atomicOr(A.counters + kCtrOverflow, 1u);
+      __syncthreads();
+      // buffer `par` is written again two steps on, after every wave has passed
+      // the next step's first barrier, so no third barrier is needed here
+      uint32_t ob = s_base[par], oa = kAirPath ? s_abase[par] : 0u;
+      for (uint32_t w = 0; w < wid; ++w) {
+        ob += s_cnt[par][w][0] + s_cnt[par][w][1];
+        if (kAirPath) oa += s_cnt[par][w][2];
+      }
+      if (kAirPath && o.has_air) {
+        const uint32_t slot = oa + lane_prefix(ma);
+        if (slot < A.shq_cap) {
+          A.shq.a[slot] = make_float4(o.aox, o.aoy, o.aoz, o.adist);
+          A.shq.b[slot] = make_float4(o.asx, o.asy, o.asz, __uint_as_float(o.aslot));
+          A.shq.c[slot] = make_uint4((uint32_t)o.aqv, (uint32_t)(o.aqv >> 32), o.acell, (uint32_t)o.hit);
+        } else {
+          atomicOr(A.counters + kCtrOverflow, 1u);
+        }
+      }
+      if (has_r) {
+        const uint32_t slot = ob + lane_prefix(mr);
+        if (slot < A.cap)
+          put_ray(A.out, slot, o.rox, o.roy, o.roz, o.range, o.rdx, o.rdy, o.rdz, o.g, o.e_refl, o.pid,
+                  (uint32_t)o.hit, o.r_meta);
+        else
+          atomicOr(A.counters + kCtrOverflow, 1u);
+      }
+      if (has_t) {
+        const uint32_t slot = ob + nr + lane_prefix(mt);
+        if (slot < A.cap)
+          put_ray(A.out, slot, o.tox, o.toy, o.toz, o.range, o.tdx, o.tdy, o.tdz, o.g, o.e_refr, o.pid,
+                  (uint32_t)o.hit, o.t_meta);
+        else
+          atomicOr(A.counters + kCtrOverflow, 1u);
+      }
     }
   }
   // ---- flush the table
