@@ -59,11 +59,11 @@ FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 # FETCH_SIZE counts half the bytes a copy reads, WRITE_SIZE all it writes.
 # The figures hold only for the kernel sources they were taken on.
 TRACE_COUNTERS = {
-    "large_scene_2m": dict(fetch_kib=329153.5, write_kib=159325.2, sq_insts_valu=903160077.5,
-                           grbm_gui_active_per_xcd=28610781.8 / 8, tcp_accesses=805478486.8,
-                           tcp_tcc_read_req=61271988.2),
+    "large_scene_2m": dict(fetch_kib=354931.2, write_kib=164287.8, sq_insts_valu=903081862.5,
+                           grbm_gui_active_per_xcd=28631238.0 / 8, tcp_accesses=805798628.8,
+                           tcp_tcc_read_req=63728289.0),
 }
-TRACE_COUNTERS_SOURCES = "68677e47f3291f3298207921b5ed57e5a1ea971c9a16b5851aea7d3242f3bd58"
+TRACE_COUNTERS_SOURCES = "26edf016c3c09b610a779546f472232e2a7557b92b85316d8c79656bbc430ecf"
 COUNTER_SCALE = dict(fetch_scale=2.0, write_scale=1.0)
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h", "api.cpp")
 
