@@ -362,12 +362,16 @@ def run_trajectory(R, ctx, which: str, steps: int, large=None):
                 batch_images_equal_single=same, graph_images_equal_batch=same_graph)
 
 
-def run_serve(R, ctx, scene, sc, seconds: float, rate_scale: float, one_per_launch: bool):
+def run_serve(R, ctx, scene, sc, seconds: float, rate_scale: float, one_per_launch: bool,
+              exclude_s: float = 0.0):
     """Replays the seeded Poisson stream (200 requests/s x rate_scale from 32
     robots, random poses, 100..800 azimuths, 256..4096 rays/beam, 2..5
     bounces) into the continuous-batching server on the resident large
     scene; or, one_per_launch, into a server of one slot and one request
-    per launch (the baseline)."""
+    per launch (the baseline).  The server's statistics restart at the first
+    request arriving at or after exclude_s (the stream's warm-up is left
+    out).  Output images go to a ring of at most 2048 device buffers; a
+    buffer is reused only once the request that held it has completed."""
     import torch
     import workloads as W
     reqs = W.request_stream(duration_s=seconds * rate_scale)
@@ -381,27 +385,37 @@ def run_serve(R, ctx, scene, sc, seconds: float, rate_scale: float, one_per_laun
     srv = R.rr_server_create(c, s, scene.materials, n_slots=1 if one else 2,
                              max_batch_scans=1 if one else 256, memory_budget=48 << 30)
     max_cells = max(r["params"]["n_azimuth"] * r["params"]["n_bins"] for r in reqs)
-    pool = torch.empty((len(reqs), max_cells), dtype=torch.float32, device="cuda")
+    ring = min(len(reqs), 2048)
+    pool = torch.empty((ring, max_cells), dtype=torch.float32, device="cuda")
     # warm-up: a few requests, then reset the statistics
-    warm = [R.rr_server_submit(srv, r["pose"], r["params"], pool[i]) for i, r in enumerate(reqs[:8])]
+    warm = [R.rr_server_submit(srv, r["pose"], r["params"], pool[i % ring]) for i, r in enumerate(reqs[:8])]
     for t in warm:
         R.rr_server_wait(srv, t)
     R.rr_server_reset_stats(srv)
     t0 = time.perf_counter()
     tickets = []
+    waited = 0
+    excluded = exclude_s <= 0.0
     for i, r in enumerate(reqs):
         delay = t0 + r["t_arrival"] - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        tickets.append(R.rr_server_submit(srv, r["pose"], r["params"], pool[i]))
-    for t in tickets:
+        if not excluded and r["t_arrival"] >= exclude_s:
+            R.rr_server_reset_stats(srv)
+            excluded = True
+        while waited <= i - ring:  # the buffer's previous request must be done
+            R.rr_server_wait(srv, tickets[waited])
+            waited += 1
+        tickets.append(R.rr_server_submit(srv, r["pose"], r["params"], pool[i % ring]))
+    for t in tickets[waited:]:
         R.rr_server_wait(srv, t)
     st = R.rr_server_get_stats(srv)
     R.rr_server_destroy(srv)
     del pool
     return dict(workload="serve_poisson_%dhz_large_scene_2m" % round(rate)
                 + ("_one_per_launch" if one else ""),
-                requests=len(reqs), stream_seconds=seconds, arrival_rate_hz=round(rate, 1),
+                requests=len(reqs), stream_seconds=seconds, excluded_seconds=exclude_s,
+                arrival_rate_hz=round(rate, 1),
                 completed=st["completed"], rejected=st["rejected"], batches=st["batches"],
                 scans_per_s=round(st["scans_per_s"], 2), mseg_per_s=round(st["mseg_per_s"], 2),
                 latency_p50_ms=round(st["latency_p50_ms"], 2), latency_p99_ms=round(st["latency_p99_ms"], 2),
@@ -429,7 +443,8 @@ def bench_serve(args):
     ctx = R.Context(0)
     scene = W.large_scene()
     sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
-    r = run_serve(R, ctx, scene, sc, args.serve_seconds, args.serve_rate_scale, args.serve_one_per_launch)
+    r = run_serve(R, ctx, scene, sc, args.serve_seconds, args.serve_rate_scale, args.serve_one_per_launch,
+                  args.serve_exclude_seconds)
     sc.release()
     ctx.close()
     out = {
@@ -637,6 +652,8 @@ def main():
                     help="trajectory workload: 64 poses on the 2M-triangle scene or in the tiny room")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed request stream (serve workload)")
+    ap.add_argument("--serve-exclude-seconds", type=float, default=0.0,
+                    help="leave the stream's first seconds out of the statistics (serve workload)")
     ap.add_argument("--serve-rate-scale", type=float, default=1.0,
                     help="compress the stream's arrival times by this factor (load x scale)")
     ap.add_argument("--serve-one-per-launch", action="store_true",
