@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -423,6 +424,59 @@ def run_serve(R, ctx, scene, sc, seconds: float, rate_scale: float, one_per_laun
                 wall_s=round(st["wall_s"], 3), segments=st["segments"])
 
 
+def bench_table3(args):
+    """Milliseconds per polar image against rays per azimuth, the form of the
+    paper's run-time table (Table III: N_s = 200 ... 1000, 400 azimuths, a
+    10 degree cone with P = 0.9, at most four interactions per path), on the
+    two-million-triangle scene.  Each row times `steps` scans after `warmup`
+    with HIP events on the scan's stream; the line also gives the least-squares
+    fit ms = fixed + N_s * 400 / rate over the rows."""
+    import numpy as np
+    import torch
+    import paper_2310_03505_amd as R
+    import workloads as W
+    ctx = R.Context(0)
+    scene = W.large_scene()
+    sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
+    c, s = ctx.handle, sc.handle
+    rows = []
+    for ns in (200, 400, 600, 800, 1000):
+        p = dict(scene.params, rays_per_beam=ns, max_bounces=4, beam_width_rad=math.radians(10.0),
+                 beam_prob=0.9)
+        img = torch.empty((p["n_azimuth"], p["n_bins"]), dtype=torch.float32, device="cuda")
+        for _ in range(max(args.warmup, 1)):
+            R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img)
+        _, st = R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img, stats=True)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            R.rr_radar_scan(c, s, scene.pose, p, scene.materials, image=img)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        rows.append(dict(rays_per_beam=ns, primaries=p["n_azimuth"] * ns, ms_per_image=round(ms, 4),
+                         scans_per_s=round(1e3 / ms, 1), segments=st["segments"],
+                         mseg_per_s=round(st["segments"] / ms / 1e3, 1)))
+        log(f"bench: table3 N_s = {ns}: {ms:.3f} ms per image, {st['segments']} segments")
+    x = np.array([r["primaries"] for r in rows], dtype=np.float64)
+    y = np.array([r["ms_per_image"] for r in rows], dtype=np.float64)
+    slope, fixed = np.polyfit(x, y, 1)
+    sc.release()
+    ctx.close()
+    out = {
+        "metric": "ms per polar image", "value": rows[-1]["ms_per_image"], "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": rows[-1]["ms_per_image"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "table3_sweep_large_scene_2m", "n_tris": scene.n_tris, "n_azimuth": 400,
+                   "beam_width_deg": 10.0, "beam_prob": 0.9, "max_bounces": 4, "rows": rows,
+                   "fit_fixed_ms": round(float(fixed), 4),
+                   "fit_marginal_mprim_per_s": round(1.0 / float(slope) / 1e3, 1)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_trajectory(args):
     import paper_2310_03505_amd as R
     ctx = R.Context(0)
@@ -647,7 +701,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "urban", "tiny", "trajectory", "serve", "post", "build"])
+                    choices=["large", "urban", "tiny", "trajectory", "serve", "post", "build", "table3"])
     ap.add_argument("--trajectory-scene", default="large", choices=["large", "tiny"],
                     help="trajectory workload: 64 poses on the 2M-triangle scene or in the tiny room")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -693,6 +747,8 @@ def main():
         return bench_trajectory(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "table3":
+        return bench_table3(args)
     if args.workload == "post":
         return bench_post(args)
     if args.workload == "build":
