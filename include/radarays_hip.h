@@ -502,15 +502,23 @@ typedef struct {
                              launch per bounce level */
   uint32_t shade_batch;    /* fused: finished rays a wave queues before it
                              shades them in one step (1..64) */
-  uint32_t reserved[1];
+  uint32_t tail_help;      /* a traversal launch whose ray bound is at most
+                             this many rays per lane of its grid (1..1024,
+                             default 12) uses tail helping: once a wave has
+                             no rays left to claim, its idle lanes walk
+                             subtrees of its unfinished rays; RR_TAIL_HELP_OFF
+                             never */
 } rr_tuning;
+#define RR_TAIL_HELP_OFF 0xffffffffu
 
+/* Zero fields take their defaults.  EINVAL for a field out of its range,
+ * and then no field changes.  rr_get_tuning returns the values in effect. */
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t);
 rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out);
 
 /* Autotuner: scans the given workload with candidate launch parameters
  * (coordinate descent over refill_lanes, trace_waves_per_cu, pool_rays,
- * tri_batch, fused and shade_batch, each candidate timed with HIP events over `reps` scans
+ * tri_batch, fused, shade_batch and tail_help, each candidate timed with HIP events over `reps` scans
  * on `stream`), keeps the fastest in the context and returns it in *best
  * with its time per scan.  Every candidate produces the same image.  The
  * one-launch mode (fused = 1) is not a candidate for an air-path scan or an

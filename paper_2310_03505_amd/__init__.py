@@ -81,7 +81,7 @@ class rr_tuning(C.Structure):
     _fields_ = [("refill_lanes", C.c_uint32), ("trace_waves_per_cu", C.c_uint32),
                 ("pool_rays", C.c_uint32), ("batch_budget_mb", C.c_uint32),
                 ("tri_batch", C.c_uint32), ("fused", C.c_uint32), ("shade_batch", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("tail_help", C.c_uint32)]
 
 
 class rr_server_options(C.Structure):
@@ -430,7 +430,8 @@ def rr_radar_scan_batch(ctx, scene, scans, materials, images=None, stats=False, 
 
 
 TUNING_KEYS = ("refill_lanes", "trace_waves_per_cu", "pool_rays", "batch_budget_mb", "tri_batch",
-               "fused", "shade_batch")
+               "fused", "shade_batch", "tail_help")
+RR_TAIL_HELP_OFF = 0xFFFFFFFF
 
 
 def _tuning_dict(t) -> dict:
@@ -439,9 +440,9 @@ def _tuning_dict(t) -> dict:
 
 def rr_set_tuning(ctx, refill_lanes: int = 0, trace_waves_per_cu: int = 0, pool_rays: int = 0,
                   batch_budget_mb: int = 0, tri_batch: int = 0, fused: int = 0,
-                  shade_batch: int = 0):
+                  shade_batch: int = 0, tail_help: int = 0):
     t = rr_tuning(refill_lanes, trace_waves_per_cu, pool_rays, batch_budget_mb, tri_batch, fused,
-                  shade_batch)
+                  shade_batch, tail_help)
     _check(load_library().rr_set_tuning(ctx, C.byref(t)), ctx)
 
 

@@ -271,6 +271,16 @@ uint32_t trace_grid_blocks(const rr_context* ctx) {
   return std::min(g, kSpillLanes / (uint32_t)kTraceBlock);
 }
 
+// Tail helping (idle lanes walk subtrees of their wave's unfinished rays)
+// for a traversal launch whose rays number at most ctx->tail_help per lane
+// of its grid (`bound` is the launch's ray bound).  Few rays per lane leave
+// the launch waiting on its longest walks, which helpers shorten; with many
+// the helpers' bookkeeping costs more than the short tail it saves.
+bool tail_help_on(const rr_context* ctx, uint64_t bound, uint32_t grid_blocks) {
+  return ctx->tail_help != RR_TAIL_HELP_OFF &&
+         bound <= (uint64_t)ctx->tail_help * grid_blocks * (uint64_t)kTraceBlock;
+}
+
 uint32_t scene_spill_need(const rr_scene* sc) {
   // in 32-bit words per lane: an eight-wide stack entry (a node group) takes two
   if (sc->bvh.width == 8)
@@ -428,7 +438,8 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     a.out = queue_at(ws, L, (d + 1) & 1);
     uint64_t tblocks = (level_bound + kTraceBlock - 1) / kTraceBlock;
     uint32_t tgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tblocks, 1), trace_grid);
-    if ((rs = timed_launch(1, d, [&] { return launch_trace(a, tgrid, st); }))) return rs;
+    const bool help = tail_help_on(ctx, level_bound, tgrid);
+    if ((rs = timed_launch(1, d, [&] { return launch_trace(a, tgrid, help, st); }))) return rs;
     // shade grid: 32 x 512 lanes per CU (the air-path variant 24 x 256): many
     // short blocks, so a finishing block hands its CU to the next while the
     // other resident blocks still run
@@ -444,7 +455,8 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     a.depth = 0;
     uint64_t vblocks = (L.shq_cap + kTraceBlock - 1) / kTraceBlock;
     uint32_t vgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(vblocks, 1), trace_grid);
-    if ((rs = timed_launch(3, 0, [&] { return launch_shadow(a, vgrid, st); }))) return rs;
+    const bool help = tail_help_on(ctx, L.shq_cap, vgrid);
+    if ((rs = timed_launch(3, 0, [&] { return launch_shadow(a, vgrid, help, st); }))) return rs;
   }
   if (post) {
     // finalize and epilogue in one launch
@@ -474,6 +486,8 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     }
     stats->overflow = ctx->h_ctr[kCtrOverflow];
     stats->air_rays = ctx->h_ctr[kCtrShadow];
+    if (stats->overflow & kOverflowSteps)
+      return fail(ctx, RR_EOVERFLOW, "a traversal launch reached its iteration bound");
     if (stats->overflow) return fail(ctx, RR_EOVERFLOW, "ray queue overflow");
   }
   return RR_OK;
@@ -1167,23 +1181,27 @@ rr_status rr_radar_scan_batch(rr_context* ctx, const rr_scene* sc, const rr_scan
 
 rr_status rr_set_tuning(rr_context* ctx, const rr_tuning* t) {
   if (!ctx || !t) return fail(ctx, RR_EINVAL, "NULL argument");
-  uint32_t rl = t->refill_lanes ? t->refill_lanes : 8u;
-  uint32_t wc = t->trace_waves_per_cu ? t->trace_waves_per_cu : 24u;
-  uint32_t pr = t->pool_rays ? t->pool_rays : 64u;
+  // every field is checked before any is applied: a refused call changes nothing
+  const uint32_t rl = t->refill_lanes ? t->refill_lanes : 8u;
+  const uint32_t wc = t->trace_waves_per_cu ? t->trace_waves_per_cu : 24u;
+  const uint32_t pr = t->pool_rays ? t->pool_rays : 64u;
   if (rl > 64) return fail(ctx, RR_EINVAL, "refill_lanes out of [1, 64]");
   if (wc > 32) return fail(ctx, RR_EINVAL, "trace_waves_per_cu out of [1, 32]");
   if (pr < 64 || pr > 4096) return fail(ctx, RR_EINVAL, "pool_rays out of [64, 4096]");
   if (t->batch_budget_mb && t->batch_budget_mb < 64) return fail(ctx, RR_EINVAL, "batch_budget_mb below 64");
+  if (t->tri_batch > 64) return fail(ctx, RR_EINVAL, "tri_batch out of [1, 64]");
+  if (t->fused > 2) return fail(ctx, RR_EINVAL, "fused out of [0, 2]");
+  if (t->shade_batch > 64) return fail(ctx, RR_EINVAL, "shade_batch out of [1, 64]");
+  if (t->tail_help > 1024 && t->tail_help != RR_TAIL_HELP_OFF)
+    return fail(ctx, RR_EINVAL, "tail_help out of [1, 1024] (or RR_TAIL_HELP_OFF)");
   ctx->batch_budget = t->batch_budget_mb ? (size_t)t->batch_budget_mb << 20 : (size_t)24 << 30;
   ctx->refill_lanes = rl;
   ctx->trace_waves_per_cu = wc;
   ctx->pool_rays = pr;
-  if (t->tri_batch > 64) return fail(ctx, RR_EINVAL, "tri_batch out of [1, 64]");
-  if (t->fused > 2) return fail(ctx, RR_EINVAL, "fused out of [0, 2]");
-  if (t->shade_batch > 64) return fail(ctx, RR_EINVAL, "shade_batch out of [1, 64]");
   ctx->fused = t->fused == 1 ? 1u : 0u;
   ctx->shade_batch = t->shade_batch ? t->shade_batch : 64u;
   ctx->tri_batch = t->tri_batch ? t->tri_batch : 6u;
+  ctx->tail_help = t->tail_help ? t->tail_help : 12u;
   return RR_OK;
 }
 
@@ -1196,6 +1214,7 @@ rr_status rr_get_tuning(const rr_context* ctx, rr_tuning* out) {
   out->tri_batch = ctx->tri_batch;
   out->fused = ctx->fused ? 1u : 2u;
   out->shade_batch = ctx->shade_batch;
+  out->tail_help = ctx->tail_help;
   out->batch_budget_mb = (uint32_t)(ctx->batch_budget >> 20);
   return RR_OK;
 }

@@ -38,6 +38,7 @@ struct rr_context {
   uint32_t tri_batch = 6;   // queued leaves that start a triangle phase
   uint32_t fused = 0;       // 1: all bounce levels in one persistent launch
   uint32_t shade_batch = 64;  // fused: finished rays that start a shade phase
+  uint32_t tail_help = 12;    // rays per trace lane up to which a level uses tail helping
   size_t batch_budget = (size_t)24 << 30;  // workspace bytes per batch group
 };
 
@@ -114,6 +115,7 @@ void make_layout(const rr_sensor_params* const* ps, uint32_t n, Layout& L, bool 
 // Persistent trace blocks of a launch at the context's tuning (the spill
 // area must hold this many blocks' lanes).
 uint32_t trace_grid_blocks(const rr_context* ctx);
+bool tail_help_on(const rr_context* ctx, uint64_t bound, uint32_t grid_blocks);
 // 32-bit spill words a lane may need beyond its LDS stack when tracing this
 // scene's tree (from the build's worst-case stack need).
 uint32_t scene_spill_need(const rr_scene* sc);

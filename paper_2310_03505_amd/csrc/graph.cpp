@@ -226,6 +226,7 @@ static rr_status tune(rr_context* ctx, hipStream_t st, uint32_t reps, bool one_l
   static const uint32_t kTriBatch[] = {4, 6, 8, 16, 32};
   static const uint32_t kFused[] = {1, 2};  // one launch per scan, one per level
   static const uint32_t kShadeBatch[] = {16, 32, 64};
+  static const uint32_t kTailHelp[] = {RR_TAIL_HELP_OFF, 4, 12, 32};
   struct Axis {
     const uint32_t* v;
     size_t n;
@@ -235,7 +236,8 @@ static rr_status tune(rr_context* ctx, hipStream_t st, uint32_t reps, bool one_l
               {kPool, 3, &rr_tuning::pool_rays},
               {kTriBatch, 5, &rr_tuning::tri_batch},
               {kFused, 2, &rr_tuning::fused},
-              {kShadeBatch, 3, &rr_tuning::shade_batch}};
+              {kShadeBatch, 3, &rr_tuning::shade_batch},
+              {kTailHelp, 4, &rr_tuning::tail_help}};
   if (!one_launch_ok && cur.fused == 1) cur.fused = 2;
   double inc = 0.0;
   s = measure(cur, inc);

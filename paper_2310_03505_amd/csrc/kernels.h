@@ -67,12 +67,12 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_gather(const float4* buf, uint32_t n_rows, uint32_t steps, float* out, uint32_t threads,
                          hipStream_t st);
 hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st);
-hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_trace(const LevelArgs& a, uint32_t grid, bool help, hipStream_t st);
 hipError_t launch_shade(const LevelArgs& a, uint32_t grid, hipStream_t st);
 // Visibility of the sensor for the air-path returns of every level (the
 // closest-hit traversal bounded by each ray's distance to the sensor); the
 // unblocked returns are added to the accumulator.  a.depth must be 0.
-hipError_t launch_shadow(const LevelArgs& a, uint32_t grid, hipStream_t st);
+hipError_t launch_shadow(const LevelArgs& a, uint32_t grid, bool help, hipStream_t st);
 // All bounce levels in one persistent launch (primaries from queue `in`).
 hipError_t launch_scan(const LevelArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_finalize(const DevScan* scans, uint32_t n_scans, const unsigned long long* acc,

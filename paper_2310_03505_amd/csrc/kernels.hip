@@ -198,12 +198,25 @@ __device__ __forceinline__ void normalize3(float& x, float& y, float& z) {
 // each bounded by its distance to the sensor (a triangle at 0 < t <= dist
 // blocks it).  A ray stops walking at its first blocker, and an unblocked
 // return is added to the image accumulator.
-template <bool kCount, bool kShadow>
-__global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
+//
+// kHelp: tail helping, for levels with few rays per lane, whose time is the
+// walk of their longest rays.  Once a wave has no rays left to claim, its
+// idle lanes take the bottom entry (the oldest, usually the largest subtree)
+// of a walking lane's stack and walk that subtree for the same ray: the
+// leaves they queue carry the owner's lane, so their hits meet in the
+// owner's (t, id) minimum, and they cull against that minimum.  The owner
+// finishes once no helper walks for it.  The result is the same minimum, so
+// images and records do not change.  Held to 80 registers, as the plain
+// variant, so that both keep 24 waves per CU resident.
+template <bool kCount, bool kShadow, bool kHelp>
+__global__ void __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(kHelp ? 6 : 1)))
+k_trace(LevelArgs A) {
   __shared__ int32_t lds_stack[kStack * kTraceBlock];
   __shared__ uint32_t lds_leaf[kTraceBlock / 64][kLeafRing];     // leaf reference
   __shared__ uint8_t lds_own[kTraceBlock / 64][kLeafRing];       // lane that appended it
   __shared__ unsigned long long lds_best[kTraceBlock];           // (t bits << 32) | original id
+  __shared__ uint32_t lds_help[kHelp ? kTraceBlock : 1];          // helpers walking for each lane's ray
+  __shared__ uint8_t lds_pair[kHelp ? kTraceBlock / 64 : 1][64];  // victim lane of each helper rank
   int32_t* stk = lds_stack + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wib = threadIdx.x >> 6;
@@ -233,8 +246,23 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
   uint32_t cnt_nodes = 0, cnt_tris = 0, cnt_rays = 0;
   uint64_t cnt_iters = 0, cnt_active = 0, cnt_tail_iters = 0, cnt_tail_active = 0;  // wave-uniform
   uint32_t cnt_max_visits = 0;
+  // tail helping: the lane whose ray this lane walks (itself unless it is a
+  // helper), the stack entries below sb handed to helpers
+  uint32_t owner = lane;
+  int sb = 0;
+  bool helper = false;
+  uint32_t guard = 0;
+  if (kHelp) lds_help[threadIdx.x] = 0u;
 
   for (;;) {
+    // a bound every wave reaches: a level takes far fewer iterations per
+    // wave than this (tens of thousands at the largest sizes); should the
+    // helpers' bookkeeping ever fail to drain, the launch still ends and the
+    // scan reports it
+    if (kHelp && ++guard > (1u << 22)) {
+      if (lane == 0) atomicOr(A.counters + kCtrOverflow, kOverflowSteps);
+      break;
+    }
     // ---- refill idle lanes (wave-uniform decision) from the wave's pool of
     // claimed rays; the pool is refilled A.pool rays at a time with one atomic
     // on a segment cursor
@@ -278,6 +306,9 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
           ridx = my;
           cur = 0;
           sp = 0;
+          sb = 0;
+          owner = lane;
+          helper = false;
           visits = 0;
           last_pos = ring_head;
           trav_done = false;
@@ -342,7 +373,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
       ring_tail += n;
       __builtin_amdgcn_wave_barrier();
       if (valid) {
-        const unsigned long long mine = lds_best[threadIdx.x];
+        const unsigned long long mine = lds_best[wave_base + (kHelp ? owner : lane)];
         best_t = __uint_as_float((uint32_t)(mine >> 32));
         // a visibility ray is done at its first blocker
         if (kShadow && (uint32_t)mine != 0xffffffffu) trav_done = true;
@@ -364,7 +395,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         // a reference outside the tree (kEmpty: none) takes the next stack
         // entry; a popped entry still outside it is dropped at the next step
         if (walk && (uint32_t)cur >= A.n_nodes) {
-          if (sp > 0) {
+          if (sp > sb) {
             --sp;
             cur = sp < kStack ? top : A.spill[(size_t)(sp - kStack) * spill_stride + gtid];
           } else {
@@ -452,7 +483,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
               if (lf[j]) {
                 const uint32_t pos = (p + lane_prefix(lm[j])) & (kLeafRing - 1u);
                 lds_leaf[wib][pos] = (uint32_t)lref[j];
-                lds_own[wib][pos] = (uint8_t)lane;
+                lds_own[wib][pos] = (uint8_t)(kHelp ? owner : lane);
               }
               p += (uint32_t)__popcll(lm[j]);
             }
@@ -467,8 +498,16 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
     }
     __builtin_amdgcn_wave_barrier();
 
-    // ---- rays whose traversal and leaf tests are complete
-    if (valid && trav_done && (int32_t)(ring_tail - last_pos) >= 0) {
+    // ---- rays whose traversal and leaf tests are complete; a helper is done
+    // with its subtree, an owner waits until no helper walks for its ray
+    if (kHelp && helper && valid && trav_done && (int32_t)(ring_tail - last_pos) >= 0) {
+      atomicSub(&lds_help[wave_base + owner], 1u);
+      valid = false;
+      helper = false;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (valid && trav_done && (int32_t)(ring_tail - last_pos) >= 0 &&
+        (!kHelp || lds_help[threadIdx.x] == 0u)) {
       if (kCount) cnt_max_visits = max(cnt_max_visits, visits);
       const unsigned long long b = lds_best[threadIdx.x];
       if constexpr (kShadow) {
@@ -486,6 +525,53 @@ __global__ void __launch_bounds__(kTraceBlock) k_trace(LevelArgs A) {
         A.hits[ridx] = make_uint2((uint32_t)(b >> 32), (uint32_t)b);
       }
       valid = false;
+    }
+
+    // ---- tail helping: once no rays are left to claim, idle lanes take the
+    // bottom entry of a walking lane's stack (two or more entries, all in
+    // LDS) and walk that subtree for the same ray; leaves they queue carry
+    // the owner's lane, so their hits meet in the owner's minimum
+    if (kHelp && exhausted) {
+      __builtin_amdgcn_wave_barrier();
+      const bool can_give = valid && !trav_done && sp - sb >= 2 && sp <= kStack;
+      const uint64_t idle_m = __ballot(!valid);
+      const uint64_t give_m = __ballot(can_give);
+      const uint32_t k = min((uint32_t)__popcll(idle_m), (uint32_t)__popcll(give_m));
+      if (k) {
+        const uint32_t rv = lane_prefix(give_m), ri = lane_prefix(idle_m);
+        const bool victim = can_give && rv < k;
+        if (victim) lds_pair[wib][rv] = (uint8_t)lane;
+        __builtin_amdgcn_wave_barrier();
+        const bool takes = !valid && ri < k;
+        const int v = takes ? (int)lds_pair[wib][ri] : (int)lane;
+        const int vsb = __shfl(sb, v);
+        const uint32_t vown = (uint32_t)__shfl((int)owner, v);
+        const float rox = __shfl(ox, v), roy = __shfl(oy, v), roz = __shfl(oz, v);
+        const float rdx = __shfl(dx, v), rdy = __shfl(dy, v), rdz = __shfl(dz, v);
+        const uint32_t rexcl = (uint32_t)__shfl((int)excl, v);
+        if (takes) {
+          cur = lds_stack[vsb * kTraceBlock + wave_base + (uint32_t)v];
+          owner = vown;
+          ox = rox;
+          oy = roy;
+          oz = roz;
+          dx = rdx;
+          dy = rdy;
+          dz = rdz;
+          excl = rexcl;
+          ray_box_setup(ox, oy, oz, dx, dy, dz, rb);
+          best_t = __uint_as_float((uint32_t)(lds_best[wave_base + vown] >> 32));
+          atomicAdd(&lds_help[wave_base + vown], 1u);
+          sp = 0;
+          sb = 0;
+          visits = 0;
+          last_pos = ring_head;
+          trav_done = false;
+          valid = true;
+          helper = true;
+        }
+        if (victim) ++sb;
+      }
     }
   }
   if (kCount) {
@@ -1611,7 +1697,7 @@ hipError_t launch_raygen(const LevelArgs& a, uint32_t grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
+hipError_t launch_trace(const LevelArgs& a, uint32_t grid, bool help, hipStream_t st) {
   const dim3 g(grid ? grid : 1), b(kTraceBlock);
   if (a.nodes8) {
     if (a.prof)
@@ -1620,15 +1706,22 @@ hipError_t launch_trace(const LevelArgs& a, uint32_t grid, hipStream_t st) {
       hipLaunchKernelGGL(k_trace8<false>, g, b, 0, st, a);
     return hipGetLastError();
   }
-  if (a.prof)
-    hipLaunchKernelGGL((k_trace<true, false>), g, b, 0, st, a);
+  if (a.prof && help)
+    hipLaunchKernelGGL((k_trace<true, false, true>), g, b, 0, st, a);
+  else if (a.prof)
+    hipLaunchKernelGGL((k_trace<true, false, false>), g, b, 0, st, a);
+  else if (help)
+    hipLaunchKernelGGL((k_trace<false, false, true>), g, b, 0, st, a);
   else
-    hipLaunchKernelGGL((k_trace<false, false>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_trace<false, false, false>), g, b, 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_shadow(const LevelArgs& a, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_trace<false, true>), dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
+hipError_t launch_shadow(const LevelArgs& a, uint32_t grid, bool help, hipStream_t st) {
+  if (help)
+    hipLaunchKernelGGL((k_trace<false, true, true>), dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_trace<false, true, false>), dim3(grid ? grid : 1), dim3(kTraceBlock), 0, st, a);
   return hipGetLastError();
 }
 

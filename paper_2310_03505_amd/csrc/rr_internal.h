@@ -117,6 +117,9 @@ constexpr size_t kRayBytes = 16 + 16 + 16 + 4;
 // read back to the host
 constexpr int kCtrCount = 0;
 constexpr int kCtrOverflow = 32;
+// bits of the overflow word: 1, a ray queue or the visibility queue was
+// full; 2, a tail-helping traversal reached its iteration bound
+constexpr uint32_t kOverflowSteps = 2u;
 constexpr int kCtrShadow = 40;
 constexpr int kCtrHostWords = 64;   // the part of the block read back to the host
 // per level, sixteen claim cursors (one per segment of the level's queue),

@@ -396,6 +396,12 @@ def test_workspace_variant_matches(R, ctx):
 def test_invalid_arguments_launch_nothing(R, ctx):
     s = W.tiny_room(n_azimuth=8, rays_per_beam=4)
     sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    before = R.rr_get_tuning(ctx.handle)
+    for bad_t in (dict(tail_help=1025), dict(tail_help=0xFFFFFFFE), dict(tri_batch=65), dict(fused=3)):
+        with pytest.raises(R.RadarError) as e:
+            R.rr_set_tuning(ctx.handle, **bad_t)
+        assert e.value.status == R.RR_EINVAL
+    assert R.rr_get_tuning(ctx.handle)["tail_help"] == before["tail_help"]
     try:
         bad = [dict(s.params, max_bounces=0), dict(s.params, beam_prob=1.0),
                dict(s.params, n_bins=0), dict(s.params, bin_size_m=-1.0),
@@ -482,6 +488,7 @@ def test_autotune_keeps_images(R, ctx):
         assert t["trace_waves_per_cu"] in (8, 12, 16, 20, 24, 32)
         assert t["pool_rays"] in (64, 128, 256) and t["tri_batch"] in (4, 6, 8, 16, 32)
         assert t["fused"] in (1, 2) and t["shade_batch"] in (16, 32, 64)
+        assert t["tail_help"] in (R.RR_TAIL_HELP_OFF, 4, 12, 32)
         assert R.rr_get_tuning(ctx.handle) == t
         b, _ = R.rr_radar_scan(ctx.handle, sc.handle, s.pose, s.params, s.materials)
         torch.cuda.synchronize()
@@ -553,19 +560,26 @@ def test_autotune_batch_keeps_images(R, ctx):
 @pytest.mark.parametrize("tuning", [
     dict(refill_lanes=1), dict(refill_lanes=64), dict(trace_waves_per_cu=1), dict(trace_waves_per_cu=32),
     dict(pool_rays=4096), dict(tri_batch=1), dict(tri_batch=64),
-    dict(refill_lanes=64, trace_waves_per_cu=1, pool_rays=4096, tri_batch=64)])
+    dict(refill_lanes=64, trace_waves_per_cu=1, pool_rays=4096, tri_batch=64),
+    dict(tail_help=0xFFFFFFFF), dict(tail_help=1), dict(tail_help=1024),
+    dict(tail_help=1024, refill_lanes=1, trace_waves_per_cu=1, tri_batch=64)])
 def test_extreme_tunings_keep_images(R, ctx, tuning):
     """Launch parameters at the ends of their ranges (one lane or a whole wave
     idle before a refill, one wave per CU or 32, claims of 4,096 rays -- more
-    than a claim segment holds -- and triangle phases after 1 or 64 queued
-    leaves) change the schedule of the trace kernel only: hit records,
-    accumulator and image equal those of the default parameters, bit for
-    bit, on the tiny room at four bounces and on 24 columns of the urban
-    block."""
+    than a claim segment holds -- triangle phases after 1 or 64 queued
+    leaves, and tail helping never, only at one ray per lane or up to 1,024)
+    change the schedule of the trace kernel only: hit records, air-path
+    outcomes, accumulator and image equal those of the default parameters,
+    bit for bit, on the tiny room at four bounces, with and without air-path
+    returns, and on 24 columns of the urban block.  The default parameters
+    walk these small scans with tail helping; tail_help = 0xFFFFFFFF walks
+    them without."""
     import torch
     before = R.rr_get_tuning(ctx.handle)
     t, u = W.tiny_room(), W.urban_block()
-    cases = [(t, dict(t.params, max_bounces=4), t.pose), (u, dict(u.params, n_azimuth=24), u.pose)]
+    cases = [(t, dict(t.params, max_bounces=4), t.pose),
+             (t, dict(t.params, max_bounces=4, flags=t.params["flags"] | W.FLAG_AIR_PATH), t.pose),
+             (u, dict(u.params, n_azimuth=24), u.pose)]
     try:
         for scene, p, pose in cases:
             sc = R.Scene(ctx, scene.vertices, scene.indices, scene.tri_material)
