@@ -52,7 +52,8 @@ VALU_ISSUE_PEAK = N_CU * 4 * CLOCK_GHZ * 1e9 / 4.0   # wave64 instructions/s
 FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 
 # Counters of one k_trace dispatch, averaged over the trace dispatches of
-# the timed scans, from rocprofv3 --pmc passes of `bench.py --no-extras
+# the timed scans (both forms: with tail helping on the levels that use it,
+# without on the others), from rocprofv3 --pmc passes of `bench.py --no-extras
 # --no-cpu-baseline` (FETCH_SIZE, WRITE_SIZE in KiB per dispatch; SQ_INSTS_VALU,
 # GRBM_GUI_ACTIVE summed over the eight XCDs, TCP_TOTAL_CACHE_ACCESSES_sum and
 # TCP_TCC_READ_REQ_sum per dispatch).  FETCH_SIZE and WRITE_SIZE are scaled by
@@ -60,11 +61,11 @@ FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2.4 GHz x 2 (non-packed FMA)
 # FETCH_SIZE counts half the bytes a copy reads, WRITE_SIZE all it writes.
 # The figures hold only for the kernel sources they were taken on.
 TRACE_COUNTERS = {
-    "large_scene_2m": dict(fetch_kib=354931.2, write_kib=164287.8, sq_insts_valu=903081862.5,
-                           grbm_gui_active_per_xcd=28631238.0 / 8, tcp_accesses=805798628.8,
-                           tcp_tcc_read_req=63728289.0),
+    "large_scene_2m": dict(fetch_kib=357690.6, write_kib=164837.6, sq_insts_valu=899413801.4,
+                           grbm_gui_active_per_xcd=28479774.6 / 8, tcp_accesses=804344143.0,
+                           tcp_tcc_read_req=64219566.5),
 }
-TRACE_COUNTERS_SOURCES = "26edf016c3c09b610a779546f472232e2a7557b92b85316d8c79656bbc430ecf"
+TRACE_COUNTERS_SOURCES = "9a3485f4335654633cea39f4ac107f2b9df26a333b253a0aa59a72147404ecad"
 COUNTER_SCALE = dict(fetch_scale=2.0, write_scale=1.0)
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h", "api.cpp")
 

@@ -502,12 +502,13 @@ typedef struct {
                              launch per bounce level */
   uint32_t shade_batch;    /* fused: finished rays a wave queues before it
                              shades them in one step (1..64) */
-  uint32_t tail_help;      /* a traversal launch whose ray bound is at most
-                             this many rays per lane of its grid (1..1024,
-                             default 12) uses tail helping: once a wave has
-                             no rays left to claim, its idle lanes walk
-                             subtrees of its unfinished rays; RR_TAIL_HELP_OFF
-                             never */
+  uint32_t tail_help;      /* a bounce level whose ray bound is at most
+                             this many rays per lane of the trace grid
+                             (1..1024, default 12) is traced with tail
+                             helping: once a wave has no rays left to claim,
+                             its idle lanes walk subtrees of its unfinished
+                             rays.  The air-path visibility launch always
+                             uses it.  RR_TAIL_HELP_OFF: never */
 } rr_tuning;
 #define RR_TAIL_HELP_OFF 0xffffffffu
 

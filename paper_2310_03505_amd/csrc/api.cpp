@@ -455,7 +455,11 @@ rr_status run(rr_context* ctx, const rr_scene* sc, std::vector<DevScan>& scans,
     a.depth = 0;
     uint64_t vblocks = (L.shq_cap + kTraceBlock - 1) / kTraceBlock;
     uint32_t vgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(vblocks, 1), trace_grid);
-    const bool help = tail_help_on(ctx, L.shq_cap, vgrid);
+    // its rays are one per air-path return that can add energy, usually a
+    // small share of the bound (one per hit at depth >= 1), and each walk
+    // ends at its first blocker: a launch of few rays per lane, so helping
+    // applies whenever it is on
+    const bool help = ctx->tail_help != RR_TAIL_HELP_OFF;
     if ((rs = timed_launch(3, 0, [&] { return launch_shadow(a, vgrid, help, st); }))) return rs;
   }
   if (post) {
