@@ -65,7 +65,7 @@ TRACE_COUNTERS = {
                            grbm_gui_active_per_xcd=28479774.6 / 8, tcp_accesses=804344143.0,
                            tcp_tcc_read_req=64219566.5),
 }
-TRACE_COUNTERS_SOURCES = "9a3485f4335654633cea39f4ac107f2b9df26a333b253a0aa59a72147404ecad"
+TRACE_COUNTERS_SOURCES = "a25686804ea058ca7c81a68fa78081718f81839e270492e25fbcffb41d851115"
 COUNTER_SCALE = dict(fetch_scale=2.0, write_scale=1.0)
 TRACE_SOURCES = ("kernels.hip", "kernels.h", "rr_internal.h", "bvh.cpp", "api_internal.h", "api.cpp")
 

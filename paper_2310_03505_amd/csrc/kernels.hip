@@ -7,7 +7,8 @@
 //             BVH: persistent lanes that take a new ray as soon as theirs is
 //             done (rays claimed 64 at a time from per-segment cursors), up
 //             to kNodeSteps node steps between two scheduling decisions,
-//             leaf tests batched wave-wide;
+//             leaf tests batched wave-wide, and on levels with few rays per
+//             lane idle lanes helping the wave's unfinished rays;
 //   k_shade   (per bounce level) the interaction at each hit (Snell,
 //             Fresnel, standard BRDF return, Sec. III-A), the return binned
 //             into the polar image with a 64-bit fixed-point atomic
