@@ -241,6 +241,51 @@ def test_large_scene_sampled_primaries(R, ctx):
     masked_diagnostic(R, ctx, s, cols, ref, base_mask=mask, label="large scene")
 
 
+def test_large_scene_full_scan_sampled_records(R, ctx):
+    """The large scene scanned whole, in the launch configuration bench.py
+    times (400 x 4096 rays, B = 5, no primary mask: levels 0-1 traced with
+    tail helping, the deeper ones without), its path records compared with
+    the oracle's on 512 seeded primaries over 16 columns (the oracle traces
+    each primary on its own, so the sample stands for the scan); then the
+    same scan with tail helping off, whose records and accumulator must be
+    equal bit for bit."""
+    import torch
+    s = W.large_scene()
+    n_az, n_s = s.params["n_azimuth"], s.params["rays_per_beam"]
+    rng = np.random.default_rng(77)
+    cols = [int(c) for c in np.sort(rng.choice(n_az, size=16, replace=False))]
+    mask = np.zeros(n_az * n_s, dtype=np.uint8)
+    for c in cols:
+        mask[c * n_s + rng.choice(n_s, size=32, replace=False)] = 1
+    log("case: large scene 400 x 4096, B = 5, whole scan; oracle on 512 sampled primaries")
+    before = R.rr_get_tuning(ctx.handle)
+    sc = R.Scene(ctx, s.vertices, s.indices, s.tri_material)
+    try:
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
+        a = R.rr_radar_scan_records(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        R.rr_set_tuning(ctx.handle, **dict({k: before[k] for k in R.TUNING_KEYS}, tail_help=R.RR_TAIL_HELP_OFF))
+        b = R.rr_radar_scan_records(ctx.handle, sc.handle, s.pose, s.params, s.materials)
+        torch.cuda.synchronize()
+        assert a["stats"]["segments"] == b["stats"]["segments"]
+        assert torch.equal(a["accum"], b["accum"])
+        assert torch.equal(a["records"], b["records"])
+        rows = np.concatenate([np.arange(c * n_s, (c + 1) * n_s) for c in cols])
+        sel = mask[rows].astype(bool)
+        g_rec = a["records"].cpu().numpy()[rows][sel]
+    finally:
+        R.rr_set_tuning(ctx.handle, **{k: before[k] for k in R.TUNING_KEYS})
+        sc.release()
+    ref = oracle.scan_scene(s, columns=cols, primary_mask=mask, records=True, exempt=True,
+                            threads=min(16, len(cols)))
+    o_rec, ex = ref["records"][sel], ref["exempt"][sel]
+    diff = (g_rec != o_rec).any(axis=1)
+    log(f"large scene, whole scan: {int((~ex).sum())} sampled primaries compared, "
+        f"{int((diff & ~ex).sum())} differ, {int(ex.sum())} exempt (of those {int((diff & ex).sum())} differ), "
+        f"{a['stats']['segments']} segments, tail helping on and off equal")
+    assert not (diff & ~ex).any()
+    assert ex.mean() <= 0.08
+
+
 def test_large_scene_run_time_table_settings(R, ctx):
     """The large scene at the settings of the paper's run-time table (Table
     III: 400 azimuths, a 10 degree cone with P = 0.9, at most four
